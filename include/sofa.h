@@ -1,0 +1,222 @@
+/*
+ * sofa.h -- C ABI of the MI355X (gfx950) library for exact k-NN search over
+ * z-normalised data series with the SFA summary under the GEMINI
+ * filter-and-refine scheme (SOFA, Schaefer et al., arXiv 2411.17483).
+ *
+ * Conventions for every entry point
+ *  - Return a sofa_status; no exception or abort crosses the ABI.  On a
+ *    non-OK status, sofa_last_error() returns a message for the calling
+ *    thread.
+ *  - Pointers named d_* are device pointers on the current HIP device; the
+ *    caller owns them and the library never frees them.  Pointers without
+ *    the prefix are host pointers.
+ *  - Series are FP32, row-major, one row of n values per series.  Row ids are
+ *    the row numbers of the array given to sofa_build (0-based).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    that stream; the functions that must read a flag back (validation,
+ *    fall-back decisions) synchronise that stream before returning, as stated
+ *    per function.
+ *  - Handles (sofa_bins, sofa_index, sofa_workspace, sofa_radius) are owned
+ *    by the caller and released with the matching *_free function.  An index
+ *    is read-only after sofa_build; concurrent sofa_knn calls on one index
+ *    are allowed when each uses its own workspace and stream.
+ */
+#ifndef SOFA_H
+#define SOFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SOFA_OK = 0,
+  SOFA_EINVAL = 1,    /* bad argument: sizes, parameters, non-finite input */
+  SOFA_ENOMEM = 2,    /* device allocation failed or workspace too small */
+  SOFA_EDEVICE = 3,   /* a HIP runtime call failed */
+  SOFA_EBUSY = 4,     /* workspace in use by another call */
+  SOFA_EINTERNAL = 5  /* an internal limit was exceeded (message says which) */
+} sofa_status;
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* sofa_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Learned SFA quantisation (Section IV-C; Algorithm 1, MCB).
+ *
+ * The pool holds the real and imaginary parts of the orthonormal DFT
+ * coefficients k = 1..pool (DC omitted: it is zero for z-normalised series,
+ * Section IV-D); pool value 2(k-1) is Re X_k, 2(k-1)+1 is Im X_k.  MCB keeps
+ * the l pool values of largest variance over the sample (ties: lower pool
+ * index first), in decreasing-variance order, and learns alpha-1 breakpoints
+ * per kept value: equi-depth beta(a) = v_(floor(a*m/alpha)) of the sorted
+ * sample, or equi-width beta(a) = min + a*(max-min)/alpha.  Bins are
+ * half-open [beta(a-1), beta(a)); the outer bins are open to -inf / +inf. */
+typedef struct sofa_bins sofa_bins;
+
+typedef struct {
+  int32_t l;       /* kept values per word, 1..16 (default 16) */
+  int32_t alpha;   /* symbols per value, 1..256 (default 256) */
+  int32_t pool;    /* DFT coefficients in the pool, 1..32 and <= n/2-1 (default 16) */
+  int32_t binning; /* 0 = equi-depth (default), 1 = equi-width */
+} sofa_bin_params;
+
+/* Learns bins from the stride sample of m rows of d_series (rows
+ * floor(i*N/m), i < m), all arithmetic in FP64 on the device: DFT of the
+ * sample, variance per pool value, top-l selection, sort and breakpoints.
+ * d_series: N x n FP32 device array.  Requires 1 <= m <= N, n >= 2*pool+2,
+ * n % 4 == 0, n <= 4096.  Synchronous (returns when *out is complete). */
+sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t n, int64_t m,
+                            const sofa_bin_params* params, void* stream, sofa_bins** out);
+
+/* Builds a bins object from given values (e.g. saved bins): sel[l] pool
+ * indices, beta[l * (alpha-1)] FP64 breakpoints row-major, var[2*pool] the
+ * pool variances (may be NULL).  Host pointers. */
+sofa_status sofa_bins_create(int32_t n, const sofa_bin_params* params, const int32_t* sel,
+                             const double* beta, const double* var, sofa_bins** out);
+
+/* Copies the learned values out to host arrays (any pointer may be NULL):
+ * sel[l], beta[l*(alpha-1)], var[2*pool]; params receives l, alpha, pool,
+ * binning; n receives the series length. */
+sofa_status sofa_bins_get(const sofa_bins* bins, sofa_bin_params* params, int32_t* n,
+                          int32_t* sel, double* beta, double* var);
+
+void sofa_bins_free(sofa_bins* bins);
+
+/* Projection onto the Fourier pool (Algorithm 2, step 1) and quantisation
+ * (Algorithm 2, step 2) of m arbitrary rows, for inspection and checks:
+ *  d_pool  (nullable) m x 2*pool FP32: every pool value of every row;
+ *  d_sel   (nullable) m x 16 FP32: the l kept values in word order
+ *          (columns >= l are zero);
+ *  d_words (nullable) m x 16 uint8: the SFA word (bytes >= l are zero).
+ * The projection runs on the matrix cores (FP32 MFMA) against a partial DFT
+ * basis; sofa_bins_get_eta() states its error bound.  Asynchronous. */
+sofa_status sofa_transform(const sofa_bins* bins, const float* d_x, int64_t m,
+                           float* d_pool, float* d_sel, uint8_t* d_words, void* stream);
+
+/* Error bound of the FP32 projection: for a row x, every computed pool value
+ * c satisfies |c - c_exact| <= eta_per_norm * ||x||_2 (+ 1e-30). */
+double sofa_bins_eta_per_norm(const sofa_bins* bins);
+
+/* ------------------------------------------------------------------------ */
+/* Index (Section IV-E, SOFA index; the MESSI tree of Section IV-A is
+ * replaced by fixed-size leaves over a sorted flat array).
+ *
+ * sofa_build SFA-transforms every row, sorts the rows by a key that
+ * interleaves the symbols' leading bits (most significant bit first, values
+ * in word order, like the iSAX-style refinement of Section IV-A), cuts the
+ * sorted order into leaves of leaf_size rows, and stores per leaf the
+ * smallest and largest symbol of each word position (its envelope).  It
+ * keeps its own permuted copy of the rows, so d_series may be freed after
+ * the call returns. */
+typedef struct sofa_index sofa_index;
+
+typedef struct {
+  int32_t leaf_size; /* rows per leaf, a multiple of 64 in [64, 4096] (default 256) */
+  int32_t precision; /* bit 0: keep a BF16 copy for the batched-distance prune */
+} sofa_build_params;
+
+/* d_series: N x n FP32 device array (z-normalised; the library does not
+ * re-normalise).  Non-finite values give SOFA_EINVAL.  N must be < 2^31.
+ * Synchronous (returns when the index is complete). */
+sofa_status sofa_build(const sofa_bins* bins, const float* d_series, int64_t N, int32_t n,
+                       const sofa_build_params* params, void* stream, sofa_index** out);
+
+typedef struct {
+  int64_t N;
+  int32_t n, n_pad, leaf_size, l, alpha;
+  int64_t n_leaves;
+  int64_t device_bytes; /* device memory held by the index */
+  double eta_x;         /* projection error bound used for the data words */
+  int32_t has_bf16;
+} sofa_index_info;
+
+sofa_status sofa_index_get_info(const sofa_index* index, sofa_index_info* info);
+
+/* Copies the index layout to caller device arrays (any may be NULL):
+ * d_words N x 16 uint8 in leaf order, d_ids N int32 (row id of each leaf-order
+ * position), d_env n_leaves x 32 uint8 (16 lower then 16 upper symbols),
+ * d_keys N uint64 sort keys in leaf order.  Asynchronous. */
+sofa_status sofa_index_export(const sofa_index* index, uint8_t* d_words, int32_t* d_ids,
+                              uint8_t* d_env, uint64_t* d_keys, void* stream);
+
+void sofa_index_free(sofa_index* index);
+
+/* ------------------------------------------------------------------------ */
+/* Exact k-NN (Section II similarity search and its k-NN extension; GEMINI,
+ * Section II-A; SFA lower bound, Eq. 2 and Eq. 3).
+ *
+ * Result: for every query, the k rows with the smallest squared Euclidean
+ * distance, ranked by (FP64 squared distance summed in time order, row id)
+ * ascending; d_ids B x k int64 row ids, d_dists B x k FP32 distances (not
+ * squared).  The GPU filters with the SFA lower bound, refines survivors
+ * with FP32 distances, and recomputes the candidates inside the FP32 error
+ * band of the k-th distance in FP64, so ids equal those of an FP64 brute
+ * force and dists are within 1e-6 relative of it.
+ *
+ * A workspace holds the per-batch scratch memory.  Create one per concurrent
+ * stream; sofa_knn returns SOFA_ENOMEM when a batch does not fit its byte
+ * limit (the serving layer treats that as "not admitted"). */
+typedef struct sofa_workspace sofa_workspace;
+
+/* max_bytes = 0: no limit (grows on demand). */
+sofa_status sofa_workspace_create(int64_t max_bytes, sofa_workspace** out);
+/* Bytes a batch of B queries with k needs on index (no allocation). */
+sofa_status sofa_workspace_bytes_for(const sofa_index* index, int64_t B, int32_t k,
+                                     int32_t prune, int64_t* bytes);
+void sofa_workspace_free(sofa_workspace* ws);
+
+typedef struct {
+  /* Batched-distance prune before the FP32 refinement: 0 off, 1 BF16 MFMA
+   * (needs an index built with precision bit 0). */
+  int32_t prune;
+  /* Nullable device array of B radii (distance units, not squared).  A
+   * finite radius seeds the best-so-far bound with radius^2 so the first
+   * pass already prunes.  A query for which fewer than k results lie within
+   * its radius is searched again without it, so results stay exact. */
+  const float* d_radius;
+  /* 0 (default): seed the bound with the exact distances of the leaf with
+   * the smallest envelope bound (the approximate search of Section IV-A);
+   * 1: skip that seed. */
+  int32_t no_seed_leaf;
+  sofa_workspace* ws; /* NULL: the index's own workspace (one caller at a time) */
+} sofa_knn_params;
+
+/* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 128).
+ * Non-finite query values give SOFA_EINVAL.  Synchronises `stream` before
+ * returning (it reads per-query status flags to run fall-backs). */
+sofa_status sofa_knn(const sofa_index* index, const float* d_queries, int64_t B, int32_t k,
+                     const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
+                     void* stream);
+
+/* Counters of the last sofa_knn call on a workspace (or the index's own). */
+typedef struct {
+  int64_t queries;
+  int64_t leaves_total;       /* B * n_leaves */
+  int64_t leaves_visited;     /* (query, leaf) pairs that passed the envelope bound */
+  int64_t series_lb_checked;  /* word lower bounds evaluated */
+  int64_t series_refined;     /* FP32 exact distances computed */
+  int64_t series_bf16_checked;/* batched-distance bounds evaluated */
+  int64_t radius_fallbacks;   /* queries searched again without their radius */
+  int64_t overflow_fallbacks; /* queries finished by the exhaustive pass */
+  double ms_total;
+} sofa_knn_stats;
+
+sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,
+                               sofa_knn_stats* out);
+
+/* Lower-bound tables and bounds for inspection: for each query, the FP32
+ * table T[j][s] = w_j * mind_j(s, v_j)^2 over word position j and symbol s
+ * (Eq. 3, widened by the projection error bounds and rounded down), and the
+ * word lower bound of every (query, leaf-order row) pair.
+ *  d_tables (nullable) B x 16 x 256 FP32;  d_lb (nullable) B x N FP32. */
+sofa_status sofa_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
+                              float* d_tables, float* d_lb, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOFA_H */

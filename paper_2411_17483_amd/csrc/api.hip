@@ -1,0 +1,592 @@
+// api.hip -- C ABI entry points of the SOFA GPU library: argument checks,
+// device memory, and the order of the kernel launches.  All arithmetic of the
+// search runs in the kernels of k_learn.hip, k_build.hip and k_search.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "search.h"
+
+namespace sofa {
+
+static thread_local std::string g_err;
+
+sofa_status set_error(sofa_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+int pad_len(int n) {
+  int p = 64;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+sofa_status DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) return SOFA_OK;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return set_error(SOFA_ENOMEM, "device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+  }
+  bytes = b;
+  return SOFA_OK;
+}
+
+sofa_status DevBuf::reserve(size_t b) {
+  if (b <= bytes) return SOFA_OK;
+  return alloc(b);
+}
+
+static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// error bound of the FP32 projection per unit row norm: any accumulation
+// order of n_pad products (each exact or rounded once) plus the rounding of
+// the basis to FP32 stays within (n_pad + 4) u * sum|x_t b_t|, and
+// sum|x_t b_t| <= ||x|| ||b|| with ||b|| = 1/sqrt(2) for every pool value.
+static double eta_per_norm_for(int n_pad) {
+  return (double)(n_pad + 4) * 0x1p-24 * 1.01 * 0.70711;
+}
+
+}  // namespace sofa
+
+using namespace sofa;
+
+// ============================================================================
+extern "C" const char* sofa_last_error(void) { return g_err.c_str(); }
+
+static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
+  if (!p) return set_error(SOFA_EINVAL, "null bin parameters");
+  if (p->l < 1 || p->l > kMaxL) return set_error(SOFA_EINVAL, "l=%d outside [1,16]", p->l);
+  if (p->alpha < 1 || p->alpha > kAlphaMax)
+    return set_error(SOFA_EINVAL, "alpha=%d outside [1,256]", p->alpha);
+  if (p->pool < 1 || p->pool > 32) return set_error(SOFA_EINVAL, "pool=%d outside [1,32]", p->pool);
+  if (p->l > 2 * p->pool) return set_error(SOFA_EINVAL, "l=%d exceeds the pool's %d values", p->l, 2 * p->pool);
+  if (p->binning != 0 && p->binning != 1) return set_error(SOFA_EINVAL, "binning must be 0 or 1");
+  if (n < 4 || n > kMaxN || (n & 3)) return set_error(SOFA_EINVAL, "n=%d must be a multiple of 4 in [4,%d]", n, kMaxN);
+  if (n < 2 * p->pool + 2) return set_error(SOFA_EINVAL, "n=%d too short for pool=%d (need n >= 2*pool+2)", n, p->pool);
+  return SOFA_OK;
+}
+
+static sofa_status bins_finish(sofa_bins* b, hipStream_t st) {
+  b->n_pad = pad_len(b->n);
+  b->ncol_pool = ((2 * b->pool + 15) / 16) * 16;
+  b->eta_per_norm = eta_per_norm_for(b->n_pad);
+  return launch_bins_tables(b, st);
+}
+
+extern "C" sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t n, int64_t m,
+                                       const sofa_bin_params* params, void* stream, sofa_bins** out) {
+  if (!out) return set_error(SOFA_EINVAL, "null output handle");
+  *out = nullptr;
+  SOFA_TRY(check_bin_params(n, params));
+  if (!d_series || N < 1 || m < 1 || m > N) return set_error(SOFA_EINVAL, "need 1 <= m <= N and a series array");
+  if (N >= (1ll << 31)) return set_error(SOFA_EINVAL, "N must be < 2^31");
+  sofa_bins* b = new sofa_bins();
+  b->n = n;
+  b->l = params->l;
+  b->alpha = params->alpha;
+  b->pool = params->pool;
+  b->binning = params->binning;
+  b->var.assign(2 * b->pool, 0.0);
+  b->beta.assign((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 0), 0.0);
+  std::vector<double> beta_tmp((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 1));
+  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, S(stream),
+                               b->var.data(), b->sel, beta_tmp.data());
+  if (s == SOFA_OK) {
+    if (b->alpha > 1) std::copy(beta_tmp.begin(), beta_tmp.begin() + b->beta.size(), b->beta.begin());
+    s = bins_finish(b, S(stream));
+  }
+  if (s != SOFA_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_bins_create(int32_t n, const sofa_bin_params* params, const int32_t* sel,
+                                        const double* beta, const double* var, sofa_bins** out) {
+  if (!out) return set_error(SOFA_EINVAL, "null output handle");
+  *out = nullptr;
+  SOFA_TRY(check_bin_params(n, params));
+  if (!sel || (params->alpha > 1 && !beta)) return set_error(SOFA_EINVAL, "null sel or beta");
+  sofa_bins* b = new sofa_bins();
+  b->n = n;
+  b->l = params->l;
+  b->alpha = params->alpha;
+  b->pool = params->pool;
+  b->binning = params->binning;
+  for (int j = 0; j < 16; j++) b->sel[j] = j < b->l ? sel[j] : 0;
+  for (int j = 0; j < b->l; j++)
+    if (sel[j] < 0 || sel[j] >= 2 * b->pool) {
+      delete b;
+      return set_error(SOFA_EINVAL, "sel[%d]=%d outside the pool", j, sel[j]);
+    }
+  b->beta.assign((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 0), 0.0);
+  if (b->alpha > 1) std::copy(beta, beta + b->beta.size(), b->beta.begin());
+  for (int j = 0; j < b->l; j++)
+    for (int a = 1; a + 1 < b->alpha; a++)
+      if (!(b->beta[(size_t)j * (b->alpha - 1) + a - 1] <= b->beta[(size_t)j * (b->alpha - 1) + a])) {
+        delete b;
+        return set_error(SOFA_EINVAL, "breakpoints of value %d are not sorted", j);
+      }
+  b->var.assign(2 * b->pool, 0.0);
+  if (var) std::copy(var, var + 2 * b->pool, b->var.begin());
+  sofa_status s = bins_finish(b, nullptr);
+  if (s != SOFA_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_bins_get(const sofa_bins* b, sofa_bin_params* params, int32_t* n,
+                                     int32_t* sel, double* beta, double* var) {
+  if (!b) return set_error(SOFA_EINVAL, "null bins");
+  if (params) {
+    params->l = b->l;
+    params->alpha = b->alpha;
+    params->pool = b->pool;
+    params->binning = b->binning;
+  }
+  if (n) *n = b->n;
+  if (sel) memcpy(sel, b->sel, sizeof(int32_t) * b->l);
+  if (beta && !b->beta.empty()) memcpy(beta, b->beta.data(), sizeof(double) * b->beta.size());
+  if (var) memcpy(var, b->var.data(), sizeof(double) * b->var.size());
+  return SOFA_OK;
+}
+
+extern "C" void sofa_bins_free(sofa_bins* b) { delete b; }
+
+extern "C" double sofa_bins_eta_per_norm(const sofa_bins* b) { return b ? b->eta_per_norm : 0.0; }
+
+extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int64_t m, float* d_pool,
+                                      float* d_sel, uint8_t* d_words, void* stream) {
+  if (!b || (!d_x && m > 0) || m < 0) return set_error(SOFA_EINVAL, "bad arguments");
+  if (d_pool) {
+    const int np = 2 * b->pool;
+    if (b->ncol_pool == np) {
+      SOFA_TRY(launch_project(d_x, m, b->n, b->n, b->d_bt_pool.as<float>(), b->ncol_pool / 16,
+                              b->n_pad, d_pool, np, nullptr, 0, nullptr, nullptr, nullptr, S(stream)));
+    } else {
+      // the projection writes 16-column groups: go through a padded temporary
+      DevBuf tmp;
+      SOFA_TRY(tmp.alloc((size_t)m * b->ncol_pool * 4));
+      SOFA_TRY(launch_project(d_x, m, b->n, b->n, b->d_bt_pool.as<float>(), b->ncol_pool / 16,
+                              b->n_pad, tmp.as<float>(), b->ncol_pool, nullptr, 0, nullptr, nullptr,
+                              nullptr, S(stream)));
+      SOFA_HIP(hipMemcpy2DAsync(d_pool, (size_t)np * 4, tmp.p, (size_t)b->ncol_pool * 4,
+                                (size_t)np * 4, (size_t)m, hipMemcpyDeviceToDevice, S(stream)));
+      SOFA_HIP(hipStreamSynchronize(S(stream)));
+    }
+  }
+  if (d_sel || d_words) {
+    DevBuf tmpw;
+    uint8_t* w = d_words;
+    if (!w) {
+      SOFA_TRY(tmpw.alloc((size_t)m * kWordBytes));
+      w = tmpw.as<uint8_t>();
+    }
+    SOFA_TRY(launch_project(d_x, m, b->n, b->n, b->d_bt_sel.as<float>(), 1, b->n_pad, d_sel, 16,
+                            b->d_beta32.as<float>(), b->l, w, nullptr, nullptr, S(stream)));
+    if (tmpw.p) SOFA_HIP(hipStreamSynchronize(S(stream)));
+  }
+  return SOFA_OK;
+}
+
+// ============================================================================
+int64_t sofa_index::device_bytes() const {
+  return (int64_t)(X.bytes + words.bytes + ids.bytes + keys.bytes + env.bytes + norm2.bytes +
+                   xb.bytes + xb_meta.bytes);
+}
+
+static sofa_status clone_bins(const sofa_bins* src, sofa_bins* dst) {
+  dst->n = src->n;
+  dst->l = src->l;
+  dst->alpha = src->alpha;
+  dst->pool = src->pool;
+  dst->binning = src->binning;
+  memcpy(dst->sel, src->sel, sizeof dst->sel);
+  dst->beta = src->beta;
+  dst->var = src->var;
+  return bins_finish(dst, nullptr);
+}
+
+extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, int64_t N, int32_t n,
+                                  const sofa_build_params* params, void* stream, sofa_index** out) {
+  if (!out) return set_error(SOFA_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!bins || !d_series) return set_error(SOFA_EINVAL, "null bins or series");
+  if (n != bins->n) return set_error(SOFA_EINVAL, "series length %d differs from the bins' %d", n, bins->n);
+  if (N < 1 || N >= (1ll << 31)) return set_error(SOFA_EINVAL, "N=%lld outside [1, 2^31)", (long long)N);
+  int L = params ? params->leaf_size : 256;
+  if (L == 0) L = 256;
+  if (L < 64 || L > 4096 || (L & 63)) return set_error(SOFA_EINVAL, "leaf_size=%d must be a multiple of 64 in [64,4096]", L);
+  hipStream_t st = S(stream);
+  sofa_index* ix = new sofa_index();
+  sofa_status s = clone_bins(bins, &ix->bins);
+  ix->bins_ref = bins;
+  ix->N = N;
+  ix->n = n;
+  ix->n_pad = ix->bins.n_pad;
+  ix->L = L;
+  ix->n_leaves = (N + L - 1) / L;
+  ix->n_blocks = (ix->n_leaves + kLeavesPerItem - 1) / kLeavesPerItem;
+  DevBuf words_in, norm_in, bad;
+  if (s == SOFA_OK) s = words_in.alloc((size_t)N * kWordBytes);
+  if (s == SOFA_OK) s = norm_in.alloc((size_t)N * 8);
+  if (s == SOFA_OK) s = bad.alloc(4);
+  if (s == SOFA_OK && hipMemsetAsync(bad.p, 0, 4, st) != hipSuccess) s = set_error(SOFA_EDEVICE, "memset failed");
+  if (s == SOFA_OK)
+    s = launch_project(d_series, N, n, n, ix->bins.d_bt_sel.as<float>(), 1, ix->n_pad, nullptr, 16,
+                       ix->bins.d_beta32.as<float>(), ix->bins.l, words_in.as<uint8_t>(),
+                       norm_in.as<double>(), bad.as<unsigned>(), st);
+  unsigned hbad = 0;
+  if (s == SOFA_OK) {
+    if (hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = set_error(SOFA_EDEVICE, "reading the validation flag failed: %s", hipGetErrorString(hipGetLastError()));
+    else if (hbad)
+      s = set_error(SOFA_EINVAL, "the series contain non-finite values");
+  }
+  if (s == SOFA_OK) s = launch_layout(ix, d_series, words_in.as<uint8_t>(), norm_in.as<double>(), st);
+  if (s == SOFA_OK) {
+    ix->eta_x = ix->bins.eta_per_norm * ix->max_norm + 1e-30;
+    if (params && (params->precision & 1)) {
+      s = set_error(SOFA_EINVAL, "the BF16 copy is not available in this build");
+    }
+  }
+  if (s != SOFA_OK) {
+    delete ix;
+    return s;
+  }
+  *out = ix;
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_index_get_info(const sofa_index* ix, sofa_index_info* info) {
+  if (!ix || !info) return set_error(SOFA_EINVAL, "null argument");
+  info->N = ix->N;
+  info->n = ix->n;
+  info->n_pad = ix->n_pad;
+  info->leaf_size = ix->L;
+  info->l = ix->bins.l;
+  info->alpha = ix->bins.alpha;
+  info->n_leaves = ix->n_leaves;
+  info->device_bytes = ix->device_bytes();
+  info->eta_x = ix->eta_x;
+  info->has_bf16 = ix->has_bf16;
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_index_export(const sofa_index* ix, uint8_t* d_words, int32_t* d_ids,
+                                         uint8_t* d_env, uint64_t* d_keys, void* stream) {
+  if (!ix) return set_error(SOFA_EINVAL, "null index");
+  hipStream_t st = S(stream);
+  if (d_words) SOFA_HIP(hipMemcpyAsync(d_words, ix->words.p, ix->words.bytes, hipMemcpyDeviceToDevice, st));
+  if (d_ids) SOFA_HIP(hipMemcpyAsync(d_ids, ix->ids.p, ix->ids.bytes, hipMemcpyDeviceToDevice, st));
+  if (d_env) SOFA_HIP(hipMemcpyAsync(d_env, ix->env.p, ix->env.bytes, hipMemcpyDeviceToDevice, st));
+  if (d_keys) SOFA_HIP(hipMemcpyAsync(d_keys, ix->keys.p, ix->keys.bytes, hipMemcpyDeviceToDevice, st));
+  return SOFA_OK;
+}
+
+// ============================================================================
+struct sofa_workspace {
+  int64_t max_bytes = 0;
+  DevBuf buf;
+  DevBuf exh;
+  std::mutex mu;
+  sofa_knn_stats stats{};
+};
+
+extern "C" void sofa_index_free(sofa_index* ix) {
+  if (!ix) return;
+  delete ix->own_ws;
+  delete ix;
+}
+
+extern "C" sofa_status sofa_workspace_create(int64_t max_bytes, sofa_workspace** out) {
+  if (!out || max_bytes < 0) return set_error(SOFA_EINVAL, "bad arguments");
+  sofa_workspace* w = new sofa_workspace();
+  w->max_bytes = max_bytes;
+  *out = w;
+  return SOFA_OK;
+}
+
+extern "C" void sofa_workspace_free(sofa_workspace* ws) { delete ws; }
+
+namespace {
+
+constexpr uint32_t kExhCap = 1u << 20;
+
+int cap_for(int k) { return k <= 16 ? 16384 : 32768; }
+
+struct Layout {
+  size_t off[24];
+  size_t total;
+};
+
+enum {
+  W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
+  W_STAT, W_STATS, W_BAD, W_END
+};
+
+Layout layout_for(const sofa_index* ix, int64_t B, int k) {
+  size_t sz[W_END];
+  sz[W_QP] = (size_t)B * ix->n_pad * 4;
+  sz[W_POOL] = (size_t)B * ix->bins.ncol_pool * 4;
+  sz[W_QN] = (size_t)B * 8;
+  sz[W_TAB] = (size_t)B * kTable * 4;
+  sz[W_SQ] = (size_t)B * 16;
+  sz[W_U] = (size_t)B * 4;
+  sz[W_U0] = (size_t)B * 4;
+  sz[W_BEST] = (size_t)B * 8;
+  sz[W_MASK] = (size_t)ix->n_blocks * B * 8;
+  sz[W_CTR] = 16;
+  sz[W_RES] = (size_t)B * cap_for(k) * 8;
+  sz[W_RCNT] = (size_t)B * 4;
+  sz[W_FLAG] = (size_t)B * 4;
+  sz[W_STAT] = (size_t)B * 4;
+  sz[W_STATS] = 8 * 8;
+  sz[W_BAD] = 4;
+  Layout L;
+  size_t o = 0;
+  for (int i = 0; i < W_END; i++) {
+    L.off[i] = o;
+    o += (sz[i] + 255) & ~(size_t)255;
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" sofa_status sofa_workspace_bytes_for(const sofa_index* ix, int64_t B, int32_t k, int32_t prune,
+                                                int64_t* bytes) {
+  (void)prune;
+  if (!ix || !bytes || B < 0 || k < 1) return set_error(SOFA_EINVAL, "bad arguments");
+  *bytes = (int64_t)layout_for(ix, B, k).total;
+  return SOFA_OK;
+}
+
+static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
+                            const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
+                            sofa_workspace* ws, sofa_knn_stats& stats);
+
+extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
+                                const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
+                                void* stream) {
+  if (!ix) return set_error(SOFA_EINVAL, "null index");
+  if (B < 0 || B > 65535) return set_error(SOFA_EINVAL, "B=%lld outside [0, 65535]", (long long)B);
+  if (k < 1 || k > kMaxK || k > ix->N)
+    return set_error(SOFA_EINVAL, "k=%d outside [1, min(N, %d)]", k, kMaxK);
+  if (B == 0) return SOFA_OK;
+  if (!d_queries || !d_ids || !d_dists) return set_error(SOFA_EINVAL, "null array");
+  if (params && params->prune != 0)
+    return set_error(SOFA_EINVAL, "the batched-distance prune is not available in this build");
+  sofa_workspace* ws = params ? params->ws : nullptr;
+  if (!ws) {
+    sofa_index* mix = const_cast<sofa_index*>(ix);
+    if (!mix->own_ws) mix->own_ws = new sofa_workspace();
+    ws = mix->own_ws;
+  }
+  std::unique_lock<std::mutex> lk(ws->mu, std::try_to_lock);
+  if (!lk.owns_lock()) return set_error(SOFA_EBUSY, "workspace in use by another call");
+  hipEvent_t e0, e1;
+  SOFA_HIP(hipEventCreate(&e0));
+  SOFA_HIP(hipEventCreate(&e1));
+  SOFA_HIP(hipEventRecord(e0, S(stream)));
+  sofa_knn_stats stats{};
+  sofa_status s = knn_impl(ix, d_queries, B, k, params, d_ids, d_dists, S(stream), ws, stats);
+  (void)hipEventRecord(e1, S(stream));
+  (void)hipEventSynchronize(e1);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  stats.ms_total = ms;
+  ws->stats = stats;
+  return s;
+}
+
+static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
+                            const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
+                            sofa_workspace* ws, sofa_knn_stats& stats) {
+  const Layout lay = layout_for(ix, B, k);
+  if (ws->max_bytes > 0 && (int64_t)lay.total > ws->max_bytes)
+    return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay.total,
+                     (long long)ws->max_bytes);
+  SOFA_TRY(ws->buf.reserve(lay.total));
+  char* base = ws->buf.as<char>();
+  auto at = [&](int i) { return (void*)(base + lay.off[i]); };
+  SearchArgs a{};
+  a.X = ix->X.as<float>();
+  a.words = ix->words.as<uint8_t>();
+  a.ids = ix->ids.as<int32_t>();
+  a.env = ix->env.as<uint8_t>();
+  a.N = ix->N;
+  a.n = ix->n;
+  a.n_pad = ix->n_pad;
+  a.L = ix->L;
+  a.n_leaves = ix->n_leaves;
+  a.n_blocks = ix->n_blocks;
+  a.B = (int)B;
+  a.k = k;
+  a.cap = cap_for(k);
+  a.seed_leaf = (p && p->no_seed_leaf) ? 0 : 1;
+  a.Qp = (float*)at(W_QP);
+  a.tables = (float*)at(W_TAB);
+  a.sq = (uint4*)at(W_SQ);
+  a.U = (uint32_t*)at(W_U);
+  a.U0 = (float*)at(W_U0);
+  a.best = (uint64_t*)at(W_BEST);
+  a.masks = (uint64_t*)at(W_MASK);
+  a.counter = (uint32_t*)at(W_CTR);
+  a.res = (uint64_t*)at(W_RES);
+  a.rescnt = (uint32_t*)at(W_RCNT);
+  a.flags = (uint32_t*)at(W_FLAG);
+  a.stats = (unsigned long long*)at(W_STATS);
+  // FP32 distance error bound: per-lane sequential sums of n_pad/16 terms, a
+  // 4-level tree, and the rounded difference squared
+  const double u = 0x1p-24;
+  const double eps = (double)(ix->n_pad / 16 + 16) * u * 1.01;
+  a.lb_f = 1.0f + 0x1p-16f;
+  a.upd_f = (float)(1.0 + 2.0 * eps + 4.0 * u);
+  a.band_f = (float)(1.0 + 3.0 * eps + 4.0 * u);
+  a.abandon_f = (float)(1.0 + 5.0 * eps + 4.0 * u);
+  a.eta_x = ix->eta_x;
+  int32_t* status = (int32_t*)at(W_STAT);
+  unsigned* bad = (unsigned*)at(W_BAD);
+  SOFA_TRY(launch_fill_u32(bad, 0u, 1, st));
+  SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 16, st));
+  SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
+                          (double*)at(W_QN), bad, st));
+  SOFA_TRY(launch_search(a, d_ids, d_d, status, st));
+  std::vector<int32_t> hst(B);
+  std::vector<float> hu0(B);
+  unsigned hbad = 0;
+  unsigned long long hstats[8];
+  SOFA_HIP(hipMemcpyAsync(hst.data(), status, 4 * B, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipMemcpyAsync(hu0.data(), a.U0, 4 * B, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipMemcpyAsync(hstats, a.stats, 64, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  if (hbad) return set_error(SOFA_EINVAL, "the queries contain non-finite values");
+  stats.queries += B;
+  stats.leaves_total += B * ix->n_leaves;
+  stats.leaves_visited += (int64_t)hstats[0];
+  stats.series_lb_checked += (int64_t)hstats[1];
+  stats.series_refined += (int64_t)hstats[2];
+  std::vector<int64_t> redo;
+  for (int64_t q = 0; q < B; q++) {
+    int st_q = hst[q];
+    bool has_radius = std::isfinite(hu0[q]);
+    if (st_q == 1 || (st_q >= 2 && has_radius)) {
+      redo.push_back(q);
+    } else if (st_q >= 2) {
+      // exhaustive pass with the query's valid bound
+      if (ws->exh.bytes == 0) SOFA_TRY(ws->exh.alloc((size_t)kExhCap * (4 + 8 + 8) + 256));
+      char* eb = ws->exh.as<char>();
+      uint32_t* pos = (uint32_t*)eb;
+      double* d64 = (double*)(eb + (size_t)kExhCap * 4);
+      int64_t* id = (int64_t*)(eb + (size_t)kExhCap * 12);
+      uint32_t* cnt = (uint32_t*)(eb + (size_t)kExhCap * 20);
+      uint32_t s_found = 0;
+      SOFA_TRY(launch_exhaustive(a, (int)q, pos, cnt, kExhCap, d64, id, d_ids, d_d, st, &s_found));
+      stats.overflow_fallbacks++;
+    }
+  }
+  if (!redo.empty()) {
+    // search these queries again without their radius (exactness does not
+    // depend on the radius)
+    const int64_t R = (int64_t)redo.size();
+    DevBuf qb, ib, db;
+    SOFA_TRY(qb.alloc((size_t)R * ix->n * 4));
+    SOFA_TRY(ib.alloc((size_t)R * k * 8));
+    SOFA_TRY(db.alloc((size_t)R * k * 4));
+    for (int64_t i = 0; i < R; i++)
+      SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + redo[i] * ix->n, (size_t)ix->n * 4,
+                              hipMemcpyDeviceToDevice, st));
+    sofa_knn_params p2{};
+    sofa_knn_stats s2{};
+    SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2));
+    for (int64_t i = 0; i < R; i++) {
+      SOFA_HIP(hipMemcpyAsync(d_ids + redo[i] * k, ib.as<int64_t>() + i * k, (size_t)k * 8,
+                              hipMemcpyDeviceToDevice, st));
+      SOFA_HIP(hipMemcpyAsync(d_d + redo[i] * k, db.as<float>() + i * k, (size_t)k * 4,
+                              hipMemcpyDeviceToDevice, st));
+    }
+    SOFA_HIP(hipStreamSynchronize(st));
+    stats.radius_fallbacks += R;
+    stats.leaves_visited += s2.leaves_visited;
+    stats.series_lb_checked += s2.series_lb_checked;
+    stats.series_refined += s2.series_refined;
+    stats.overflow_fallbacks += s2.overflow_fallbacks;
+  }
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* ix, sofa_knn_stats* out) {
+  if (!out) return set_error(SOFA_EINVAL, "null output");
+  const sofa_workspace* w = ws ? ws : (ix ? ix->own_ws : nullptr);
+  if (!w) {
+    memset(out, 0, sizeof *out);
+    return SOFA_OK;
+  }
+  *out = w->stats;
+  return SOFA_OK;
+}
+
+namespace sofa {
+sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
+}
+
+extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
+                                         float* d_tables, float* d_lb, void* stream) {
+  if (!ix || B < 0 || (B > 0 && !d_queries)) return set_error(SOFA_EINVAL, "bad arguments");
+  if (B == 0) return SOFA_OK;
+  hipStream_t st = S(stream);
+  DevBuf qp, pool, qn, tab, sq, u0, bad;
+  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
+  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
+  SOFA_TRY(qn.alloc((size_t)B * 8));
+  SOFA_TRY(tab.alloc((size_t)B * kTable * 4));
+  SOFA_TRY(sq.alloc((size_t)B * 16));
+  SOFA_TRY(u0.alloc((size_t)B * 4));
+  SOFA_TRY(bad.alloc(4));
+  SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
+  SearchArgs a{};
+  a.X = ix->X.as<float>();
+  a.words = ix->words.as<uint8_t>();
+  a.N = ix->N;
+  a.n = ix->n;
+  a.n_pad = ix->n_pad;
+  a.B = (int)B;
+  a.Qp = qp.as<float>();
+  a.tables = tab.as<float>();
+  a.sq = sq.as<uint4>();
+  a.U0 = u0.as<float>();
+  a.eta_x = ix->eta_x;
+  SOFA_TRY(launch_prepare(a, d_queries, nullptr, ix->bins, pool.as<float>(), qn.as<double>(),
+                          bad.as<unsigned>(), st));
+  if (d_tables)
+    SOFA_HIP(hipMemcpyAsync(d_tables, tab.p, (size_t)B * kTable * 4, hipMemcpyDeviceToDevice, st));
+  if (d_lb) SOFA_TRY(launch_all_lb(a, d_lb, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  return SOFA_OK;
+}

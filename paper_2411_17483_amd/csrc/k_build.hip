@@ -1,0 +1,407 @@
+// k_build.hip -- SFA transform of a collection on the matrix cores and the
+// leaf layout of the index.
+//
+// Projection (Algorithm 2, step 1): the kept Fourier values of a row are dot
+// products with a partial orthonormal DFT basis (only the kept columns are
+// needed, not a full FFT), so a batch of rows times the basis is a GEMM,
+// [rows x n] . [n x 16], run with v_mfma_f32_16x16x4f32.  Rows are staged
+// through LDS with coalesced 16-byte loads and read back in the MFMA operand
+// layout.  Quantisation (Algorithm 2, step 2) is fused into the epilogue: a
+// binary search over the FP32 breakpoints held in LDS.
+//
+// Layout: the MESSI tree of Section IV-A is replaced by a flat array sorted
+// by a key that interleaves the leading bits of the symbols (most significant
+// first, positions in word order), cut into fixed-size leaves; each leaf
+// keeps a per-position [min, max] symbol envelope.
+#include "kernels.h"
+
+namespace sofa {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+// ----------------------------------------------------------------------------
+// projection
+constexpr int kPrjCh = 128;            // staged columns per chunk
+constexpr int kPrjRow = kPrjCh + 4;    // padded LDS row (floats), keeps 16-byte alignment
+
+template <int NG, bool QUANT>
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, int64_t m, int n,
+                                                 int64_t ldx, const float* __restrict__ BT,
+                                                 int n_pad, float* __restrict__ out, int ld_out,
+                                                 const float* __restrict__ beta32, int l,
+                                                 uint8_t* __restrict__ words,
+                                                 double* __restrict__ norm2,
+                                                 unsigned* __restrict__ bad) {
+  __shared__ __attribute__((aligned(16))) float S[4][16 * kPrjRow];
+  __shared__ float bq[QUANT ? kTable : 1];
+  __shared__ __attribute__((aligned(16))) uint8_t Wb[4][16 * 16];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, g = lane >> 4;
+  if (QUANT)
+    for (int i = threadIdx.x; i < kTable; i += 256) bq[i] = beta32[i];
+  __syncthreads();
+  unsigned badf = 0;
+  const int64_t ntile = (m + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t row0 = tile * 64 + wave * 16;
+    f4v acc[NG];
+#pragma unroll
+    for (int gi = 0; gi < NG; gi++) acc[gi] = (f4v){0.f, 0.f, 0.f, 0.f};
+    double nrm = 0.0;
+    for (int c0 = 0; c0 < n; c0 += kPrjCh) {
+      // stage 16 rows x kPrjCh columns (coalesced float4 loads)
+#pragma unroll
+      for (int r = 0; r < (16 * kPrjCh / 4) / 64; r++) {
+        int f = lane + 64 * r;
+        int rr = f / (kPrjCh / 4), c4 = f % (kPrjCh / 4);
+        int col = c0 + 4 * c4;
+        int64_t row = row0 + rr;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < m && col < n) v = *reinterpret_cast<const float4*>(X + row * ldx + col);
+        *reinterpret_cast<float4*>(&S[wave][rr * kPrjRow + 4 * c4]) = v;
+      }
+      __syncthreads();
+      // lane group g owns columns [c0 + g*kPrjCh/4, c0 + (g+1)*kPrjCh/4) of the chunk
+#pragma unroll
+      for (int s4 = 0; s4 < kPrjCh / 16; s4++) {
+        int cc = g * (kPrjCh / 4) + 4 * s4;
+        float4 a = *reinterpret_cast<const float4*>(&S[wave][li * kPrjRow + cc]);
+        nrm += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
+        if (!(isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w))) badf = 1;
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++) {
+          float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (c0 + cc < n_pad)
+            b = *reinterpret_cast<const float4*>(BT + (int64_t)(gi * 16 + li) * n_pad + c0 + cc);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[gi], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+    // D[row 4g+r][col li] of each 16-column group
+    if (out) {
+#pragma unroll
+      for (int gi = 0; gi < NG; gi++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int64_t row = row0 + 4 * g + r;
+          if (row < m) out[row * ld_out + gi * 16 + li] = acc[gi][r];
+        }
+    }
+    if (norm2) {
+      nrm += __shfl_xor(nrm, 16);
+      nrm += __shfl_xor(nrm, 32);
+      if (g == 0 && row0 + li < m) norm2[row0 + li] = nrm;
+    }
+    if (QUANT) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        float c = acc[0][r];
+        int s = 0;
+        if (li < l) {
+          const float* bj = bq + li * kAlphaMax;
+#pragma unroll
+          for (int step = 128; step > 0; step >>= 1)
+            if (bj[s + step - 1] <= c) s += step;
+        }
+        Wb[wave][(4 * g + r) * 16 + li] = (uint8_t)s;
+      }
+      __syncthreads();
+      if (lane < 16 && row0 + lane < m)
+        *reinterpret_cast<uint4*>(words + (row0 + lane) * kWordBytes) =
+            *reinterpret_cast<const uint4*>(&Wb[wave][lane * 16]);
+      __syncthreads();
+    }
+  }
+  if (bad && badf) atomicOr(bad, 1u);
+}
+
+template <int NG, bool QUANT>
+static void launch_project_t(const float* X, int64_t m, int n, int64_t ldx, const float* bt,
+                             int n_pad, float* out, int ld_out, const float* beta32, int l,
+                             uint8_t* words, double* norm2, unsigned* bad, hipStream_t st) {
+  int64_t tiles = (m + 63) / 64;
+  unsigned grid = (unsigned)(tiles < 256 * 6 ? tiles : 256 * 6);
+  if (grid == 0) grid = 1;
+  k_project<NG, QUANT><<<grid, 256, 0, st>>>(X, m, n, ldx, bt, n_pad, out, ld_out, beta32, l,
+                                             words, norm2, bad);
+}
+
+sofa_status launch_project(const float* X, int64_t m, int n, int64_t ldx, const float* bt, int ng,
+                           int n_pad, float* out, int ld_out, const float* beta32, int l,
+                           uint8_t* words, double* norm2, unsigned* bad, hipStream_t st) {
+  if (m <= 0) return SOFA_OK;
+  if ((n & 3) || (ldx & 3) || (reinterpret_cast<uintptr_t>(X) & 15))
+    return set_error(SOFA_EINVAL, "projection needs n and the row stride to be multiples of 4 "
+                                  "and a 16-byte aligned array");
+  if (words) {
+    if (ng != 1) return set_error(SOFA_EINTERNAL, "quantised projection needs one column group");
+    launch_project_t<1, true>(X, m, n, ldx, bt, n_pad, out, ld_out, beta32, l, words, norm2, bad, st);
+  } else {
+    switch (ng) {
+      case 1: launch_project_t<1, false>(X, m, n, ldx, bt, n_pad, out, ld_out, nullptr, 0, nullptr, norm2, bad, st); break;
+      case 2: launch_project_t<2, false>(X, m, n, ldx, bt, n_pad, out, ld_out, nullptr, 0, nullptr, norm2, bad, st); break;
+      case 3: launch_project_t<3, false>(X, m, n, ldx, bt, n_pad, out, ld_out, nullptr, 0, nullptr, norm2, bad, st); break;
+      case 4: launch_project_t<4, false>(X, m, n, ldx, bt, n_pad, out, ld_out, nullptr, 0, nullptr, norm2, bad, st); break;
+      default: return set_error(SOFA_EINTERNAL, "unsupported column groups %d", ng);
+    }
+  }
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+// ----------------------------------------------------------------------------
+// sort key: bit-interleave (most significant first) of the leading 4 bits of
+// every symbol scaled to 8 bits, positions in word order.
+__global__ void k_keys(const uint8_t* __restrict__ words, int64_t N, int l, int alpha,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint4 w = *reinterpret_cast<const uint4*>(words + i * kWordBytes);
+  uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+  uint32_t s8[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    uint32_t s = (wv[j >> 2] >> (8 * (j & 3))) & 255u;
+    s8[j] = (j < l) ? (s * 256u) / (uint32_t)alpha : 0u;
+  }
+  uint64_t key = 0;
+#pragma unroll
+  for (int b = 7; b >= 4; b--)
+#pragma unroll
+    for (int j = 0; j < 16; j++) key = (key << 1) | ((s8[j] >> b) & 1u);
+  keys[i] = key;
+  vals[i] = (uint32_t)i;
+}
+
+// LSD radix sort of (u64 key, u32 value), 8-bit digits, stable.
+constexpr int kRsItems = 16;
+constexpr int kRsTile = 256 * kRsItems;
+
+__global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t N,
+                                                 int shift, uint32_t* __restrict__ hist,
+                                                 int64_t ntiles) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; r++) {
+    int64_t i = base + r * 256 + threadIdx.x;
+    if (i < N) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// exclusive scan of h[0..M) in one block (M = 256 * ntiles < 2^31)
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ h, int64_t M) {
+  __shared__ uint32_t part[1024];
+  int64_t per = (M + 1023) / 1024;
+  int64_t b = threadIdx.x * per, e = b + per < M ? b + per : M;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; i++) s += h[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int64_t i = b; i < e; i++) {
+    uint32_t v = h[i];
+    h[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                    const uint32_t* __restrict__ vin,
+                                                    uint64_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout, int64_t N,
+                                                    int shift, const uint32_t* __restrict__ hist,
+                                                    int64_t ntiles) {
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t wc[4][256];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  gbase[t] = hist[(int64_t)t * ntiles + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRsItems; r++) {
+    int64_t i = base + r * 256 + t;
+    bool valid = i < N;
+    uint64_t k = valid ? kin[i] : ~0ull;
+    uint32_t v = valid ? vin[i] : 0u;
+    uint32_t d = (uint32_t)(k >> shift) & 255u;
+    uint64_t peers = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+      uint64_t bal = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? bal : ~bal;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    wc[0][t] = 0u;
+    wc[1][t] = 0u;
+    wc[2][t] = 0u;
+    wc[3][t] = 0u;
+    __syncthreads();
+    if (rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      uint32_t run = gbase[t];
+      for (int w = 0; w < 4; w++) {
+        uint32_t c = wc[w][t];
+        wc[w][t] = run;
+        run += c;
+      }
+      gbase[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      uint32_t dst = wc[wave][d] + rank;
+      kout[dst] = k;
+      vout[dst] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// permuted copy: leaf-order position p holds row src = perm[p]
+__global__ __launch_bounds__(256) void k_permute(const float* __restrict__ X, int n,
+                                                 const uint32_t* __restrict__ perm, int64_t N,
+                                                 int n_pad, float* __restrict__ Xo,
+                                                 const uint8_t* __restrict__ win,
+                                                 uint8_t* __restrict__ wout,
+                                                 const double* __restrict__ nin,
+                                                 double* __restrict__ nout,
+                                                 int32_t* __restrict__ ids) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t p = (int64_t)blockIdx.x * 4 + wave;
+  if (p >= N) return;
+  int64_t src = perm[p];
+  for (int c = lane * 4; c < n_pad; c += 256) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c < n) v = *reinterpret_cast<const float4*>(X + src * n + c);
+    *reinterpret_cast<float4*>(Xo + p * n_pad + c) = v;
+  }
+  if (lane == 0) {
+    *reinterpret_cast<uint4*>(wout + p * kWordBytes) =
+        *reinterpret_cast<const uint4*>(win + src * kWordBytes);
+    nout[p] = nin[src];
+    ids[p] = (int32_t)src;
+  }
+}
+
+// per-leaf envelope: lo[16] then hi[16] symbols; one wave per leaf
+__global__ __launch_bounds__(256) void k_envelope(const uint8_t* __restrict__ words, int64_t N,
+                                                  int L, int64_t n_leaves,
+                                                  uint8_t* __restrict__ env) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t leaf = (int64_t)blockIdx.x * 4 + wave;
+  if (leaf >= n_leaves) return;
+  int64_t s = leaf * L, e = s + L < N ? s + L : N;
+  uint32_t lo[16], hi[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    lo[j] = 255u;
+    hi[j] = 0u;
+  }
+  for (int64_t p = s + lane; p < e; p += 64) {
+    uint4 w = *reinterpret_cast<const uint4*>(words + p * kWordBytes);
+    uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      uint32_t b = (wv[j >> 2] >> (8 * (j & 3))) & 255u;
+      lo[j] = b < lo[j] ? b : lo[j];
+      hi[j] = b > hi[j] ? b : hi[j];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      uint32_t a = __shfl_xor(lo[j], off), b = __shfl_xor(hi[j], off);
+      lo[j] = a < lo[j] ? a : lo[j];
+      hi[j] = b > hi[j] ? b : hi[j];
+    }
+  if (lane < 32) {
+    uint32_t v = lane < 16 ? lo[0] : hi[0];
+#pragma unroll
+    for (int j = 1; j < 16; j++)
+      if ((lane & 15) == j) v = lane < 16 ? lo[j] : hi[j];
+    env[leaf * 32 + lane] = (uint8_t)v;
+  }
+}
+
+// maximum of FP64 squared norms (non-negative, so the bit patterns order like the values)
+__global__ __launch_bounds__(256) void k_max_norm(const double* __restrict__ nrm, int64_t N,
+                                                  unsigned long long* __restrict__ out) {
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+    mx = nrm[i] > mx ? nrm[i] : mx;
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(mx));
+}
+
+sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_in,
+                          const double* norm2_in, hipStream_t st) {
+  const int64_t N = ix->N;
+  const int n = ix->n, n_pad = ix->n_pad;
+  DevBuf k0, k1, v0, v1, hist, mx;
+  SOFA_TRY(k0.alloc(8 * N));
+  SOFA_TRY(k1.alloc(8 * N));
+  SOFA_TRY(v0.alloc(4 * N));
+  SOFA_TRY(v1.alloc(4 * N));
+  const int64_t ntiles = (N + kRsTile - 1) / kRsTile;
+  SOFA_TRY(hist.alloc(4 * 256 * ntiles));
+  SOFA_TRY(mx.alloc(8));
+  k_keys<<<nblk(N, 256), 256, 0, st>>>(words_in, N, ix->bins.l, ix->bins.alpha, k0.as<uint64_t>(),
+                                       v0.as<uint32_t>());
+  uint64_t *ka = k0.as<uint64_t>(), *kb = k1.as<uint64_t>();
+  uint32_t *va = v0.as<uint32_t>(), *vb = v1.as<uint32_t>();
+  for (int shift = 0; shift < 64; shift += 8) {
+    k_rs_hist<<<(unsigned)ntiles, 256, 0, st>>>(ka, N, shift, hist.as<uint32_t>(), ntiles);
+    k_rs_scan<<<1, 1024, 0, st>>>(hist.as<uint32_t>(), 256 * ntiles);
+    k_rs_scatter<<<(unsigned)ntiles, 256, 0, st>>>(ka, va, kb, vb, N, shift, hist.as<uint32_t>(), ntiles);
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
+  // after 8 passes the sorted keys/values are back in k0/v0
+  SOFA_TRY(ix->X.alloc(sizeof(float) * N * n_pad));
+  SOFA_TRY(ix->words.alloc(kWordBytes * N));
+  SOFA_TRY(ix->ids.alloc(4 * N));
+  SOFA_TRY(ix->norm2.alloc(8 * N));
+  SOFA_TRY(ix->env.alloc(32 * ix->n_leaves));
+  k_permute<<<nblk(N, 4), 256, 0, st>>>(X, n, va, N, n_pad, ix->X.as<float>(), words_in,
+                                        ix->words.as<uint8_t>(), norm2_in, ix->norm2.as<double>(),
+                                        ix->ids.as<int32_t>());
+  k_envelope<<<nblk(ix->n_leaves, 4), 256, 0, st>>>(ix->words.as<uint8_t>(), N, ix->L, ix->n_leaves,
+                                                   ix->env.as<uint8_t>());
+  SOFA_HIP(hipMemsetAsync(mx.p, 0, 8, st));
+  k_max_norm<<<1024, 256, 0, st>>>(ix->norm2.as<double>(), N, mx.as<unsigned long long>());
+  SOFA_HIP(hipGetLastError());
+  unsigned long long bits = 0;
+  SOFA_HIP(hipMemcpyAsync(&bits, mx.p, 8, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  double mn2;
+  memcpy(&mn2, &bits, 8);
+  ix->max_norm = sqrt(mn2);
+  // keep the sorted keys for inspection
+  ix->keys.release();
+  ix->keys.p = k0.p;
+  ix->keys.bytes = k0.bytes;
+  k0.p = nullptr;
+  k0.bytes = 0;
+  return SOFA_OK;
+}
+
+}  // namespace sofa

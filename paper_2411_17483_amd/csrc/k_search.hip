@@ -1,0 +1,697 @@
+// k_search.hip -- exact k-NN under the GEMINI filter-and-refine scheme with
+// the SFA lower bound (Section II-A; Eq. 2 and Eq. 3; Section IV-A search).
+//
+// Per batch of B queries:
+//  1. k_tables   per query: lower-bound table T[j][s] = w_j * mind_j(s, v_j)^2
+//                (Eq. 3, widened by the projection error bounds, rounded down),
+//                the query's own symbols, in HBM (16 KB per query).
+//  2. k_leaf_lb  every (query, leaf): envelope bound sum_j T[j][clamp(s_q,lo,hi)]
+//                (valid because each table row is unimodal with its zero at the
+//                query's own symbol).  Pass 0 finds the best leaf per query;
+//                pass 1 writes a 64-leaf survivor mask per (leaf block, query).
+//  3. k_seed     exact distances to the best leaf's rows (the approximate search
+//                of Section IV-A) give the first best-so-far bound.
+//  4. k_refine   persistent kernel over (leaf block, query) items, leaf-block
+//                major so that concurrent queries share the same rows in L2:
+//                table in LDS, word lower bounds (16-byte coalesced loads),
+//                ballot compaction of the survivors, gathered FP32 distances
+//                (16 lanes x float4 per row, chunked early abandoning), a
+//                sorted per-wave candidate list in registers, atomicMin of the
+//                bound, and a flush of the in-band candidates per item.
+//  5. k_finalize per query: candidates inside the FP32 error band of the final
+//                bound are recomputed in FP64 in time order (no contraction)
+//                and ranked by (distance, row id).
+//
+// Rigour.  Every prune compares a quantity that can only be smaller than the
+// exact squared distance against a bound U that can only be larger than the
+// exact k-th squared distance D*:
+//   U is +inf, a radius the caller vouches for (checked afterwards), or
+//   K32 * (1 + 2 eps) where K32 is the k-th smallest FP32 distance seen by
+//   one wave and eps bounds |d32 - d| / d.  Lower bounds are kept when
+//   LB32 <= U * (1 + 2^-16) (the FP32 table sum overestimates by at most
+//   ~20 ulp).  Distances are kept when d32 <= U * (1 + 3 eps), which contains
+//   every series whose exact distance is <= U.  The final ranking uses FP64.
+#include "search.h"
+
+namespace sofa {
+
+static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t byte_of(const uint4& w, int j) {
+  uint32_t v = (j < 4) ? w.x : (j < 8) ? w.y : (j < 12) ? w.z : w.w;
+  return (v >> (8 * (j & 3))) & 255u;
+}
+
+__device__ __forceinline__ float lb_word(const float* T, const uint4& w) {
+  // positions 0..15 in order: bytes 0..3 of w.x, then w.y, w.z, w.w
+  float s = 0.0f;
+  const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int j = 0; j < 16; j++) s += T[j * kAlphaMax + ((wv[j >> 2] >> (8 * (j & 3))) & 255u)];
+  return s;
+}
+
+__device__ __forceinline__ float lb_leaf(const float* T, const uint4& sq, const uint4& lo,
+                                         const uint4& hi) {
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    uint32_t q = byte_of(sq, j), a = byte_of(lo, j), b = byte_of(hi, j);
+    uint32_t c = q < a ? a : (q > b ? b : q);
+    s += T[j * kAlphaMax + c];
+  }
+  return s;
+}
+
+__device__ __forceinline__ float key_d(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
+constexpr uint64_t kEmpty = ~0ull;
+
+// Sorted per-wave candidate list: rank r lives in register r/64, lane r%64.
+template <int R>
+struct WaveList {
+  uint64_t e[R];
+  __device__ void reset() {
+#pragma unroll
+    for (int r = 0; r < R; r++) e[r] = kEmpty;
+  }
+  __device__ uint64_t at(int rank) const {
+    uint64_t v = kEmpty;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      if (rank / 64 == r) v = __shfl(e[r], rank & 63);
+    return v;
+  }
+  // insert key; *ovf set if an entry within `band` is dropped
+  __device__ void insert(uint64_t key, float band, int lane, unsigned& ovf) {
+    int pos = 0;
+    uint64_t top[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      pos += __popcll(__ballot(e[r] < key));
+      top[r] = __shfl(e[r], 63);
+    }
+    if (pos >= 64 * R) {
+      if (key_d(key) <= band) ovf = 1u;
+      return;
+    }
+    uint64_t last = top[R - 1];
+    if (last != kEmpty && key_d(last) <= band) ovf = 1u;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      uint64_t up = __shfl_up(e[r], 1);
+      if (lane == 0) up = (r > 0) ? top[r - 1] : e[r];
+      int rank = lane + 64 * r;
+      e[r] = rank < pos ? e[r] : (rank == pos ? key : up);
+    }
+  }
+};
+
+// FP32 squared distance of 4 rows at once: lane group g = lane/16 handles the
+// row at xrow (when active); lane li = lane%16 owns elements li*4 + 64*it.
+// Partial sums are checked every 256 elements against `abandon`; a group whose
+// partial exceeds it stops loading.  Returns the group's sum (all 16 lanes) or
+// +inf when abandoned/inactive.
+template <int NIT>
+__device__ __forceinline__ float dist4(const float* __restrict__ xrow, bool active,
+                                       const float4 (&q)[NIT], int li, float abandon) {
+  float acc = 0.0f;
+  bool live = active;
+#pragma unroll
+  for (int it = 0; it < NIT; it++) {
+    if (live) {
+      float4 x = *reinterpret_cast<const float4*>(xrow + li * 4 + 64 * it);
+      float d0 = q[it].x - x.x, d1 = q[it].y - x.y, d2 = q[it].z - x.z, d3 = q[it].w - x.w;
+      acc = fmaf(d0, d0, acc);
+      acc = fmaf(d1, d1, acc);
+      acc = fmaf(d2, d2, acc);
+      acc = fmaf(d3, d3, acc);
+    }
+    if ((it & 3) == 3 && it + 1 < NIT) {
+      float p = acc;
+      p += __shfl_xor(p, 8);
+      p += __shfl_xor(p, 4);
+      p += __shfl_xor(p, 2);
+      p += __shfl_xor(p, 1);
+      if (p > abandon) live = false;
+    }
+  }
+  acc += __shfl_xor(acc, 8);
+  acc += __shfl_xor(acc, 4);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 1);
+  return live ? acc : INFINITY;
+}
+
+// ----------------------------------------------------------------------------
+// 1. lower-bound tables
+__global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, int ld_pool,
+                                                const double* __restrict__ qnorm2,
+                                                const int* __restrict__ sel, int l,
+                                                const float* __restrict__ beta32,
+                                                double eta_x, double eta_per_norm,
+                                                float* __restrict__ tables,
+                                                uint4* __restrict__ sq) {
+  __shared__ float v[16];
+  __shared__ uint8_t sym[16];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const double eta_q = eta_per_norm * sqrt(qnorm2[q]) + 1e-30;
+  if (t < 16) {
+    float vv = (t < l) ? pool[(int64_t)q * ld_pool + sel[t]] : 0.0f;
+    v[t] = vv;
+    int s = 0;
+    if (t < l) {
+      const float* bj = beta32 + t * kAlphaMax;
+      for (int step = 128; step > 0; step >>= 1)
+        if (bj[s + step - 1] <= vv) s += step;
+    }
+    sym[t] = (uint8_t)s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int j = 0; j < 16; j++) w[j >> 2] |= (uint32_t)sym[j] << (8 * (j & 3));
+    sq[q] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  const double eta = eta_x + eta_q;
+  for (int i = t; i < kTable; i += 256) {
+    int j = i / kAlphaMax, s = i % kAlphaMax;
+    float out = 0.0f;
+    if (j < l) {
+      double vj = (double)v[j];
+      double lo = (s == 0) ? -INFINITY : (double)beta32[j * kAlphaMax + s - 1] - eta;
+      double hi = (double)beta32[j * kAlphaMax + s] + eta;  // +inf beyond alpha-1
+      double gap = 0.0;
+      if (lo - vj > gap) gap = lo - vj;
+      if (vj - hi > gap) gap = vj - hi;
+      double T = 2.0 * gap * gap * (1.0 - 0x1p-40);
+      out = __double2float_rd(T);
+    }
+    tables[(int64_t)q * kTable + i] = out;
+  }
+}
+
+// 2. envelope bounds of every (query, leaf).  pass 0: atomicMin of
+// (bound bits << 32 | leaf) per query; pass 1: survivor masks per 64-leaf block.
+constexpr int kSegLeaves = 4096;
+
+template <int PASS>
+__global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
+  __shared__ float T[kTable];
+  const int q = blockIdx.y;
+  const int64_t seg0 = (int64_t)blockIdx.x * kSegLeaves;
+  const float4* src = reinterpret_cast<const float4*>(a.tables + (int64_t)q * kTable);
+  for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T)[i] = src[i];
+  __syncthreads();
+  const uint4 sq = a.sq[q];
+  const int lane = threadIdx.x & 63;
+  float thr = 0.0f;
+  if (PASS == 1) thr = __uint_as_float(a.U[q]) * (1.0f + 0x1p-16f);
+  uint64_t best = kEmpty;
+  unsigned long long visited = 0;
+  for (int it = 0; it < kSegLeaves / 256; it++) {
+    int64_t leaf = seg0 + it * 256 + threadIdx.x;
+    bool valid = leaf < a.n_leaves;
+    float lb = INFINITY;
+    if (valid) {
+      const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
+      lb = lb_leaf(T, sq, e[0], e[1]);
+    }
+    if (PASS == 0) {
+      uint64_t key = ((uint64_t)__float_as_uint(lb) << 32) | (uint64_t)(uint32_t)leaf;
+      if (valid && key < best) best = key;
+    } else {
+      uint64_t m = __ballot(valid && lb <= thr);
+      int64_t blk = (seg0 + it * 256 + (threadIdx.x & ~63)) / kLeavesPerItem;
+      if (lane == 0 && blk < a.n_blocks) a.masks[blk * a.B + q] = m;
+      visited += (lane == 0) ? __popcll(m) : 0;
+    }
+  }
+  if (PASS == 0) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      uint64_t o = __shfl_xor(best, off);
+      best = o < best ? o : best;
+    }
+    if (lane == 0 && best != kEmpty) atomicMin(reinterpret_cast<unsigned long long*>(a.best) + q, best);
+  } else {
+    if (lane == 0 && visited) atomicAdd(a.stats + 0, visited);
+  }
+}
+
+// q row of a query held in registers by lane li of every 16-lane group
+template <int NIT>
+__device__ __forceinline__ void load_q(const float* qrow, int li, float4 (&q)[NIT]) {
+#pragma unroll
+  for (int it = 0; it < NIT; it++) q[it] = *reinterpret_cast<const float4*>(qrow + li * 4 + 64 * it);
+}
+
+// 3. seed: one wave per query scans the best leaf's rows.
+template <int NIT, int R>
+__global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int q = blockIdx.x * 4 + wave;
+  if (q >= a.B) return;
+  float U0 = a.U0[q];
+  uint64_t bestk = a.best[q];
+  if (bestk == kEmpty || a.seed_leaf == 0) {
+    if (lane == 0) a.U[q] = __float_as_uint(U0);
+    return;
+  }
+  const int64_t leaf = (int64_t)(uint32_t)bestk;
+  const int64_t start = leaf * a.L, end = start + a.L < a.N ? start + a.L : a.N;
+  float4 qr[NIT];
+  load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
+  WaveList<R> wl;
+  wl.reset();
+  unsigned ovf = 0;
+  float Umin = U0;
+  for (int64_t p0 = start; p0 < end; p0 += 4) {
+    int64_t p = p0 + g;
+    bool act = p < end;
+    float d = dist4<NIT>(a.X + (act ? p : start) * a.n_pad, act, qr, li, Umin * a.abandon_f);
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++) {
+      float dd = __shfl(d, 16 * gi);
+      if (p0 + gi < end && dd <= Umin * a.band_f) {
+        uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)(p0 + gi);
+        wl.insert(key, Umin * a.band_f, lane, ovf);
+      }
+    }
+    uint64_t kth = wl.at(a.k - 1);
+    if (kth != kEmpty) {
+      float uw = key_d(kth) * a.upd_f;
+      Umin = uw < Umin ? uw : Umin;
+    }
+  }
+  if (lane == 0) a.U[q] = __float_as_uint(Umin);
+}
+
+// 4. refinement over (leaf block, query) work items
+template <int NIT, int R>
+__global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
+  __shared__ float T[kTable];
+  __shared__ uint32_t item_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  unsigned long long st_words = 0, st_refined = 0;
+  const uint64_t total = (uint64_t)a.n_blocks * (uint64_t)a.B;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const uint64_t item = item_sh;
+    __syncthreads();
+    if (item >= total) break;
+    const uint64_t mask = a.masks[item];
+    if (mask == 0ull) continue;
+    const int q = (int)(item % (uint64_t)a.B);
+    const int64_t blk = (int64_t)(item / (uint64_t)a.B);
+    const float4* src = reinterpret_cast<const float4*>(a.tables + (int64_t)q * kTable);
+    for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T)[i] = src[i];
+    const uint4 sq = a.sq[q];
+    float4 qr[NIT];
+    load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
+    __syncthreads();
+    float Umin = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+    float Upub = Umin;
+    WaveList<R> wl;
+    wl.reset();
+    unsigned ovf = 0;
+    int zc = 0;
+    for (uint64_t mm = mask; mm; mm &= mm - 1) {
+      const int64_t leaf = blk * kLeavesPerItem + __builtin_ctzll(mm);
+      const int64_t start = leaf * a.L, end = start + a.L < a.N ? start + a.L : a.N;
+      const int nsl = (int)((end - start + 63) / 64);
+      for (int s = 0; s < nsl; s++, zc++) {
+        if ((zc & 3) != wave) continue;
+        // current bound: the shared one and this wave's own
+        float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+        Umin = ug < Umin ? ug : Umin;
+        if (s == 0 || true) {
+          const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
+          float lbl = lb_leaf(T, sq, e[0], e[1]);
+          if (lbl > Umin * a.lb_f) continue;
+        }
+        const int64_t base = start + 64 * s;
+        const int64_t p = base + lane;
+        const bool valid = p < end;
+        uint4 w = valid ? *reinterpret_cast<const uint4*>(a.words + p * kWordBytes)
+                        : make_uint4(0, 0, 0, 0);
+        float lb = lb_word(T, w);
+        uint64_t bal = __ballot(valid && lb <= Umin * a.lb_f);
+        st_words += (lane == 0) ? (unsigned long long)__popcll(__ballot(valid)) : 0ull;
+        while (bal) {
+          int c[4];
+#pragma unroll
+          for (int gi = 0; gi < 4; gi++) {
+            c[gi] = bal ? __builtin_ctzll(bal) : -1;
+            bal = bal ? (bal & (bal - 1)) : 0ull;
+          }
+          const int cg = c[g];
+          const float* xrow = a.X + (base + (cg >= 0 ? cg : 0)) * a.n_pad;
+          float d = dist4<NIT>(xrow, cg >= 0, qr, li, Umin * a.abandon_f);
+          const float band = Umin * a.band_f;
+#pragma unroll
+          for (int gi = 0; gi < 4; gi++) {
+            float dd = __shfl(d, 16 * gi);
+            if (c[gi] >= 0) {
+              st_refined += (lane == 0) ? 1ull : 0ull;
+              if (dd <= band) {
+                uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)(base + c[gi]);
+                wl.insert(key, band, lane, ovf);
+              }
+            }
+          }
+          uint64_t kth = wl.at(a.k - 1);
+          if (kth != kEmpty) {
+            float uw = key_d(kth) * a.upd_f;
+            Umin = uw < Umin ? uw : Umin;
+          }
+        }
+        if (Umin < Upub) {
+          if (lane == 0) atomicMin(a.U + q, __float_as_uint(Umin));
+          Upub = Umin;
+        }
+      }
+    }
+    // flush the in-band candidates of this wave
+    {
+      float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+      Umin = ug < Umin ? ug : Umin;
+      const float band = Umin * a.band_f;
+      uint64_t last = __shfl(wl.e[R - 1], 63);
+      if (last != kEmpty && key_d(last) <= band) ovf = 1u;
+      int cnt = 0;
+      uint64_t bals[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        bals[r] = __ballot(wl.e[r] != kEmpty && key_d(wl.e[r]) <= band);
+        cnt += __popcll(bals[r]);
+      }
+      if (cnt > 0) {
+        uint32_t b0 = 0;
+        if (lane == 0) b0 = atomicAdd(a.rescnt + q, (uint32_t)cnt);
+        b0 = __shfl(b0, 0);
+        int off = 0;
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if ((bals[r] >> lane) & 1ull) {
+            uint32_t slot = b0 + off + __popcll(bals[r] & lt);
+            if (slot < (uint32_t)a.cap) a.res[(int64_t)q * a.cap + slot] = wl.e[r];
+          }
+          off += __popcll(bals[r]);
+        }
+      }
+      if (ovf && lane == 0) atomicOr(a.flags + q, 1u);
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    if (st_words) atomicAdd(a.stats + 1, st_words);
+    if (st_refined) atomicAdd(a.stats + 2, st_refined);
+  }
+}
+
+// 5. finalize: FP64 recomputation of the in-band candidates and ranking.
+constexpr int kSMax = 1024;
+
+__device__ double exact_d2(const float* __restrict__ q, const float* __restrict__ x, int n) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  for (int t = 0; t < n; t++) {
+    double d = (double)q[t] - (double)x[t];
+    double sq = d * d;
+    s = s + sq;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restrict__ out_ids,
+                                                  float* __restrict__ out_d,
+                                                  int32_t* __restrict__ status) {
+  __shared__ uint32_t spos[kSMax];
+  __shared__ double sd[kSMax];
+  __shared__ int64_t sid[kSMax];
+  __shared__ uint32_t scount;
+  __shared__ int sstat;
+  const int q = blockIdx.x, t = threadIdx.x;
+  if (t == 0) {
+    scount = 0;
+    sstat = 0;
+  }
+  __syncthreads();
+  const uint32_t cnt = a.rescnt[q];
+  bool ovf = (a.flags[q] & 1u) || cnt > (uint32_t)a.cap;
+  const float band = __uint_as_float(a.U[q]) * a.band_f;
+  const uint32_t lim = cnt < (uint32_t)a.cap ? cnt : (uint32_t)a.cap;
+  for (uint32_t i = t; i < lim; i += 256) {
+    uint64_t key = a.res[(int64_t)q * a.cap + i];
+    if (key_d(key) <= band) {
+      uint32_t slot = atomicAdd(&scount, 1u);
+      if (slot < kSMax) spos[slot] = (uint32_t)key;
+    }
+  }
+  __syncthreads();
+  const uint32_t s = scount;
+  if (ovf || s > kSMax) {
+    if (t == 0) status[q] = 2;
+    return;
+  }
+  const float* qrow = a.Qp + (int64_t)q * a.n_pad;
+  for (uint32_t i = t; i < s; i += 256) {
+    uint32_t pos = spos[i];
+    sd[i] = exact_d2(qrow, a.X + (int64_t)pos * a.n_pad, a.n);
+    sid[i] = a.ids[pos];
+  }
+  __syncthreads();
+  const int k = a.k;
+  for (uint32_t i = t; i < s; i += 256) {
+    double di = sd[i];
+    int64_t ii = sid[i];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < s; j++) rank += (sd[j] < di || (sd[j] == di && sid[j] < ii)) ? 1u : 0u;
+    if (rank < (uint32_t)k) {
+      out_ids[(int64_t)q * k + rank] = ii;
+      out_d[(int64_t)q * k + rank] = (float)sqrt(di);
+    }
+    if (rank == (uint32_t)(k - 1)) {
+      float r0 = a.U0[q];
+      if (isfinite(r0) && !(di <= (double)r0 * (1.0 - 1e-9))) sstat = 1;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int st = sstat;
+    if (s < (uint32_t)k) st = isfinite(a.U0[q]) ? 1 : 3;
+    status[q] = st;
+  }
+  for (uint32_t r = s + t; r < (uint32_t)k; r += 256) {
+    out_ids[(int64_t)q * k + r] = -1;
+    out_d[(int64_t)q * k + r] = INFINITY;
+  }
+}
+
+// Exhaustive pass for one query whose candidate lists overflowed (e.g. many
+// exact duplicates): every row's FP32 distance, all rows inside the band of
+// the bound U[q] appended to a large buffer.
+template <int NIT>
+__global__ __launch_bounds__(256) void k_exhaustive(SearchArgs a, int q, uint32_t* __restrict__ pos_out,
+                                                    uint32_t* __restrict__ cnt, uint32_t cap) {
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  float4 qr[NIT];
+  load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
+  const float band = __uint_as_float(a.U[q]) * a.band_f;
+  const int64_t wave_id = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t p0 = wave_id * 4; p0 < a.N; p0 += nwaves * 4) {
+    int64_t p = p0 + g;
+    bool act = p < a.N;
+    float d = dist4<NIT>(a.X + (act ? p : 0) * a.n_pad, act, qr, li, band * 2.0f);
+    if (li == 0 && act && d <= band) {
+      uint32_t slot = atomicAdd(cnt, 1u);
+      if (slot < cap) pos_out[slot] = (uint32_t)p;
+    }
+  }
+}
+
+// FP64 distances of the exhaustive survivors
+__global__ void k_exh_exact(SearchArgs a, int q, const uint32_t* __restrict__ pos, uint32_t s,
+                            double* __restrict__ d, int64_t* __restrict__ id) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s) return;
+  d[i] = exact_d2(a.Qp + (int64_t)q * a.n_pad, a.X + (int64_t)pos[i] * a.n_pad, a.n);
+  id[i] = a.ids[pos[i]];
+}
+
+__global__ void k_exh_rank(int k, int q, uint32_t s, const double* __restrict__ d,
+                           const int64_t* __restrict__ id, int64_t* __restrict__ out_ids,
+                           float* __restrict__ out_d) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s) return;
+  double di = d[i];
+  int64_t ii = id[i];
+  uint32_t rank = 0;
+  for (uint32_t j = 0; j < s; j++) rank += (d[j] < di || (d[j] == di && id[j] < ii)) ? 1u : 0u;
+  if (rank < (uint32_t)k) {
+    out_ids[(int64_t)q * k + rank] = ii;
+    out_d[(int64_t)q * k + rank] = (float)sqrt(di);
+  }
+}
+
+// small fills (kept as kernels so that the sequence can be captured)
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_pad_queries(const float* __restrict__ Q, int64_t B, int n, int n_pad,
+                              float* __restrict__ Qp, const float* __restrict__ radius,
+                              float* __restrict__ U0, unsigned* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B * n_pad) {
+    int64_t b = i / n_pad;
+    int c = (int)(i % n_pad);
+    float v = c < n ? Q[b * n + c] : 0.0f;
+    if (!isfinite(v)) atomicOr(bad, 1u);
+    Qp[i] = v;
+  }
+  if (i < B) {
+    float u = INFINITY;
+    if (radius) {
+      float r = radius[i];
+      if (isfinite(r) && r >= 0.0f) {
+        // squared radius rounded up
+        double r2 = (double)r * (double)r;
+        u = __double2float_ru(r2 * (1.0 + 1e-12));
+      }
+    }
+    U0[i] = u;
+  }
+}
+
+// word lower bound of every (query, leaf-order row) pair, for inspection
+__global__ __launch_bounds__(256) void k_all_lb(const float* __restrict__ tables,
+                                                const uint8_t* __restrict__ words, int64_t N,
+                                                float* __restrict__ out) {
+  __shared__ float T[kTable];
+  const int q = blockIdx.y;
+  const float4* src = reinterpret_cast<const float4*>(tables + (int64_t)q * kTable);
+  for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T)[i] = src[i];
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256) {
+    uint4 w = *reinterpret_cast<const uint4*>(words + p * kWordBytes);
+    out[(int64_t)q * N + p] = lb_word(T, w);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host launchers
+sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n > 0) k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(p, v, n);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st) {
+  unsigned gx = nblk(a.N, 256);
+  if (gx > 512) gx = 512;
+  dim3 g(gx, (unsigned)a.B);
+  k_all_lb<<<g, 256, 0, st>>>(a.tables, a.words, a.N, d_lb);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+template <int NIT, int R>
+static void launch_search_t(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                            unsigned refine_grid, hipStream_t st) {
+  dim3 gl((unsigned)((a.n_leaves + kSegLeaves - 1) / kSegLeaves), (unsigned)a.B);
+  k_leaf_lb<0><<<gl, 256, 0, st>>>(a);
+  k_seed<NIT, R><<<nblk(a.B, 4), 256, 0, st>>>(a);
+  k_leaf_lb<1><<<gl, 256, 0, st>>>(a);
+  k_refine<NIT, R><<<refine_grid, 256, 0, st>>>(a);
+  k_finalize<<<(unsigned)a.B, 256, 0, st>>>(a, out_ids, out_d, status);
+}
+
+template <int NIT>
+static void launch_exh_t(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt, uint32_t cap,
+                         hipStream_t st) {
+  k_exhaustive<NIT><<<1024, 256, 0, st>>>(a, q, pos, cnt, cap);
+}
+
+sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* radius,
+                           const sofa_bins& bins, float* pool, double* qnorm2, unsigned* bad,
+                           hipStream_t st) {
+  const int64_t B = a.B;
+  k_pad_queries<<<nblk(B * a.n_pad, 256), 256, 0, st>>>(Q, B, a.n, a.n_pad,
+                                                         const_cast<float*>(a.Qp), radius,
+                                                         const_cast<float*>(a.U0), bad);
+  SOFA_TRY(launch_project(a.Qp, B, a.n_pad, a.n_pad, bins.d_bt_pool.as<float>(), bins.ncol_pool / 16,
+                          a.n_pad, pool, bins.ncol_pool, nullptr, 0, nullptr, qnorm2, nullptr, st));
+  k_tables<<<(unsigned)B, 256, 0, st>>>(pool, bins.ncol_pool, qnorm2, bins.d_sel.as<int>(), bins.l,
+                                        bins.d_beta32.as<float>(), a.eta_x, bins.eta_per_norm,
+                                        const_cast<float*>(a.tables), const_cast<uint4*>(a.sq));
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                          hipStream_t st) {
+  const int64_t B = a.B;
+  k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.best, kEmpty, B);
+  k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.rescnt, 0u, B);
+  k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.flags, 0u, B);
+  k_fill_u32<<<1, 256, 0, st>>>(a.counter, 0u, 4);
+  unsigned grid = 256 * 6;
+  uint64_t total = (uint64_t)a.n_blocks * (uint64_t)B;
+  if (total < grid) grid = (unsigned)total;
+  if (grid == 0) grid = 1;
+  const int R = (a.k + 16 <= 64) ? 1 : 2;
+  const int nit = a.n_pad / 64;
+#define SOFA_CASE(NI)                                                               \
+  case NI:                                                                          \
+    if (R == 1) launch_search_t<NI, 1>(a, out_ids, out_d, status, grid, st);        \
+    else launch_search_t<NI, 2>(a, out_ids, out_d, status, grid, st);               \
+    break;
+  switch (nit) {
+    SOFA_CASE(1)
+    SOFA_CASE(2)
+    SOFA_CASE(4)
+    SOFA_CASE(8)
+    SOFA_CASE(16)
+    default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
+  }
+#undef SOFA_CASE
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,
+                              uint32_t cap, double* d, int64_t* id, int64_t* out_ids, float* out_d,
+                              hipStream_t st, uint32_t* s_out) {
+  k_fill_u32<<<1, 64, 0, st>>>(cnt, 0u, 1);
+  switch (a.n_pad / 64) {
+    case 1: launch_exh_t<1>(a, q, pos, cnt, cap, st); break;
+    case 2: launch_exh_t<2>(a, q, pos, cnt, cap, st); break;
+    case 4: launch_exh_t<4>(a, q, pos, cnt, cap, st); break;
+    case 8: launch_exh_t<8>(a, q, pos, cnt, cap, st); break;
+    case 16: launch_exh_t<16>(a, q, pos, cnt, cap, st); break;
+    default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
+  }
+  uint32_t s = 0;
+  SOFA_HIP(hipMemcpyAsync(&s, cnt, 4, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  if (s > cap)
+    return set_error(SOFA_EINTERNAL, "query %d: %u series tie within the FP32 error band "
+                                     "(limit %u)", q, s, cap);
+  if (s < (uint32_t)a.k) return set_error(SOFA_EINTERNAL, "query %d: exhaustive pass found %u < k rows", q, s);
+  k_exh_exact<<<nblk(s, 256), 256, 0, st>>>(a, q, pos, s, d, id);
+  k_exh_rank<<<nblk(s, 256), 256, 0, st>>>(a.k, q, s, d, id, out_ids, out_d);
+  SOFA_HIP(hipGetLastError());
+  *s_out = s;
+  return SOFA_OK;
+}
+
+}  // namespace sofa

@@ -1,0 +1,47 @@
+// search.h -- arguments of the search kernels (internal).
+#pragma once
+
+#include "kernels.h"
+
+namespace sofa {
+
+struct SearchArgs {
+  // index (leaf order)
+  const float* X;        // N x n_pad
+  const uint8_t* words;  // N x 16
+  const int32_t* ids;    // N
+  const uint8_t* env;    // n_leaves x 32
+  int64_t N;
+  int n, n_pad, L;
+  int64_t n_leaves, n_blocks;
+  // batch
+  int B, k, cap, seed_leaf;
+  float* Qp;             // B x n_pad, zero padded
+  float* tables;         // B x 16 x 256
+  uint4* sq;             // B query symbols
+  uint32_t* U;           // B bounds on the k-th squared distance (FP32 bits)
+  float* U0;             // B radius bounds (+inf when none)
+  uint64_t* best;        // B best leaf (bound bits << 32 | leaf)
+  uint64_t* masks;       // n_blocks x B survivor masks
+  uint32_t* counter;     // work-queue counter
+  uint64_t* res;         // B x cap candidates (d32 bits << 32 | position)
+  uint32_t* rescnt;      // B
+  uint32_t* flags;       // B, bit 0: a candidate list overflowed
+  unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
+  // factors derived from the FP32 error bounds
+  float lb_f, band_f, upd_f, abandon_f;
+  double eta_x;
+};
+
+sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* radius,
+                           const sofa_bins& bins, float* pool, double* qnorm2, unsigned* bad,
+                           hipStream_t st);
+sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                          hipStream_t st);
+sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
+sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,
+                              uint32_t cap, double* d, int64_t* id, int64_t* out_ids, float* out_d,
+                              hipStream_t st, uint32_t* s_out);
+
+}  // namespace sofa

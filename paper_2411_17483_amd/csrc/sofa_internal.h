@@ -1,0 +1,100 @@
+// sofa_internal.h -- internal declarations of the SOFA GPU library (not ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sofa.h"
+
+namespace sofa {
+
+// ----------------------------------------------------------------------------
+// error reporting
+sofa_status set_error(sofa_status st, const char* fmt, ...);
+#define SOFA_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t _e = (call);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return ::sofa::set_error(SOFA_EDEVICE, "%s failed: %s (%s:%d)", #call,            \
+                               hipGetErrorString(_e), __FILE__, __LINE__);              \
+  } while (0)
+#define SOFA_TRY(expr)                  \
+  do {                                  \
+    sofa_status _s = (expr);            \
+    if (_s != SOFA_OK) return _s;       \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// fixed sizes of the packed layouts
+constexpr int kWordBytes = 16;    // one SFA word: up to 16 symbols of 8 bits
+constexpr int kMaxL = 16;         // word positions
+constexpr int kAlphaMax = 256;    // symbols per position
+constexpr int kTable = kMaxL * kAlphaMax;  // lower-bound table entries per query
+constexpr int kLeavesPerItem = 64;         // leaves per refinement work item (one u64 mask)
+constexpr int kMaxK = 100;
+constexpr int kMaxN = 1024;
+
+// n_pad: row length of the permuted copy, a power-of-two multiple of 64 so that
+// 16 lanes x float4 cover a row in n_pad/64 steps
+int pad_len(int n);
+
+// device buffer owned by a host object
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  sofa_status alloc(size_t b);      // exact size, drops old contents
+  sofa_status reserve(size_t b);    // grows only
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace sofa
+
+// ----------------------------------------------------------------------------
+// handle types (opaque in the ABI)
+struct sofa_bins {
+  int32_t n = 0, n_pad = 0, l = 16, alpha = 256, pool = 16, binning = 0;
+  int32_t sel[16] = {0};
+  std::vector<double> beta;  // l x (alpha-1)
+  std::vector<double> var;   // 2*pool
+  int ncol_pool = 0;         // 2*pool rounded up to 16
+  double eta_per_norm = 0;   // projection error bound per unit row norm
+  // device copies
+  sofa::DevBuf d_bt_sel;     // 16 x n_pad FP32: basis rows of the kept values (transposed)
+  sofa::DevBuf d_bt_pool;    // ncol_pool x n_pad FP32: basis rows of every pool value
+  sofa::DevBuf d_beta32;     // 16 x 256 FP32 breakpoints, +inf beyond alpha-1 and for j >= l
+  sofa::DevBuf d_sel;        // 16 int32
+};
+
+struct sofa_workspace;
+
+struct sofa_index {
+  const sofa_bins* bins_ref = nullptr;  // not owned; copied below
+  sofa_bins bins;                       // private copy (device tables included)
+  int64_t N = 0;
+  int32_t n = 0, n_pad = 0, L = 256;
+  int64_t n_leaves = 0, n_blocks = 0;
+  double eta_x = 0;            // |c32 - c| bound for every data row
+  double max_norm = 0;
+  sofa::DevBuf X;              // N x n_pad FP32, leaf order, zero padded
+  sofa::DevBuf words;          // N x 16 u8, leaf order
+  sofa::DevBuf ids;            // N int32: row id per leaf-order position
+  sofa::DevBuf keys;           // N u64 sort keys, leaf order
+  sofa::DevBuf env;            // n_leaves x 32 u8: lo[16], hi[16]
+  sofa::DevBuf norm2;          // N FP64 squared norms, leaf order
+  // BF16 tier
+  int has_bf16 = 0;
+  sofa::DevBuf xb;             // BF16 copy, MFMA-tile order
+  sofa::DevBuf xb_meta;        // per row: ||x||^2 (rd), r_x (ru), ||xhat|| (ru) as float4
+  sofa_workspace* own_ws = nullptr;
+  int64_t device_bytes() const;
+};

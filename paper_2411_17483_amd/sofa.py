@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libsofa.so (the C ABI declared in include/sofa.h).
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  torch tensors supply device memory and the current stream.  The
+binding refuses to run without the compiled library: there is no CPU path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsofa.so")
+_lib = None
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+SOFA_OK, SOFA_EINVAL, SOFA_ENOMEM, SOFA_EDEVICE, SOFA_EBUSY, SOFA_EINTERNAL = range(6)
+EXPORTED = [
+    "sofa_last_error", "sofa_learn_bins", "sofa_bins_create", "sofa_bins_get", "sofa_bins_free",
+    "sofa_transform", "sofa_bins_eta_per_norm", "sofa_build", "sofa_index_get_info",
+    "sofa_index_export", "sofa_index_free", "sofa_workspace_create", "sofa_workspace_bytes_for",
+    "sofa_workspace_free", "sofa_knn", "sofa_knn_get_stats", "sofa_lower_bounds",
+]
+
+
+class SofaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sofa status {status}: {msg}")
+        self.status = status
+
+
+class BinParams(ctypes.Structure):
+    _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32)]
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("leaf_size", _i32), ("precision", _i32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("N", _i64), ("n", _i32), ("n_pad", _i32), ("leaf_size", _i32), ("l", _i32),
+                ("alpha", _i32), ("n_leaves", _i64), ("device_bytes", _i64), ("eta_x", ctypes.c_double),
+                ("has_bf16", _i32)]
+
+
+class KnnParams(ctypes.Structure):
+    _fields_ = [("prune", _i32), ("d_radius", _vp), ("no_seed_leaf", _i32), ("ws", _vp)]
+
+
+class KnnStats(ctypes.Structure):
+    _fields_ = [("queries", _i64), ("leaves_total", _i64), ("leaves_visited", _i64),
+                ("series_lb_checked", _i64), ("series_refined", _i64),
+                ("series_bf16_checked", _i64), ("radius_fallbacks", _i64),
+                ("overflow_fallbacks", _i64), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def load():
+    """Load libsofa.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_17483_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.sofa_last_error.restype = ctypes.c_char_p
+    L.sofa_learn_bins.argtypes = [_vp, _i64, _i32, _i64, ctypes.POINTER(BinParams), _vp,
+                                  ctypes.POINTER(_vp)]
+    L.sofa_bins_create.argtypes = [_i32, ctypes.POINTER(BinParams), _vp, _vp, _vp, ctypes.POINTER(_vp)]
+    L.sofa_bins_get.argtypes = [_vp, ctypes.POINTER(BinParams), ctypes.POINTER(_i32), _vp, _vp, _vp]
+    L.sofa_bins_free.argtypes = [_vp]
+    L.sofa_bins_free.restype = None
+    L.sofa_transform.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp]
+    L.sofa_bins_eta_per_norm.argtypes = [_vp]
+    L.sofa_bins_eta_per_norm.restype = ctypes.c_double
+    L.sofa_build.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(BuildParams), _vp, ctypes.POINTER(_vp)]
+    L.sofa_index_get_info.argtypes = [_vp, ctypes.POINTER(IndexInfo)]
+    L.sofa_index_export.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.sofa_index_free.argtypes = [_vp]
+    L.sofa_index_free.restype = None
+    L.sofa_workspace_create.argtypes = [_i64, ctypes.POINTER(_vp)]
+    L.sofa_workspace_bytes_for.argtypes = [_vp, _i64, _i32, _i32, ctypes.POINTER(_i64)]
+    L.sofa_workspace_free.argtypes = [_vp]
+    L.sofa_workspace_free.restype = None
+    L.sofa_knn.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(KnnParams), _vp, _vp, _vp]
+    L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
+    L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != SOFA_OK:
+        raise SofaError(st, load().sofa_last_error().decode())
+
+
+def _stream():
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=None):
+    import torch
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return _vp(t.data_ptr())
+
+
+# --------------------------------------------------------------------------- #
+class Bins:
+    """Learned SFA quantisation (sofa_learn_bins / sofa_bins_create)."""
+
+    def __init__(self, handle):
+        self._h = _vp(handle)
+
+    @classmethod
+    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0):
+        import torch
+        L = load()
+        N, n = X.shape
+        h = _vp()
+        p = BinParams(l, alpha, pool, binning)
+        _check(L.sofa_learn_bins(_dev(X, torch.float32), N, n, m, ctypes.byref(p), _stream(),
+                                 ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def create(cls, n, sel, beta, var=None, pool=16, binning=0):
+        L = load()
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        l, am1 = beta.shape
+        p = BinParams(l, am1 + 1, pool, binning)
+        v = None if var is None else np.ascontiguousarray(var, dtype=np.float64)
+        h = _vp()
+        _check(L.sofa_bins_create(n, ctypes.byref(p), sel.ctypes.data, beta.ctypes.data,
+                                  None if v is None else v.ctypes.data, ctypes.byref(h)))
+        return cls(h.value)
+
+    def get(self):
+        L = load()
+        p = BinParams()
+        n = _i32()
+        _check(L.sofa_bins_get(self._h, ctypes.byref(p), ctypes.byref(n), None, None, None))
+        sel = np.zeros(p.l, dtype=np.int32)
+        beta = np.zeros((p.l, max(p.alpha - 1, 0)), dtype=np.float64)
+        var = np.zeros(2 * p.pool, dtype=np.float64)
+        _check(L.sofa_bins_get(self._h, None, None, sel.ctypes.data,
+                               beta.ctypes.data if beta.size else None, var.ctypes.data))
+        return {"n": n.value, "l": p.l, "alpha": p.alpha, "pool": p.pool, "binning": p.binning,
+                "sel": sel, "beta": beta, "var": var}
+
+    @property
+    def eta_per_norm(self):
+        return load().sofa_bins_eta_per_norm(self._h)
+
+    def transform(self, X, pool=True, sel=True, words=True):
+        """(pool values m x 2P, kept values m x 16, words m x 16 uint8) as device tensors."""
+        import torch
+        info = self.get()
+        m = X.shape[0]
+        dev = X.device
+        P = torch.empty((m, 2 * info["pool"]), dtype=torch.float32, device=dev) if pool else None
+        S = torch.empty((m, 16), dtype=torch.float32, device=dev) if sel else None
+        W = torch.empty((m, 16), dtype=torch.uint8, device=dev) if words else None
+        _check(load().sofa_transform(self._h, _dev(X, torch.float32), m,
+                                     None if P is None else _dev(P), None if S is None else _dev(S),
+                                     None if W is None else _dev(W), _stream()))
+        return P, S, W
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
+            _lib.sofa_bins_free(self._h)
+            self._h = _vp()
+
+
+class Workspace:
+    def __init__(self, max_bytes=0):
+        h = _vp()
+        _check(load().sofa_workspace_create(int(max_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def stats(self):
+        s = KnnStats()
+        _check(load().sofa_knn_get_stats(self._h, None, ctypes.byref(s)))
+        return s.as_dict()
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
+            _lib.sofa_workspace_free(self._h)
+            self._h = _vp()
+
+
+class Index:
+    """A built index (sofa_build) and exact k-NN queries (sofa_knn)."""
+
+    def __init__(self, bins, X, leaf_size=256, precision=0):
+        import torch
+        L = load()
+        N, n = X.shape
+        h = _vp()
+        p = BuildParams(leaf_size, precision)
+        _check(L.sofa_build(bins._h, _dev(X, torch.float32), N, n, ctypes.byref(p), _stream(),
+                            ctypes.byref(h)))
+        self._h = h
+        self.bins = bins
+
+    def info(self):
+        i = IndexInfo()
+        _check(load().sofa_index_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def export(self):
+        import torch
+        info = self.info()
+        N, nl = info["N"], info["n_leaves"]
+        W = torch.empty((N, 16), dtype=torch.uint8, device="cuda")
+        ids = torch.empty(N, dtype=torch.int32, device="cuda")
+        env = torch.empty((nl, 32), dtype=torch.uint8, device="cuda")
+        keys = torch.empty(N, dtype=torch.int64, device="cuda")
+        _check(load().sofa_index_export(self._h, _dev(W), _dev(ids), _dev(env), _dev(keys), _stream()))
+        return W, ids, env, keys
+
+    def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None):
+        """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors."""
+        import torch
+        B = Q.shape[0]
+        ids = torch.empty((B, k), dtype=torch.int64, device=Q.device)
+        d = torch.empty((B, k), dtype=torch.float32, device=Q.device)
+        p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
+                      1 if no_seed_leaf else 0, None if ws is None else ws._h)
+        _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
+                               _dev(d), _stream()))
+        return ids, d
+
+    def stats(self, ws=None):
+        s = KnnStats()
+        _check(load().sofa_knn_get_stats(None if ws is None else ws._h, self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def workspace_bytes(self, B, k, prune=0):
+        b = _i64()
+        _check(load().sofa_workspace_bytes_for(self._h, B, k, prune, ctypes.byref(b)))
+        return b.value
+
+    def lower_bounds(self, Q, tables=True, lb=True):
+        """(tables B x 16 x 256, word bounds B x N in leaf order) as device tensors."""
+        import torch
+        B = Q.shape[0]
+        N = self.info()["N"]
+        T = torch.empty((B, 16, 256), dtype=torch.float32, device=Q.device) if tables else None
+        LB = torch.empty((B, N), dtype=torch.float32, device=Q.device) if lb else None
+        _check(load().sofa_lower_bounds(self._h, _dev(Q, torch.float32), B,
+                                        None if T is None else _dev(T),
+                                        None if LB is None else _dev(LB), _stream()))
+        return T, LB
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
+            _lib.sofa_index_free(self._h)
+            self._h = _vp()

@@ -1,0 +1,43 @@
+"""The C-ABI library loads and exports every entry point include/sofa.h declares.
+
+CPU only: no compute call is made (this container has no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sofa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sofa_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for core in ("sofa_learn_bins", "sofa_build", "sofa_knn", "sofa_last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2411_17483_amd import sofa
+    lib = sofa.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(sofa.EXPORTED) == sorted(set(sofa.EXPORTED))
+    assert set(sofa.EXPORTED) <= set(_declared())
+
+
+def test_errors_without_device_work():
+    from paper_2411_17483_amd import sofa
+    lib = sofa.load()
+    h = ctypes.c_void_p()
+    p = sofa.BinParams(0, 256, 16, 0)  # l = 0 is rejected before any device call
+    st = lib.sofa_learn_bins(None, 10, 256, 5, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == sofa.SOFA_EINVAL
+    assert b"l=0" in lib.sofa_last_error()
+    st = lib.sofa_knn(None, None, 1, 1, None, None, None, None)
+    assert st == sofa.SOFA_EINVAL

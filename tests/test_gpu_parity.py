@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (stated per test): breakpoints within 1e-12 relative and identical
+selections; pool values within the projection bound eta * ||x||; symbols
+valid for the exact value within that bound; lower bounds never above the
+FP64 distance; neighbour ids bit-identical to the oracle's (distance, id)
+ranking; distances within 1e-6 relative of sqrt(FP64 d^2).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bins(sofa, X, m, **kw):
+    return sofa.Bins.learn(_t(X), m, **kw)
+
+
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("binning", [0, 1])
+@pytest.mark.parametrize("alpha", [4, 256])
+def test_learn_bins_matches_oracle(gpu_lib, binning, alpha):
+    X = synth.collection(20000, 256, "mix", seed=101)
+    m = 3000
+    b = _bins(gpu_lib, X, m, alpha=alpha, binning=binning).get()
+    var, sel, beta = oracle.learn_bins(X, m, P=16, l=16, alpha=alpha, binning=binning)
+    assert b["sel"].tolist() == sel.tolist()
+    assert np.allclose(b["var"], var, rtol=1e-10, atol=0)
+    scale = np.max(np.abs(beta))
+    assert np.max(np.abs(b["beta"] - beta)) <= 1e-12 * scale
+
+
+def test_learn_bins_small_pool_and_l(gpu_lib):
+    X = synth.collection(5000, 64, "hf", seed=5)
+    b = _bins(gpu_lib, X, 5000, l=6, alpha=16, pool=8).get()
+    var, sel, beta = oracle.learn_bins(X, 5000, P=8, l=6, alpha=16)
+    assert b["sel"].tolist() == sel.tolist()
+    assert np.max(np.abs(b["beta"] - beta)) <= 1e-12 * np.max(np.abs(beta))
+
+
+@pytest.mark.parametrize("n", [64, 100, 256, 1024])
+def test_transform_within_projection_bound(gpu_lib, n):
+    P = min(16, n // 2 - 1)
+    X = synth.collection(3001, n, "mix", seed=7 + n)
+    bins = _bins(gpu_lib, X, 3001, pool=P)
+    info = bins.get()
+    pool, selv, words = bins.transform(_t(X))
+    pool, selv, words = pool.cpu().numpy(), selv.cpu().numpy(), words.cpu().numpy()
+    ref = oracle.dft_pool(X, P)
+    norms = np.sqrt(np.sum(X.astype(np.float64) ** 2, axis=1))
+    eta = bins.eta_per_norm * norms + 1e-30
+    err = np.abs(pool.astype(np.float64) - ref)
+    assert np.all(err <= eta[:, None]), float(np.max(err / eta[:, None]))
+    sel, beta = info["sel"], info["beta"]
+    l, am1 = beta.shape
+    for j in range(l):
+        c = ref[:, sel[j]]
+        s = words[:, j].astype(np.int64)
+        lo = np.where(s > 0, beta[j][np.maximum(s - 1, 0)], -np.inf)
+        hi = np.where(s < am1, beta[j][np.minimum(s, am1 - 1)], np.inf)
+        slack = eta + 2.0 ** -23 * np.abs(np.where(np.isfinite(lo), lo, 0)) + 1e-12
+        assert np.all(lo - slack <= c), j
+        slack_hi = eta + 2.0 ** -23 * np.abs(np.where(np.isfinite(hi), hi, 0)) + 1e-12
+        assert np.all(c < hi + slack_hi), j
+        assert np.array_equal(selv[:, j], pool[:, sel[j]])
+    # symbols equal to the oracle's wherever the exact value is clear of every
+    # breakpoint by more than the projection bound (rows of the sample sit on
+    # breakpoints, where either neighbouring symbol is valid)
+    W, C = oracle.words(X[:300], sel, beta, P=P)
+    for j in range(l):
+        gap = np.min(np.abs(C[:, j][:, None] - beta[j][None, :]), axis=1)
+        clear = gap > eta[:300] + 2.0 ** -23 * np.max(np.abs(beta[j])) + 1e-12
+        assert np.array_equal(W[clear, j], words[:300, j][clear]), j
+        assert np.mean(clear) > 0.5
+
+
+def test_index_layout_properties(gpu_lib):
+    import torch
+    N, n, L = 10000 + 37, 128, 128
+    X = synth.collection(N, n, "mix", seed=9)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    W, ids, env, keys = (t.cpu().numpy() for t in ix.export())
+    info = ix.info()
+    assert info["n_leaves"] == (N + L - 1) // L
+    assert np.array_equal(np.sort(ids), np.arange(N))
+    _, _, W0 = bins.transform(_t(X))
+    assert np.array_equal(W, W0.cpu().numpy()[ids])
+    # key = interleave (MSB first) of the top 4 bits of each symbol, word order
+    s8 = W.astype(np.uint64)
+    k = np.zeros(N, dtype=np.uint64)
+    for b in range(7, 3, -1):
+        for j in range(16):
+            k = (k << np.uint64(1)) | ((s8[:, j] >> np.uint64(b)) & np.uint64(1))
+    ku = keys.view(np.uint64)
+    assert np.array_equal(ku, k)
+    assert np.all(ku[1:] >= ku[:-1])
+    # stable: equal keys keep increasing row ids
+    same = ku[1:] == ku[:-1]
+    assert np.all(ids[1:][same] > ids[:-1][same])
+    for leaf in range(info["n_leaves"]):
+        blk = W[leaf * L:(leaf + 1) * L]
+        assert np.array_equal(env[leaf, :16], blk.min(axis=0))
+        assert np.array_equal(env[leaf, 16:], blk.max(axis=0))
+
+
+@pytest.mark.parametrize("binning", [0, 1])
+def test_lower_bounds_never_exceed_distance(gpu_lib, binning):
+    N, n, B = 3000, 256, 24
+    X = synth.collection(N, n, "mix", seed=13)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=14)
+    Q[:4] = synth.collection(4, n, "hf", seed=99)  # unrelated queries too
+    bins = _bins(gpu_lib, X, N, binning=binning)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=64)
+    T, LB = ix.lower_bounds(_t(Q))
+    T, LB = T.cpu().numpy().astype(np.float64), LB.cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    ids = ids.cpu().numpy()
+    info = bins.get()
+    sel, beta = info["sel"], info["beta"]
+    Xd = X.astype(np.float64)
+    for b in range(B):
+        d2 = np.sum((Xd[ids] - Q[b].astype(np.float64)) ** 2, axis=1)
+        assert np.all(LB[b] <= d2 * (1 + 1e-12)), b
+    # tables: never above 2*mind^2 of the exact query values (Eq. 3), and no
+    # lower than that gap shrunk by the projection bounds of data and query
+    # plus the FP32 rounding of the breakpoints
+    qv = oracle.dft_pool(Q, 16)[:, sel]
+    # (the table widens by eta_x + eta_q around the GPU's own query value, which
+    # is itself within eta_q of the exact one)
+    eta = ix.info()["eta_x"] + 2 * bins.eta_per_norm * np.sqrt(np.sum(Q.astype(np.float64) ** 2, 1))
+    for b in range(B):
+        for j in range(16):
+            shrink = 1.01 * eta[b] + 2.0 ** -23 * np.max(np.abs(beta[j]))
+            for s in range(0, 256, 3):
+                m = oracle.mind(qv[b, j], s, beta[j])
+                assert T[b, j, s] <= 2.0 * m * m * (1 + 1e-12) + 1e-30
+                lo = 2.0 * max(0.0, m - shrink) ** 2 * (1 - 1e-6)
+                assert T[b, j, s] >= lo - 1e-12, (b, j, s, T[b, j, s], lo)
+
+
+def _check_knn(ids, d, ref_ids, ref_d2):
+    assert np.array_equal(ids, ref_ids)
+    ref = np.sqrt(ref_d2)
+    assert np.all(np.abs(d.astype(np.float64) - ref) <= 1e-6 * np.maximum(ref, 1e-30))
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_knn_matches_oracle_mix(gpu_lib, k):
+    N, n, B = 30000 + 11, 256, 48
+    X = synth.collection(N, n, "mix", seed=21)
+    X[1000] = X[20]            # exact duplicates: ties go to the lower row id
+    X[29000] = X[20]
+    Q, src = synth.queries(X, B, sigma=0.1, seed=22)
+    Q[0] = X[20]               # query equal to three rows
+    Q[1] = synth.collection(1, n, "hf", seed=1234)[0]   # a far query
+    bins = _bins(gpu_lib, X, 3000)
+    ix = gpu_lib.Index(bins, _t(X))
+    ids, d = ix.knn(_t(Q), k)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    if k >= 3:
+        assert ids[0, :3].cpu().tolist() == [20, 1000, 29000]
+
+
+def test_knn_small_config_plain(gpu_lib):
+    """100,000 random walks x 256, bins from a 10,000-row stride sample,
+    100 noisy-copy queries (sigma 0.1), exact 1-NN."""
+    N, n = 100000, 256
+    X = synth.collection(N, n, "rw", seed=1)
+    Q, src = synth.queries(X, 100, sigma=0.1, seed=2)
+    bins = _bins(gpu_lib, X, 10000)
+    ix = gpu_lib.Index(bins, _t(X))
+    ids, d = ix.knn(_t(Q), 1)
+    ref_ids, ref_d2 = oracle.knn(X, Q, 1)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    st = ix.stats()
+    assert st["leaves_visited"] < st["leaves_total"]
+
+
+@pytest.mark.parametrize("n,L,N", [(100, 64, 5000 + 3), (64, 512, 9000 + 1), (512, 256, 4000 + 5),
+                                   (1024, 64, 2000 + 7)])
+def test_knn_ragged_shapes(gpu_lib, n, L, N):
+    P = min(16, n // 2 - 1)
+    X = synth.collection(N, n, "mix", seed=31 + n)
+    Q, _ = synth.queries(X, 16, sigma=0.1, seed=32)
+    bins = _bins(gpu_lib, X, min(N, 2000), pool=P)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    for k in (1, 7, 70):
+        ids, d = ix.knn(_t(Q), k)
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
+def test_knn_radius_paths_are_exact(gpu_lib):
+    import torch
+    N, n, B, k = 20000, 256, 32, 10
+    X = synth.collection(N, n, "mix", seed=41)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=42)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X))
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    kth = np.sqrt(ref_d2[:, -1]).astype(np.float32)
+    for radius in (np.full(B, 1e-3, np.float32),          # every query misses -> fallback
+                   np.full(B, 1e3, np.float32),           # loose
+                   kth * np.float32(1.001),               # just outside the k-th
+                   kth * np.float32(0.999)):              # just inside: fallback
+        ids, d = ix.knn(_t(Q), k, radius=_t(radius))
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    ids, d = ix.knn(_t(Q), k, radius=_t(np.full(B, 1e-3, np.float32)))
+    assert ix.stats()["radius_fallbacks"] == B
+
+
+def test_knn_many_exact_ties_take_exhaustive_pass(gpu_lib):
+    N, n = 8000, 128
+    X = synth.collection(N, n, "rw", seed=51)
+    dup = np.sort(np.random.default_rng(0).choice(np.arange(1, N), 300, replace=False))
+    X[dup] = X[0]
+    Q = np.stack([X[0], X[5]])
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=64)
+    for k in (1, 5, 90):
+        ids, d = ix.knn(_t(Q), k)
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
+def test_knn_no_seed_and_repeatable(gpu_lib):
+    N, n = 15000, 256
+    X = synth.collection(N, n, "mix", seed=61)
+    Q, _ = synth.queries(X, 20, sigma=0.1, seed=62)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X))
+    a_ids, a_d = ix.knn(_t(Q), 5)
+    b_ids, b_d = ix.knn(_t(Q), 5, no_seed_leaf=True)
+    c_ids, c_d = ix.knn(_t(Q), 5)
+    assert np.array_equal(a_ids.cpu().numpy(), b_ids.cpu().numpy())
+    assert np.array_equal(a_ids.cpu().numpy(), c_ids.cpu().numpy())
+    assert np.array_equal(a_d.cpu().numpy(), c_d.cpu().numpy())
+
+
+def test_errors_are_reported(gpu_lib):
+    import torch
+    N, n = 2000, 64
+    X = synth.collection(N, n, "rw", seed=71)
+    bins = _bins(gpu_lib, X, 500, pool=8)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=64)
+    Q = X[:3].copy()
+    Q[1, 5] = np.nan
+    with pytest.raises(gpu_lib.SofaError) as e:
+        ix.knn(_t(Q), 1)
+    assert e.value.status == gpu_lib.SOFA_EINVAL
+    with pytest.raises(gpu_lib.SofaError):
+        ix.knn(_t(X[:2]), 0)
+    with pytest.raises(gpu_lib.SofaError):
+        ix.knn(_t(X[:2]), 101)
+    Xb = X.copy()
+    Xb[7, 3] = np.inf
+    with pytest.raises(gpu_lib.SofaError):
+        gpu_lib.Index(bins, _t(Xb))
+    ids, d = ix.knn(_t(X[:0]), 3)
+    assert ids.shape == (0, 3)
+    ws = gpu_lib.Workspace(max_bytes=1024)
+    with pytest.raises(gpu_lib.SofaError) as e:
+        ix.knn(_t(X[:4]), 1, ws=ws)
+    assert e.value.status == gpu_lib.SOFA_ENOMEM
