@@ -182,6 +182,10 @@ typedef struct {
    * 1: skip that seed. */
   int32_t no_seed_leaf;
   sofa_workspace* ws; /* NULL: the index's own workspace (one caller at a time) */
+  /* Candidate slots per query in the workspace (0 = library default).  A
+   * smaller value only costs time: when in-band candidates are dropped the
+   * query is finished by an exhaustive pass, so results stay exact. */
+  int32_t candidate_capacity;
 } sofa_knn_params;
 
 /* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 128).
@@ -201,7 +205,12 @@ typedef struct {
   int64_t series_bf16_checked;/* batched-distance bounds evaluated */
   int64_t radius_fallbacks;   /* queries searched again without their radius */
   int64_t overflow_fallbacks; /* queries finished by the exhaustive pass */
-  double ms_total;
+  double ms_total;            /* wall time of the call on its stream (HIP events) */
+  /* time of each stage of the first pass, from HIP events recorded on the
+   * call's stream around the launches: query preparation (padding, MFMA
+   * projection, tables), envelope bounds (both passes), seed, refinement,
+   * final FP64 ranking */
+  double ms_prepare, ms_leaf, ms_seed, ms_refine, ms_finalize;
 } sofa_knn_stats;
 
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,

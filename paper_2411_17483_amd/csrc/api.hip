@@ -312,6 +312,20 @@ struct sofa_workspace {
   DevBuf exh;
   std::mutex mu;
   sofa_knn_stats stats{};
+  hipEvent_t ev[7] = {};
+  bool ev_ok = false;
+  ~sofa_workspace() {
+    if (ev_ok)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  hipEvent_t* events() {
+    if (!ev_ok) {
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_ok = true;
+    }
+    return ev;
+  }
 };
 
 extern "C" void sofa_index_free(sofa_index* ix) {
@@ -334,7 +348,10 @@ namespace {
 
 constexpr uint32_t kExhCap = 1u << 20;
 
-int cap_for(int k) { return k <= 16 ? 16384 : 32768; }
+int cap_for(int k, const sofa_knn_params* p) {
+  if (p && p->candidate_capacity > 0) return p->candidate_capacity;
+  return k <= 16 ? 32768 : 65536;
+}
 
 struct Layout {
   size_t off[24];
@@ -343,10 +360,10 @@ struct Layout {
 
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
-  W_STAT, W_STATS, W_BAD, W_END
+  W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE, W_END
 };
 
-Layout layout_for(const sofa_index* ix, int64_t B, int k) {
+Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
   size_t sz[W_END];
   sz[W_QP] = (size_t)B * ix->n_pad * 4;
   sz[W_POOL] = (size_t)B * ix->bins.ncol_pool * 4;
@@ -357,13 +374,15 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k) {
   sz[W_U0] = (size_t)B * 4;
   sz[W_BEST] = (size_t)B * 8;
   sz[W_MASK] = (size_t)ix->n_blocks * B * 8;
-  sz[W_CTR] = 16;
-  sz[W_RES] = (size_t)B * cap_for(k) * 8;
+  sz[W_CTR] = 64;
+  sz[W_RES] = (size_t)B * cap_for(k, p) * 8;
   sz[W_RCNT] = (size_t)B * 4;
-  sz[W_FLAG] = (size_t)B * 4;
+  sz[W_FLAG] = (size_t)B * 8;
   sz[W_STAT] = (size_t)B * 4;
   sz[W_STATS] = 8 * 8;
   sz[W_BAD] = 4;
+  sz[W_HIST] = (size_t)B * 256 * 4;
+  sz[W_HBASE] = (size_t)B * 4;
   Layout L;
   size_t o = 0;
   for (int i = 0; i < W_END; i++) {
@@ -380,7 +399,7 @@ extern "C" sofa_status sofa_workspace_bytes_for(const sofa_index* ix, int64_t B,
                                                 int64_t* bytes) {
   (void)prune;
   if (!ix || !bytes || B < 0 || k < 1) return set_error(SOFA_EINVAL, "bad arguments");
-  *bytes = (int64_t)layout_for(ix, B, k).total;
+  *bytes = (int64_t)layout_for(ix, B, k, nullptr).total;
   return SOFA_OK;
 }
 
@@ -427,7 +446,7 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
                             sofa_workspace* ws, sofa_knn_stats& stats) {
-  const Layout lay = layout_for(ix, B, k);
+  const Layout lay = layout_for(ix, B, k, p);
   if (ws->max_bytes > 0 && (int64_t)lay.total > ws->max_bytes)
     return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay.total,
                      (long long)ws->max_bytes);
@@ -447,7 +466,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   a.n_blocks = ix->n_blocks;
   a.B = (int)B;
   a.k = k;
-  a.cap = cap_for(k);
+  a.cap = cap_for(k, p);
   a.seed_leaf = (p && p->no_seed_leaf) ? 0 : 1;
   a.Qp = (float*)at(W_QP);
   a.tables = (float*)at(W_TAB);
@@ -459,7 +478,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   a.counter = (uint32_t*)at(W_CTR);
   a.res = (uint64_t*)at(W_RES);
   a.rescnt = (uint32_t*)at(W_RCNT);
-  a.flags = (uint32_t*)at(W_FLAG);
+  a.evmin = (uint64_t*)at(W_FLAG);
+  a.hist = (uint32_t*)at(W_HIST);
+  a.hbase = (float*)at(W_HBASE);
   a.stats = (unsigned long long*)at(W_STATS);
   // FP32 distance error bound: per-lane sequential sums of n_pad/16 terms, a
   // 4-level tree, and the rounded difference squared
@@ -474,9 +495,11 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   unsigned* bad = (unsigned*)at(W_BAD);
   SOFA_TRY(launch_fill_u32(bad, 0u, 1, st));
   SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 16, st));
+  hipEvent_t* ev = ws->events();
+  if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
-  SOFA_TRY(launch_search(a, d_ids, d_d, status, st));
+  SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
   std::vector<int32_t> hst(B);
   std::vector<float> hu0(B);
   unsigned hbad = 0;
@@ -487,6 +510,15 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   SOFA_HIP(hipMemcpyAsync(hstats, a.stats, 64, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipStreamSynchronize(st));
   if (hbad) return set_error(SOFA_EINVAL, "the queries contain non-finite values");
+  if (ev && stats.queries == 0) {
+    float t[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 6; i++) (void)hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
+    stats.ms_prepare = t[0];
+    stats.ms_leaf = t[1] + t[3];
+    stats.ms_seed = t[2];
+    stats.ms_refine = t[4];
+    stats.ms_finalize = t[5];
+  }
   stats.queries += B;
   stats.leaves_total += B * ix->n_leaves;
   stats.leaves_visited += (int64_t)hstats[0];
@@ -523,6 +555,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + redo[i] * ix->n, (size_t)ix->n * 4,
                               hipMemcpyDeviceToDevice, st));
     sofa_knn_params p2{};
+    if (p) p2.candidate_capacity = p->candidate_capacity;
     sofa_knn_stats s2{};
     SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2));
     for (int64_t i = 0; i < R; i++) {

@@ -68,12 +68,17 @@ __device__ __forceinline__ float key_d(uint64_t key) { return __uint_as_float((u
 constexpr uint64_t kEmpty = ~0ull;
 
 // Sorted per-wave candidate list: rank r lives in register r/64, lane r%64.
+// `evicted` keeps the smallest key ever pushed out of the list (or refused
+// when the list was full); the search is exact as long as that key lies
+// outside the final error band, which k_finalize checks.
 template <int R>
 struct WaveList {
   uint64_t e[R];
+  uint64_t evicted;
   __device__ void reset() {
 #pragma unroll
     for (int r = 0; r < R; r++) e[r] = kEmpty;
+    evicted = kEmpty;
   }
   __device__ uint64_t at(int rank) const {
     uint64_t v = kEmpty;
@@ -82,8 +87,7 @@ struct WaveList {
       if (rank / 64 == r) v = __shfl(e[r], rank & 63);
     return v;
   }
-  // insert key; *ovf set if an entry within `band` is dropped
-  __device__ void insert(uint64_t key, float band, int lane, unsigned& ovf) {
+  __device__ void insert(uint64_t key, int lane) {
     int pos = 0;
     uint64_t top[R];
 #pragma unroll
@@ -92,11 +96,11 @@ struct WaveList {
       top[r] = __shfl(e[r], 63);
     }
     if (pos >= 64 * R) {
-      if (key_d(key) <= band) ovf = 1u;
+      evicted = key < evicted ? key : evicted;
       return;
     }
-    uint64_t last = top[R - 1];
-    if (last != kEmpty && key_d(last) <= band) ovf = 1u;
+    const uint64_t last = top[R - 1];
+    evicted = last < evicted ? last : evicted;
 #pragma unroll
     for (int r = 0; r < R; r++) {
       uint64_t up = __shfl_up(e[r], 1);
@@ -255,7 +259,10 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
   float U0 = a.U0[q];
   uint64_t bestk = a.best[q];
   if (bestk == kEmpty || a.seed_leaf == 0) {
-    if (lane == 0) a.U[q] = __float_as_uint(U0);
+    if (lane == 0) {
+      a.U[q] = __float_as_uint(U0);
+      a.hbase[q] = U0;
+    }
     return;
   }
   const int64_t leaf = (int64_t)(uint32_t)bestk;
@@ -264,7 +271,6 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
   load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
   WaveList<R> wl;
   wl.reset();
-  unsigned ovf = 0;
   float Umin = U0;
   for (int64_t p0 = start; p0 < end; p0 += 4) {
     int64_t p = p0 + g;
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
       float dd = __shfl(d, 16 * gi);
       if (p0 + gi < end && dd <= Umin * a.band_f) {
         uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)(p0 + gi);
-        wl.insert(key, Umin * a.band_f, lane, ovf);
+        wl.insert(key, lane);
       }
     }
     uint64_t kth = wl.at(a.k - 1);
@@ -284,27 +290,43 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
       Umin = uw < Umin ? uw : Umin;
     }
   }
-  if (lane == 0) a.U[q] = __float_as_uint(Umin);
+  if (lane == 0) {
+    a.U[q] = __float_as_uint(Umin);
+    a.hbase[q] = Umin;
+  }
 }
 
-// 4. refinement over (leaf block, query) work items
+// 4. refinement over (leaf sub-block, query) work items.  Workgroup w feeds
+// from queue w % 8, and queue x holds the sub-blocks of the 64-leaf blocks
+// b = x mod 8, query-minor: workgroups are dispatched to the 8 XCDs round
+// robin, so the rows that concurrent queries share stay in one XCD's L2.
+constexpr int kSub = 8;                        // leaves per work item
+constexpr int kHistBins = 256;                 // per-query histogram of flushed distances
+constexpr int kSubPerBlock = kLeavesPerItem / kSub;
+constexpr int kQueues = 8;
+
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
   __shared__ float T[kTable];
   __shared__ uint32_t item_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   unsigned long long st_words = 0, st_refined = 0;
-  const uint64_t total = (uint64_t)a.n_blocks * (uint64_t)a.B;
+  const int xq = blockIdx.x % kQueues;
+  // blocks of this queue: b = xq, xq + 8, ...
+  const int64_t nb_q = a.n_blocks > xq ? (a.n_blocks - xq + kQueues - 1) / kQueues : 0;
+  const uint64_t total = (uint64_t)nb_q * kSubPerBlock * (uint64_t)a.B;
   for (;;) {
-    if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1u);
+    if (threadIdx.x == 0) item_sh = atomicAdd(a.counter + xq, 1u);
     __syncthreads();
     const uint64_t item = item_sh;
     __syncthreads();
     if (item >= total) break;
-    const uint64_t mask = a.masks[item];
-    if (mask == 0ull) continue;
     const int q = (int)(item % (uint64_t)a.B);
-    const int64_t blk = (int64_t)(item / (uint64_t)a.B);
+    const uint64_t bs = item / (uint64_t)a.B;
+    const int64_t blk = (int64_t)(bs / kSubPerBlock) * kQueues + xq;
+    const int sub = (int)(bs % kSubPerBlock);
+    const uint32_t mask = (uint32_t)(a.masks[blk * a.B + q] >> (kSub * sub)) & ((1u << kSub) - 1u);
+    if (mask == 0u) continue;
     const float4* src = reinterpret_cast<const float4*>(a.tables + (int64_t)q * kTable);
     for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T)[i] = src[i];
     const uint4 sq = a.sq[q];
@@ -315,56 +337,67 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
     float Upub = Umin;
     WaveList<R> wl;
     wl.reset();
-    unsigned ovf = 0;
     int zc = 0;
-    for (uint64_t mm = mask; mm; mm &= mm - 1) {
-      const int64_t leaf = blk * kLeavesPerItem + __builtin_ctzll(mm);
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
+      const int64_t leaf = blk * kLeavesPerItem + kSub * sub + __builtin_ctz(mm);
       const int64_t start = leaf * a.L, end = start + a.L < a.N ? start + a.L : a.N;
       const int nsl = (int)((end - start + 63) / 64);
       for (int s = 0; s < nsl; s++, zc++) {
         if ((zc & 3) != wave) continue;
         // current bound: the shared one and this wave's own
-        float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+        const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
         Umin = ug < Umin ? ug : Umin;
-        if (s == 0 || true) {
+        {
           const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
-          float lbl = lb_leaf(T, sq, e[0], e[1]);
-          if (lbl > Umin * a.lb_f) continue;
+          if (lb_leaf(T, sq, e[0], e[1]) > Umin * a.lb_f) continue;
         }
         const int64_t base = start + 64 * s;
         const int64_t p = base + lane;
         const bool valid = p < end;
         uint4 w = valid ? *reinterpret_cast<const uint4*>(a.words + p * kWordBytes)
                         : make_uint4(0, 0, 0, 0);
-        float lb = lb_word(T, w);
+        const float lb = lb_word(T, w);
         uint64_t bal = __ballot(valid && lb <= Umin * a.lb_f);
-        st_words += (lane == 0) ? (unsigned long long)__popcll(__ballot(valid)) : 0ull;
+        st_words += (unsigned long long)__popcll(__ballot(valid));
+        st_refined += (unsigned long long)__popcll(bal);
         while (bal) {
-          int c[4];
+          // two groups of four candidates per pass: lane group g takes c0 and c1
+          int c0[4], c1[4];
 #pragma unroll
           for (int gi = 0; gi < 4; gi++) {
-            c[gi] = bal ? __builtin_ctzll(bal) : -1;
+            c0[gi] = bal ? __builtin_ctzll(bal) : -1;
             bal = bal ? (bal & (bal - 1)) : 0ull;
           }
-          const int cg = c[g];
-          const float* xrow = a.X + (base + (cg >= 0 ? cg : 0)) * a.n_pad;
-          float d = dist4<NIT>(xrow, cg >= 0, qr, li, Umin * a.abandon_f);
-          const float band = Umin * a.band_f;
 #pragma unroll
           for (int gi = 0; gi < 4; gi++) {
-            float dd = __shfl(d, 16 * gi);
-            if (c[gi] >= 0) {
-              st_refined += (lane == 0) ? 1ull : 0ull;
-              if (dd <= band) {
-                uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)(base + c[gi]);
-                wl.insert(key, band, lane, ovf);
+            c1[gi] = bal ? __builtin_ctzll(bal) : -1;
+            bal = bal ? (bal & (bal - 1)) : 0ull;
+          }
+          const int ca = c0[g], cb = c1[g];
+          const float abandon = Umin * a.abandon_f;
+          float da = dist4<NIT>(a.X + (base + (ca >= 0 ? ca : 0)) * a.n_pad, ca >= 0, qr, li, abandon);
+          float db = INFINITY;
+          if (c1[0] >= 0)
+            db = dist4<NIT>(a.X + (base + (cb >= 0 ? cb : 0)) * a.n_pad, cb >= 0, qr, li, abandon);
+          float band = Umin * a.band_f;
+          uint64_t ins = __ballot(li == 0 && ((ca >= 0 && da <= band) || (cb >= 0 && db <= band)));
+          while (ins) {
+            const int gl = __builtin_ctzll(ins);
+            ins &= ins - 1;
+            const int gg = gl >> 4;
+            const float dA = __shfl(da, gl), dB = __shfl(db, gl);
+            if (c0[gg] >= 0 && dA <= band)
+              wl.insert(((uint64_t)__float_as_uint(dA) << 32) | (uint64_t)(base + c0[gg]), lane);
+            if (c1[gg] >= 0 && dB <= band)
+              wl.insert(((uint64_t)__float_as_uint(dB) << 32) | (uint64_t)(base + c1[gg]), lane);
+            const uint64_t kth = wl.at(a.k - 1);
+            if (kth != kEmpty) {
+              const float uw = key_d(kth) * a.upd_f;
+              if (uw < Umin) {
+                Umin = uw;
+                band = Umin * a.band_f;
               }
             }
-          }
-          uint64_t kth = wl.at(a.k - 1);
-          if (kth != kEmpty) {
-            float uw = key_d(kth) * a.upd_f;
-            Umin = uw < Umin ? uw : Umin;
           }
         }
         if (Umin < Upub) {
@@ -375,11 +408,10 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
     }
     // flush the in-band candidates of this wave
     {
-      float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+      const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
       Umin = ug < Umin ? ug : Umin;
       const float band = Umin * a.band_f;
-      uint64_t last = __shfl(wl.e[R - 1], 63);
-      if (last != kEmpty && key_d(last) <= band) ovf = 1u;
+      uint64_t evk = wl.evicted;
       int cnt = 0;
       uint64_t bals[R];
 #pragma unroll
@@ -393,16 +425,68 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
         b0 = __shfl(b0, 0);
         int off = 0;
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        uint64_t lost = kEmpty;
+        const float hb = a.hbase[q];
+        const bool hist_on = hb > 0.0f && hb < INFINITY;
 #pragma unroll
         for (int r = 0; r < R; r++) {
           if ((bals[r] >> lane) & 1ull) {
-            uint32_t slot = b0 + off + __popcll(bals[r] & lt);
+            const uint32_t slot = b0 + off + __popcll(bals[r] & lt);
             if (slot < (uint32_t)a.cap) a.res[(int64_t)q * a.cap + slot] = wl.e[r];
+            else lost = wl.e[r] < lost ? wl.e[r] : lost;
+            if (hist_on) {
+              int bk = (int)(key_d(wl.e[r]) / hb * (float)kHistBins);
+              bk = bk < 0 ? 0 : (bk >= kHistBins ? kHistBins - 1 : bk);
+              atomicAdd(a.hist + (int64_t)q * kHistBins + bk, 1u);
+            }
           }
           off += __popcll(bals[r]);
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          uint64_t t = __shfl_xor(lost, o);
+          lost = t < lost ? t : lost;
+        }
+        evk = lost < evk ? lost : evk;
+        if (hist_on) {
+          // the first bucket edge below which at least k candidates lie is a
+          // bound on the k-th distance (one bucket of slack for rounding)
+          uint32_t c4[kHistBins / 64];
+          uint32_t cs = 0;
+#pragma unroll
+          for (int i = 0; i < kHistBins / 64; i++) {
+            c4[i] = __atomic_load_n(a.hist + (int64_t)q * kHistBins + lane * (kHistBins / 64) + i,
+                                    __ATOMIC_RELAXED);
+            cs += c4[i];
+          }
+          uint32_t incl = cs;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            uint32_t t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+          }
+          const uint64_t hit = __ballot(incl >= (uint32_t)a.k);
+          if (hit) {
+            const int hl = __builtin_ctzll(hit);
+            uint32_t run = __shfl(incl - cs, hl);
+            int bk = hl * (kHistBins / 64) + kHistBins / 64 - 1;
+            for (int i = 0; i < kHistBins / 64; i++) {
+              run += __shfl(c4[i], hl);
+              if (run >= (uint32_t)a.k) {
+                bk = hl * (kHistBins / 64) + i;
+                break;
+              }
+            }
+            const float uh = hb * ((float)(bk + 2) / (float)kHistBins) * a.upd_f;
+            if (uh < Umin) {
+              Umin = uh;
+              if (lane == 0) atomicMin(a.U + q, __float_as_uint(uh));
+            }
+          }
+        }
       }
-      if (ovf && lane == 0) atomicOr(a.flags + q, 1u);
+      if (lane == 0 && evk != kEmpty && key_d(evk) <= band)
+        atomicMin(reinterpret_cast<unsigned long long*>(a.evmin) + q, evk);
     }
     __syncthreads();
   }
@@ -441,8 +525,10 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
   }
   __syncthreads();
   const uint32_t cnt = a.rescnt[q];
-  bool ovf = (a.flags[q] & 1u) || cnt > (uint32_t)a.cap;
   const float band = __uint_as_float(a.U[q]) * a.band_f;
+  // exact unless a key inside the final band was ever evicted or dropped
+  const uint64_t ev = a.evmin[q];
+  bool ovf = ev != kEmpty && key_d(ev) <= band;
   const uint32_t lim = cnt < (uint32_t)a.cap ? cnt : (uint32_t)a.cap;
   for (uint32_t i = t; i < lim; i += 256) {
     uint64_t key = a.res[(int64_t)q * a.cap + i];
@@ -604,15 +690,25 @@ sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st) {
   return SOFA_OK;
 }
 
+static inline void mark(hipEvent_t* ev, int i, hipStream_t st) {
+  if (ev) (void)hipEventRecord(ev[i], st);
+}
+
 template <int NIT, int R>
 static void launch_search_t(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
-                            unsigned refine_grid, hipStream_t st) {
+                            unsigned refine_grid, hipStream_t st, hipEvent_t* ev) {
   dim3 gl((unsigned)((a.n_leaves + kSegLeaves - 1) / kSegLeaves), (unsigned)a.B);
+  mark(ev, 1, st);
   k_leaf_lb<0><<<gl, 256, 0, st>>>(a);
+  mark(ev, 2, st);
   k_seed<NIT, R><<<nblk(a.B, 4), 256, 0, st>>>(a);
+  mark(ev, 3, st);
   k_leaf_lb<1><<<gl, 256, 0, st>>>(a);
+  mark(ev, 4, st);
   k_refine<NIT, R><<<refine_grid, 256, 0, st>>>(a);
+  mark(ev, 5, st);
   k_finalize<<<(unsigned)a.B, 256, 0, st>>>(a, out_ids, out_d, status);
+  mark(ev, 6, st);
 }
 
 template <int NIT>
@@ -638,22 +734,24 @@ sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* rad
 }
 
 sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
-                          hipStream_t st) {
+                          hipStream_t st, hipEvent_t* ev) {
   const int64_t B = a.B;
   k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.best, kEmpty, B);
   k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.rescnt, 0u, B);
-  k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.flags, 0u, B);
-  k_fill_u32<<<1, 256, 0, st>>>(a.counter, 0u, 4);
+  k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.evmin, kEmpty, B);
+  k_fill_u32<<<nblk(B * kHistBins, 256), 256, 0, st>>>(a.hist, 0u, B * kHistBins);
+  k_fill_u32<<<1, 256, 0, st>>>(a.counter, 0u, kQueues);
+  // persistent grid: a multiple of the queue count so every queue has workers
   unsigned grid = 256 * 6;
-  uint64_t total = (uint64_t)a.n_blocks * (uint64_t)B;
-  if (total < grid) grid = (unsigned)total;
-  if (grid == 0) grid = 1;
+  uint64_t total = (uint64_t)a.n_blocks * kSubPerBlock * (uint64_t)B;
+  if (total < grid) grid = (unsigned)(((total + kQueues - 1) / kQueues) * kQueues);
+  if (grid == 0) grid = kQueues;
   const int R = (a.k + 16 <= 64) ? 1 : 2;
   const int nit = a.n_pad / 64;
 #define SOFA_CASE(NI)                                                               \
   case NI:                                                                          \
-    if (R == 1) launch_search_t<NI, 1>(a, out_ids, out_d, status, grid, st);        \
-    else launch_search_t<NI, 2>(a, out_ids, out_d, status, grid, st);               \
+    if (R == 1) launch_search_t<NI, 1>(a, out_ids, out_d, status, grid, st, ev);    \
+    else launch_search_t<NI, 2>(a, out_ids, out_d, status, grid, st, ev);           \
     break;
   switch (nit) {
     SOFA_CASE(1)

@@ -23,10 +23,12 @@ struct SearchArgs {
   float* U0;             // B radius bounds (+inf when none)
   uint64_t* best;        // B best leaf (bound bits << 32 | leaf)
   uint64_t* masks;       // n_blocks x B survivor masks
-  uint32_t* counter;     // work-queue counter
+  uint32_t* counter;     // work-queue counters (one per XCD queue)
   uint64_t* res;         // B x cap candidates (d32 bits << 32 | position)
   uint32_t* rescnt;      // B
-  uint32_t* flags;       // B, bit 0: a candidate list overflowed
+  uint64_t* evmin;       // B smallest candidate key evicted from a list or dropped
+  uint32_t* hist;        // B x 256 counts of flushed candidate distances
+  float* hbase;          // B histogram range [0, hbase) (the bound after the seed)
   unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
   // factors derived from the FP32 error bounds
   float lb_f, band_f, upd_f, abandon_f;
@@ -36,8 +38,9 @@ struct SearchArgs {
 sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* radius,
                            const sofa_bins& bins, float* pool, double* qnorm2, unsigned* bad,
                            hipStream_t st);
+// ev (nullable): 6 events recorded around the stages (see sofa_knn_stats)
 sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
-                          hipStream_t st);
+                          hipStream_t st, hipEvent_t* ev);
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,

@@ -47,14 +47,18 @@ class IndexInfo(ctypes.Structure):
 
 
 class KnnParams(ctypes.Structure):
-    _fields_ = [("prune", _i32), ("d_radius", _vp), ("no_seed_leaf", _i32), ("ws", _vp)]
+    _fields_ = [("prune", _i32), ("d_radius", _vp), ("no_seed_leaf", _i32), ("ws", _vp),
+                ("candidate_capacity", _i32)]
 
 
 class KnnStats(ctypes.Structure):
     _fields_ = [("queries", _i64), ("leaves_total", _i64), ("leaves_visited", _i64),
                 ("series_lb_checked", _i64), ("series_refined", _i64),
                 ("series_bf16_checked", _i64), ("radius_fallbacks", _i64),
-                ("overflow_fallbacks", _i64), ("ms_total", ctypes.c_double)]
+                ("overflow_fallbacks", _i64), ("ms_total", ctypes.c_double),
+                ("ms_prepare", ctypes.c_double), ("ms_leaf", ctypes.c_double),
+                ("ms_seed", ctypes.c_double), ("ms_refine", ctypes.c_double),
+                ("ms_finalize", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -229,14 +233,15 @@ class Index:
         _check(load().sofa_index_export(self._h, _dev(W), _dev(ids), _dev(env), _dev(keys), _stream()))
         return W, ids, env, keys
 
-    def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None):
+    def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0):
         """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors."""
         import torch
         B = Q.shape[0]
         ids = torch.empty((B, k), dtype=torch.int64, device=Q.device)
         d = torch.empty((B, k), dtype=torch.float32, device=Q.device)
         p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
-                      1 if no_seed_leaf else 0, None if ws is None else ws._h)
+                      1 if no_seed_leaf else 0, None if ws is None else ws._h,
+                      int(candidate_capacity))
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
         return ids, d

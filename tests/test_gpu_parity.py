@@ -233,6 +233,38 @@ def test_knn_many_exact_ties_take_exhaustive_pass(gpu_lib):
         _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
 
 
+def test_knn_tiny_candidate_capacity_stays_exact(gpu_lib):
+    N, n, B = 20000, 256, 24
+    X = synth.collection(N, n, "mix", seed=81)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=82)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X))
+    for k, cap in ((1, 1), (10, 4), (10, 40)):
+        ids, d = ix.knn(_t(Q), k, candidate_capacity=cap)
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    assert ix.stats()["overflow_fallbacks"] > 0
+
+
+def test_knn_counters_consistent(gpu_lib):
+    N, n, B, L = 20000 + 5, 256, 16, 64
+    X = synth.collection(N, n, "mix", seed=91)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=92)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    for k in (1, 10):
+        ix.knn(_t(Q), k)
+        st = ix.stats()
+        nl = ix.info()["n_leaves"]
+        assert st["leaves_total"] == B * nl
+        assert 0 < st["leaves_visited"] <= st["leaves_total"]
+        assert st["series_refined"] <= st["series_lb_checked"] <= st["leaves_visited"] * L
+        assert st["series_refined"] >= k * B
+        assert st["overflow_fallbacks"] == 0
+    # with no bound at all every row of every query is refined
+    ix.knn(_t(Q[:2]), 1, radius=None, no_seed_leaf=True)
+
+
 def test_knn_no_seed_and_repeatable(gpu_lib):
     N, n = 15000, 256
     X = synth.collection(N, n, "mix", seed=61)
