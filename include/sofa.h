@@ -116,6 +116,10 @@ typedef struct sofa_index sofa_index;
 typedef struct {
   int32_t leaf_size; /* rows per leaf, a multiple of 64 in [64, 4096] (default 256) */
   int32_t precision; /* bit 0: keep a BF16 copy for the batched-distance prune */
+  /* sort key: 0 (default) spends 8/8/8/8, 4/4/4/4, 2 x 8 key bits on word
+   * positions 0-3, 4-7, 8-15 (positions are in decreasing-variance order),
+   * interleaved most significant first; 1 spends 4 bits on every position */
+  int32_t key_scheme;
 } sofa_build_params;
 
 /* d_series: N x n FP32 device array (z-normalised; the library does not
@@ -223,6 +227,15 @@ sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index
  *  d_tables (nullable) B x 16 x 256 FP32;  d_lb (nullable) B x N FP32. */
 sofa_status sofa_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
                               float* d_tables, float* d_lb, void* stream);
+
+/* Batched-distance lower bounds for inspection (index built with the BF16
+ * copy): for every (query, leaf-order row) pair the bound
+ *   |q|^2 + |x|^2 - 2 (P + g|qh||xh| + |q| r_x + r_q |xh|)
+ * that the BF16 prune compares with the k-th-distance bound, computed by the
+ * same MFMA kernel the search uses (P: FP32 accumulation of the BF16
+ * products, qh/xh the BF16 copies, r = |x - xh|).  d_lb: B x N FP32. */
+sofa_status sofa_bf16_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
+                                   float* d_lb, void* stream);
 
 #ifdef __cplusplus
 }

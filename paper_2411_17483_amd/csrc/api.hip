@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "search.h"
+#include "bf16.h"
 
 namespace sofa {
 
@@ -212,7 +212,7 @@ extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int6
 // ============================================================================
 int64_t sofa_index::device_bytes() const {
   return (int64_t)(X.bytes + words.bytes + ids.bytes + keys.bytes + env.bytes + norm2.bytes +
-                   xb.bytes + xb_meta.bytes);
+                   xb.bytes + xb_meta.bytes + xb_leafmeta.bytes);
 }
 
 static sofa_status clone_bins(const sofa_bins* src, sofa_bins* dst) {
@@ -245,6 +245,11 @@ extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, 
   ix->n = n;
   ix->n_pad = ix->bins.n_pad;
   ix->L = L;
+  ix->key_scheme = params ? params->key_scheme : 0;
+  if (ix->key_scheme != 0 && ix->key_scheme != 1) {
+    delete ix;
+    return set_error(SOFA_EINVAL, "key_scheme must be 0 or 1");
+  }
   ix->n_leaves = (N + L - 1) / L;
   ix->n_blocks = (ix->n_leaves + kLeavesPerItem - 1) / kLeavesPerItem;
   DevBuf words_in, norm_in, bad;
@@ -268,7 +273,23 @@ extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, 
   if (s == SOFA_OK) {
     ix->eta_x = ix->bins.eta_per_norm * ix->max_norm + 1e-30;
     if (params && (params->precision & 1)) {
-      s = set_error(SOFA_EINVAL, "the BF16 copy is not available in this build");
+      if (ix->n_pad > 256)
+        s = set_error(SOFA_EINVAL, "the BF16 copy supports n <= 256 (padded length %d)", ix->n_pad);
+      else if (ix->L % 256)
+        s = set_error(SOFA_EINVAL, "the BF16 copy needs leaf_size to be a multiple of 256");
+      else {
+        const int64_t nrb = ((N + 255) / 256) * 8;
+        const int KS = ix->n_pad / 16;
+        if (s == SOFA_OK) s = ix->xb.alloc((size_t)nrb * KS * 64 * 16);
+        if (s == SOFA_OK) s = ix->xb_meta.alloc((size_t)N * 16);
+        if (s == SOFA_OK) s = ix->xb_leafmeta.alloc((size_t)ix->n_leaves * 16);
+        if (s == SOFA_OK)
+          s = launch_bf16_build(ix->X.as<float>(), N, ix->n_pad, ix->L, ix->n_leaves, ix->xb.as<uint4>(),
+                                ix->xb_meta.as<float4>(), ix->xb_leafmeta.as<float4>(), st);
+        if (s == SOFA_OK && hipStreamSynchronize(st) != hipSuccess)
+          s = set_error(SOFA_EDEVICE, "BF16 copy failed: %s", hipGetErrorString(hipGetLastError()));
+        if (s == SOFA_OK) ix->has_bf16 = 1;
+      }
     }
   }
   if (s != SOFA_OK) {
@@ -360,11 +381,20 @@ struct Layout {
 
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
-  W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE, W_END
+  W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_QB, W_QMETA, W_BCTR, W_END
 };
+
+constexpr int kBf16Cap = 32768;  // BF16 candidates per query and pass
+int bf16_cap(const sofa_knn_params* p) {
+  return (p && p->candidate_capacity > 0) ? p->candidate_capacity : kBf16Cap;
+}
+constexpr int kSampleStride = 32;  // no-radius BF16 search: every 32nd chunk first
 
 Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
   size_t sz[W_END];
+  const bool bf = p && p->prune == 1;
+  const int64_t G = (B + kGroup - 1) / kGroup;
   sz[W_QP] = (size_t)B * ix->n_pad * 4;
   sz[W_POOL] = (size_t)B * ix->bins.ncol_pool * 4;
   sz[W_QN] = (size_t)B * 8;
@@ -383,6 +413,15 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_BAD] = 4;
   sz[W_HIST] = (size_t)B * 256 * 4;
   sz[W_HBASE] = (size_t)B * 4;
+  sz[W_CAND] = bf ? (size_t)B * bf16_cap(p) * 4 : 0;
+  sz[W_CCNT] = bf ? (size_t)B * 4 : 0;
+  sz[W_CEV] = bf ? (size_t)B * 4 : 0;
+  sz[W_QCNT] = bf ? (size_t)B * 4 : 0;
+  sz[W_PERM] = bf ? (size_t)B * 4 : 0;
+  sz[W_GMASK] = bf ? (size_t)ix->n_blocks * G * 8 : 0;
+  sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
+  sz[W_QMETA] = bf ? (size_t)G * kGroup * 16 : 0;
+  sz[W_BCTR] = bf ? 64 : 0;
   Layout L;
   size_t o = 0;
   for (int i = 0; i < W_END; i++) {
@@ -397,9 +436,10 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
 
 extern "C" sofa_status sofa_workspace_bytes_for(const sofa_index* ix, int64_t B, int32_t k, int32_t prune,
                                                 int64_t* bytes) {
-  (void)prune;
   if (!ix || !bytes || B < 0 || k < 1) return set_error(SOFA_EINVAL, "bad arguments");
-  *bytes = (int64_t)layout_for(ix, B, k, nullptr).total;
+  sofa_knn_params p{};
+  p.prune = prune;
+  *bytes = (int64_t)layout_for(ix, B, k, &p).total;
   return SOFA_OK;
 }
 
@@ -416,8 +456,10 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
     return set_error(SOFA_EINVAL, "k=%d outside [1, min(N, %d)]", k, kMaxK);
   if (B == 0) return SOFA_OK;
   if (!d_queries || !d_ids || !d_dists) return set_error(SOFA_EINVAL, "null array");
-  if (params && params->prune != 0)
-    return set_error(SOFA_EINVAL, "the batched-distance prune is not available in this build");
+  if (params && params->prune != 0) {
+    if (params->prune != 1) return set_error(SOFA_EINVAL, "prune must be 0 (off) or 1 (BF16)");
+    if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+  }
   sofa_workspace* ws = params ? params->ws : nullptr;
   if (!ws) {
     sofa_index* mix = const_cast<sofa_index*>(ix);
@@ -499,7 +541,41 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
-  SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
+  const bool bf = p && p->prune == 1;
+  if (!bf) {
+    SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
+  } else {
+    uint32_t* cev = (uint32_t*)at(W_CEV);
+    a.cevmin = cev;
+    SOFA_TRY(launch_fill_u32(cev, 0xFFFFFFFFu, B, st));
+    SOFA_TRY(launch_front(a, st, ev));
+    Bf16Args b{};
+    b.xb = ix->xb.as<uint4>();
+    b.meta = ix->xb_meta.as<float4>();
+    b.leafmeta = ix->xb_leafmeta.as<float4>();
+    b.qb = (uint4*)at(W_QB);
+    b.qmeta = (float4*)at(W_QMETA);
+    b.perm = (int32_t*)at(W_PERM);
+    b.qcount = (uint32_t*)at(W_QCNT);
+    b.gmask = (uint64_t*)at(W_GMASK);
+    b.G = (int)((B + kGroup - 1) / kGroup);
+    b.cand = (uint32_t*)at(W_CAND);
+    b.ccnt = (uint32_t*)at(W_CCNT);
+    b.cevmin = cev;
+    b.cap = bf16_cap(p);
+    b.counter = (uint32_t*)at(W_BCTR);
+    SOFA_TRY(launch_bf16_queries(a, b, st));
+    const int64_t n_chunks = (ix->N + 255) / 256;
+    if (p->d_radius) {
+      SOFA_TRY(launch_bf16_pass(a, b, 0, 1, n_chunks, 0, st));
+    } else {
+      // a systematic sample of chunks first gives a tight bound for the rest
+      const int64_t n1 = (n_chunks + kSampleStride - 1) / kSampleStride;
+      SOFA_TRY(launch_bf16_pass(a, b, 0, kSampleStride, n1, 0, st));
+      SOFA_TRY(launch_bf16_pass(a, b, 0, 0, n_chunks - n1, kSampleStride, st));
+    }
+    SOFA_TRY(launch_finalize(a, d_ids, d_d, status, st, ev));
+  }
   std::vector<int32_t> hst(B);
   std::vector<float> hu0(B);
   unsigned hbad = 0;
@@ -524,6 +600,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   stats.leaves_visited += (int64_t)hstats[0];
   stats.series_lb_checked += (int64_t)hstats[1];
   stats.series_refined += (int64_t)hstats[2];
+  stats.series_bf16_checked += (int64_t)hstats[3];
   std::vector<int64_t> redo;
   for (int64_t q = 0; q < B; q++) {
     int st_q = hst[q];
@@ -555,7 +632,10 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + redo[i] * ix->n, (size_t)ix->n * 4,
                               hipMemcpyDeviceToDevice, st));
     sofa_knn_params p2{};
-    if (p) p2.candidate_capacity = p->candidate_capacity;
+    if (p) {
+      p2.candidate_capacity = p->candidate_capacity;
+      p2.prune = p->prune;
+    }
     sofa_knn_stats s2{};
     SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2));
     for (int64_t i = 0; i < R; i++) {
@@ -569,6 +649,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.leaves_visited += s2.leaves_visited;
     stats.series_lb_checked += s2.series_lb_checked;
     stats.series_refined += s2.series_refined;
+    stats.series_bf16_checked += s2.series_bf16_checked;
     stats.overflow_fallbacks += s2.overflow_fallbacks;
   }
   return SOFA_OK;
@@ -620,6 +701,71 @@ extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_qu
   if (d_tables)
     SOFA_HIP(hipMemcpyAsync(d_tables, tab.p, (size_t)B * kTable * 4, hipMemcpyDeviceToDevice, st));
   if (d_lb) SOFA_TRY(launch_all_lb(a, d_lb, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
+                                              float* d_lb, void* stream) {
+  if (!ix || B < 0 || (B > 0 && (!d_queries || !d_lb))) return set_error(SOFA_EINVAL, "bad arguments");
+  if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+  if (B == 0) return SOFA_OK;
+  if (B > 65535) return set_error(SOFA_EINVAL, "B too large");
+  hipStream_t st = S(stream);
+  const int64_t G = (B + kGroup - 1) / kGroup;
+  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, perm, qb, qmeta, ctr, U, stats;
+  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
+  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
+  SOFA_TRY(qn.alloc((size_t)B * 8));
+  SOFA_TRY(tab.alloc((size_t)B * kTable * 4));
+  SOFA_TRY(sq.alloc((size_t)B * 16));
+  SOFA_TRY(u0.alloc((size_t)B * 4));
+  SOFA_TRY(U.alloc((size_t)B * 4));
+  SOFA_TRY(bad.alloc(4));
+  SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8));
+  SOFA_TRY(gm.alloc((size_t)ix->n_blocks * G * 8));
+  SOFA_TRY(perm.alloc((size_t)B * 4));
+  SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2));
+  SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16));
+  SOFA_TRY(ctr.alloc(64));
+  SOFA_TRY(stats.alloc(64));
+  SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
+  SOFA_TRY(launch_fill_u32(stats.as<uint32_t>(), 0u, 16, st));
+  SearchArgs a{};
+  a.stats = stats.as<unsigned long long>();
+  a.X = ix->X.as<float>();
+  a.N = ix->N;
+  a.n = ix->n;
+  a.n_pad = ix->n_pad;
+  a.L = ix->L;
+  a.n_leaves = ix->n_leaves;
+  a.n_blocks = ix->n_blocks;
+  a.B = (int)B;
+  a.Qp = qp.as<float>();
+  a.tables = tab.as<float>();
+  a.sq = sq.as<uint4>();
+  a.U0 = u0.as<float>();
+  a.U = U.as<uint32_t>();
+  a.masks = masks.as<uint64_t>();
+  a.eta_x = ix->eta_x;
+  a.lb_f = 1.0f;
+  SOFA_TRY(launch_prepare(a, d_queries, nullptr, ix->bins, pool.as<float>(), qn.as<double>(),
+                          bad.as<unsigned>(), st));
+  SOFA_TRY(launch_fill_u32((uint32_t*)masks.p, 0xFFFFFFFFu, ix->n_blocks * B * 2, st));
+  SOFA_TRY(launch_fill_u32(U.as<uint32_t>(), 0x7F800000u, B, st));
+  Bf16Args b{};
+  b.xb = ix->xb.as<uint4>();
+  b.meta = ix->xb_meta.as<float4>();
+  b.leafmeta = ix->xb_leafmeta.as<float4>();
+  b.qb = qb.as<uint4>();
+  b.qmeta = qmeta.as<float4>();
+  b.perm = perm.as<int32_t>();
+  b.qcount = u0.as<uint32_t>();  // scratch for the density sort
+  b.gmask = gm.as<uint64_t>();
+  b.G = (int)G;
+  b.counter = ctr.as<uint32_t>();
+  SOFA_TRY(launch_bf16_queries(a, b, st));
+  SOFA_TRY(launch_bf16_dump(a, b, d_lb, st));
   SOFA_HIP(hipStreamSynchronize(st));
   return SOFA_OK;
 }

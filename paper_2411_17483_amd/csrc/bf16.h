@@ -1,0 +1,37 @@
+// bf16.h -- arguments of the BF16 batched-distance prune (internal).
+#pragma once
+
+#include "search_dev.h"
+
+namespace sofa {
+
+constexpr int kGroup = 64;  // queries per MFMA query group
+
+struct Bf16Args {
+  const uint4* xb;          // BF16 rows in MFMA A-operand order
+  const float4* meta;       // per row: |x|^2 (down), r_x (up), |xh| (up)
+  const float4* leafmeta;   // per leaf: max |xh|, max r_x, max |x|^2
+  uint4* qb;                // BF16 query fragments per sorted slot
+  float4* qmeta;            // per slot: |q|^2 (down), r_q (up), |qh| (up), |q| (up)
+  int32_t* perm;            // sorted slot -> query
+  uint32_t* qcount;         // surviving leaves per query
+  uint64_t* gmask;          // n_blocks x G group survivor masks
+  int G;                    // query groups
+  uint32_t* cand;           // B x cap candidate rows
+  uint32_t* ccnt;           // B
+  uint32_t* cevmin;         // B smallest lower bound of a dropped candidate (FP32 bits)
+  int cap;
+  uint32_t* counter;
+  int64_t chunk_first, chunk_stride, n_items;  // 256-row chunks of this pass
+  int skip;                 // > 0: the pass enumerates the chunks that are not multiples of skip
+  float* dump;              // inspection only: B x N lower bounds of every pair (no pruning)
+};
+
+sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
+                              uint4* xb, float4* meta, float4* leafmeta, hipStream_t st);
+sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st);
+sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
+sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t first, int64_t stride,
+                             int64_t n_items, int skip, hipStream_t st);
+
+}  // namespace sofa

@@ -1,0 +1,495 @@
+// k_bf16.hip -- batched-distance prune on the matrix cores (BF16 inputs,
+// FP32 accumulation), used only to discard rows under a rigorous bound; the
+// survivors are refined with exact FP32 distances and ranked in FP64.
+//
+// For a query q and a row x (both FP32) with BF16 copies qh, xh,
+//   q.x = qh.xh + q.(x - xh) + (q - qh).xh
+// so with P the FP32 MFMA sum of the exact BF16 products,
+//   q.x <= P + g*|qh||xh| + |q| r_x + r_q |xh|,   r_x = |x - xh|, r_q = |q - qh|,
+// where g = (K + 16) 2^-23 bounds the FP32 accumulation of K products.  Then
+//   d^2 = |q|^2 + |x|^2 - 2 q.x >= |q|^2 + |x|^2 - 2 P - 2 (g|qh||xh| + |q| r_x + r_q |xh|),
+// and a row is kept only when this lower bound does not exceed the query's
+// bound U on the k-th distance.  |x|^2 and |q|^2 are rounded down, r_x, r_q,
+// |xh|, |qh| up, and a relative 2^-20 of |q|^2 + |x|^2 covers the FP32
+// evaluation of the bound.  Per leaf, |xh| and r_x enter through their
+// maxima over the leaf, so the per-pair epilogue is one FMA and a compare.
+//
+// Layout: the BF16 copy is stored in v_mfma_f32_32x32x16_bf16 A-operand
+// order, so that one wave's fragment load for a 32-row x 16-column block is
+// one contiguous 1 KB read.  A workgroup takes 256 rows (4 waves x 64 rows,
+// operand held in registers) and loops over the 64-query groups that have a
+// surviving (query, leaf) pair; each group's BF16 query fragments are staged
+// in LDS.  Queries are ordered by their number of surviving leaves, so that
+// queries the SFA bound cannot prune share groups.
+#include "bf16.h"
+
+namespace sofa {
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_val(uint32_t h) { return __uint_as_float(h << 16); }
+
+// ----------------------------------------------------------------------------
+// build: swizzled BF16 copy.  Thread i writes the 8 values of fragment slot
+// i = ((rb*KS + ks)*64 + lane): rows rb*32 + lane%32, columns ks*16 + 8*(lane/32) + e.
+__global__ void k_bf16_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
+                            uint4* __restrict__ xb) {
+  const int KS = n_pad / 16;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrb * KS * 64) return;
+  const int lane = (int)(i % 64);
+  const int64_t t = i / 64;
+  const int ks = (int)(t % KS);
+  const int64_t rb = t / KS;
+  const int64_t row = rb * 32 + lane % 32;
+  const int k0 = ks * 16 + 8 * (lane / 32);
+  uint32_t w[4] = {0, 0, 0, 0};
+  if (row < N) {
+    float4 a = *reinterpret_cast<const float4*>(X + row * n_pad + k0);
+    float4 b = *reinterpret_cast<const float4*>(X + row * n_pad + k0 + 4);
+    w[0] = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
+    w[1] = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
+    w[2] = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
+    w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
+  }
+  xb[i] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// per row: |x|^2 rounded down, r_x = |x - xh| up, |xh| up (one wave per row)
+__device__ __forceinline__ void norms_of(const float* __restrict__ row, int n_pad, int lane,
+                                         float4& out) {
+  double s2 = 0.0, r2 = 0.0, h2 = 0.0;
+  for (int c = lane * 4; c < n_pad; c += 256) {
+    float4 v = *reinterpret_cast<const float4*>(row + c);
+    float xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      double x = xs[e], h = bf16_val(bf16_bits(xs[e]));
+      s2 += x * x;
+      r2 += (x - h) * (x - h);
+      h2 += h * h;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s2 += __shfl_xor(s2, o);
+    r2 += __shfl_xor(r2, o);
+    h2 += __shfl_xor(h2, o);
+  }
+  out = make_float4(__double2float_rd(s2 * (1.0 - 1e-12)), __double2float_ru(sqrt(r2) * (1.0 + 1e-12)),
+                    __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
+}
+
+__global__ __launch_bounds__(256) void k_bf16_meta(const float* __restrict__ X, int64_t N, int n_pad,
+                                                   float4* __restrict__ meta) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  float4 m;
+  norms_of(X + row * n_pad, n_pad, lane, m);
+  if (lane == 0) meta[row] = m;
+}
+
+// per leaf: (max |xh|, max r_x, max |x|^2)
+__global__ __launch_bounds__(256) void k_bf16_leafmeta(const float4* __restrict__ meta, int64_t N,
+                                                       int L, int64_t n_leaves,
+                                                       float4* __restrict__ lm) {
+  const int lane = threadIdx.x & 63;
+  const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (leaf >= n_leaves) return;
+  float xh = 0.0f, rx = 0.0f, xn = 0.0f;
+  for (int64_t p = leaf * L + lane; p < (leaf + 1) * L && p < N; p += 64) {
+    float4 m = meta[p];
+    xh = fmaxf(xh, m.z);
+    rx = fmaxf(rx, m.y);
+    xn = fmaxf(xn, m.x);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    xh = fmaxf(xh, __shfl_xor(xh, o));
+    rx = fmaxf(rx, __shfl_xor(rx, o));
+    xn = fmaxf(xn, __shfl_xor(xn, o));
+  }
+  // |x|^2 was rounded down: the margin below uses a value rounded up
+  if (lane == 0) lm[leaf] = make_float4(xh, rx, xn * (1.0f + 0x1p-20f), 0.0f);
+}
+
+// ----------------------------------------------------------------------------
+// query side
+// surviving leaves per query
+__global__ void k_qcount(const uint64_t* __restrict__ masks, int64_t n_blocks, int B,
+                         uint32_t* __restrict__ cnt) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= B) return;
+  uint32_t c = 0;
+  for (int64_t b = 0; b < n_blocks; b++) c += __popcll(masks[b * B + q]);
+  cnt[q] = c;
+}
+
+// order: more surviving leaves first, then lower query index
+__global__ void k_qsort(const uint32_t* __restrict__ cnt, int B, int32_t* __restrict__ perm) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= B) return;
+  uint32_t c = cnt[q];
+  int rank = 0;
+  for (int o = 0; o < B; o++) {
+    uint32_t d = cnt[o];
+    rank += (d > c || (d == c && o < q)) ? 1 : 0;
+  }
+  perm[rank] = q;
+}
+
+// gmask[blk][g]: bit i set when leaf blk*64+i survives for some query of group g
+__global__ void k_gmask(const uint64_t* __restrict__ masks, int64_t n_blocks, int B,
+                        const int32_t* __restrict__ perm, int G, uint64_t* __restrict__ gmask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_blocks * G) return;
+  int64_t b = i / G;
+  int g = (int)(i % G);
+  uint64_t m = 0;
+  for (int s = g * kGroup; s < (g + 1) * kGroup && s < B; s++) m |= masks[b * B + perm[s]];
+  gmask[i] = m;
+}
+
+// swizzled BF16 query fragments per sorted slot and the query bound terms
+__global__ void k_qprep_bf16(const float* __restrict__ Qp, int B, int n_pad, int Spad,
+                             const int32_t* __restrict__ perm, uint4* __restrict__ qb) {
+  const int KS = n_pad / 16;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)(Spad / 32) * KS * 64) return;
+  const int lane = (int)(i % 64);
+  const int64_t t = i / 64;
+  const int ks = (int)(t % KS);
+  const int cb = (int)(t / KS);
+  const int s = cb * 32 + lane % 32;
+  const int k0 = ks * 16 + 8 * (lane / 32);
+  uint32_t w[4] = {0, 0, 0, 0};
+  if (s < B) {
+    const float* qr = Qp + (int64_t)perm[s] * n_pad;
+    float4 a = *reinterpret_cast<const float4*>(qr + k0);
+    float4 b = *reinterpret_cast<const float4*>(qr + k0 + 4);
+    w[0] = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
+    w[1] = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
+    w[2] = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
+    w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
+  }
+  qb[i] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp, int B, int n_pad,
+                                                    const int32_t* __restrict__ perm, int Spad,
+                                                    float4* __restrict__ qmeta) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= Spad) return;
+  float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (s < B) norms_of(Qp + (int64_t)perm[s] * n_pad, n_pad, lane, m);
+  // m = (|q|^2 down, r_q up, |qh| up); the bound also needs |q| (up)
+  if (lane == 0) {
+    m.w = __double2float_ru(sqrt((double)m.x) * (1.0 + 1e-7) + 1e-30);
+    qmeta[s] = m;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// tiles: one 256-row chunk per work item
+template <int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_bf16_tiles(SearchArgs a, Bf16Args b) {
+  __shared__ __attribute__((aligned(16))) uint4 Bs[2 * KS * 64];
+  __shared__ float xn2s[256];
+  __shared__ uint32_t item_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float gam = (float)(KS * 16 + 16) * 0x1p-23f;
+  unsigned long long st_pairs = 0;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const uint32_t it = item_sh;
+    __syncthreads();
+    if ((int64_t)it >= b.n_items) break;
+    // skip > 0: enumerate the chunks that are not multiples of skip
+    const int64_t chunk = b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
+                                     : (int64_t)it * b.chunk_stride + b.chunk_first;
+    const int64_t c0 = chunk * 256;
+    const int64_t leaf = c0 / a.L;
+    const int64_t blk = leaf / kLeavesPerItem;
+    const int bit = (int)(leaf % kLeavesPerItem);
+    // A operand: this wave's 64 rows, all K steps, in registers
+    const int64_t rb0 = (c0 + 64 * wave) / 32;
+    bf8v av[2][KS];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        uint4 v = b.xb[((rb0 + r) * KS + ks) * 64 + lane];
+        av[r][ks] = *reinterpret_cast<bf8v*>(&v);
+      }
+    {
+      const int64_t row = c0 + threadIdx.x;
+      xn2s[threadIdx.x] = row < a.N ? b.meta[row].x : 0.0f;
+    }
+    const float4 lmx = b.leafmeta[leaf];
+    for (int g = 0; g < b.G; g++) {
+      if (!((b.gmask[blk * b.G + g] >> bit) & 1ull)) continue;
+      __syncthreads();
+      const uint4* src = b.qb + (int64_t)(2 * g) * KS * 64;
+      for (int i = threadIdx.x; i < 2 * KS * 64; i += 256) Bs[i] = src[i];
+      // per-lane query terms for the two 32-query blocks of the group
+      float cq[2], oq[2];
+      int qo[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++) {
+        const int s = g * kGroup + cb * 32 + (lane & 31);
+        qo[cb] = s < a.B ? b.perm[s] : -1;
+        const float4 qm = b.qmeta[s];
+        const float U = qo[cb] >= 0 ? __uint_as_float(__atomic_load_n(a.U + qo[cb], __ATOMIC_RELAXED)) : -1.0f;
+        // offset o: LB = t - o with t = |x|^2 - 2P
+        const float o = -qm.x + 2.0f * (gam * qm.z + qm.y) * lmx.x + 2.0f * qm.w * lmx.y +
+                        (qm.x + lmx.z) * 0x1p-20f;
+        cq[cb] = qo[cb] >= 0 ? U * a.lb_f + o : -INFINITY;
+        oq[cb] = o;
+      }
+      __syncthreads();
+      f16v acc[2][2];
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+          for (int e = 0; e < 16; e++) acc[r][cb][e] = 0.0f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        uint4 u0 = Bs[(0 * KS + ks) * 64 + lane];
+        uint4 u1 = Bs[(1 * KS + ks) * 64 + lane];
+        bf8v b0 = *reinterpret_cast<bf8v*>(&u0);
+        bf8v b1 = *reinterpret_cast<bf8v*>(&u1);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], b1, acc[1][1], 0, 0, 0);
+      }
+      st_pairs += 64 * 64;
+      // epilogue: D[i][j], j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row).
+      // Unrolled compares build a hit mask; the rare hits are appended in a
+      // loop that only needs the row index.
+      if (b.dump) {
+        // inspection: the lower bound of every pair, t - o
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+          for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+              const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+              const float t = fmaf(-2.0f, acc[r][cb][e], xn2s[ri]);
+              if (c0 + ri < a.N && qo[cb] >= 0) b.dump[(int64_t)qo[cb] * a.N + c0 + ri] = t - oq[cb];
+            }
+        continue;
+      }
+      uint32_t hits[2][2];
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) {
+          uint32_t h = 0;
+#pragma unroll
+          for (int e = 0; e < 16; e++) {
+            const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+            const float t = fmaf(-2.0f, acc[r][cb][e], xn2s[ri]);
+            h |= (t <= cq[cb]) ? (1u << e) : 0u;
+          }
+          hits[r][cb] = h;
+        }
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) {
+          uint32_t h = hits[r][cb];
+          while (h) {
+            const int e = __builtin_ctz(h);
+            h &= h - 1;
+            const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+            const int64_t row = c0 + ri;
+            const int q = qo[cb];
+            if (row < a.N && ((a.masks[blk * a.B + q] >> bit) & 1ull)) {
+              const uint32_t slot = atomicAdd(b.ccnt + q, 1u);
+              if (slot < (uint32_t)b.cap)
+                b.cand[(int64_t)q * b.cap + slot] = (uint32_t)row;
+              else
+                atomicMin(b.cevmin + q, 0u);  // a dropped candidate: finish exhaustively
+            }
+          }
+        }
+    }
+  }
+  if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
+}
+
+// ----------------------------------------------------------------------------
+// exact FP32 refinement of the candidate lists: workgroup (q, z) of a
+// (B x kCandSplit) grid; wave w takes 64-candidate chunks z*4+w, +4*kCandSplit, ...
+constexpr int kCandSplit = 8;
+
+template <int NIT, int R>
+__global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
+  const int q = blockIdx.x, z = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const uint32_t cnt_all = b.ccnt[q];
+  const uint32_t cnt = cnt_all < (uint32_t)b.cap ? cnt_all : (uint32_t)b.cap;
+  if ((uint32_t)(z * 4 + wave) * 64 >= cnt) return;
+  float4 qr[NIT];
+  load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
+  float Umin = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+  float Upub = Umin;
+  WaveList<R> wl;
+  wl.reset();
+  unsigned long long st_refined = 0;
+  for (uint32_t ch = z * 4 + wave; ch * 64 < cnt; ch += 4 * kCandSplit) {
+    const uint32_t idx = ch * 64 + lane;
+    const bool valid = idx < cnt;
+    const uint32_t pos = valid ? b.cand[(int64_t)q * b.cap + idx] : 0u;
+    uint64_t bal = __ballot(valid);
+    st_refined += (unsigned long long)__popcll(bal);
+    const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+    Umin = ug < Umin ? ug : Umin;
+    while (bal) {
+      int c0[4], c1[4];
+#pragma unroll
+      for (int gi = 0; gi < 4; gi++) {
+        c0[gi] = bal ? __builtin_ctzll(bal) : -1;
+        bal = bal ? (bal & (bal - 1)) : 0ull;
+      }
+#pragma unroll
+      for (int gi = 0; gi < 4; gi++) {
+        c1[gi] = bal ? __builtin_ctzll(bal) : -1;
+        bal = bal ? (bal & (bal - 1)) : 0ull;
+      }
+      uint32_t p0[4], p1[4];
+#pragma unroll
+      for (int gi = 0; gi < 4; gi++) {
+        p0[gi] = __shfl(pos, c0[gi] >= 0 ? c0[gi] : 0);
+        p1[gi] = __shfl(pos, c1[gi] >= 0 ? c1[gi] : 0);
+      }
+      const int ca = c0[g], cbb = c1[g];
+      const float abandon = Umin * a.abandon_f;
+      float da = dist4<NIT>(a.X + (int64_t)p0[g] * a.n_pad, ca >= 0, qr, li, abandon);
+      float db = INFINITY;
+      if (c1[0] >= 0) db = dist4<NIT>(a.X + (int64_t)p1[g] * a.n_pad, cbb >= 0, qr, li, abandon);
+      float band = Umin * a.band_f;
+      uint64_t ins = __ballot(li == 0 && ((ca >= 0 && da <= band) || (cbb >= 0 && db <= band)));
+      while (ins) {
+        const int gl = __builtin_ctzll(ins);
+        ins &= ins - 1;
+        const int gg = gl >> 4;
+        const float dA = __shfl(da, gl), dB = __shfl(db, gl);
+        if (c0[gg] >= 0 && dA <= band) wl.insert(((uint64_t)__float_as_uint(dA) << 32) | p0[gg], lane);
+        if (c1[gg] >= 0 && dB <= band) wl.insert(((uint64_t)__float_as_uint(dB) << 32) | p1[gg], lane);
+        const uint64_t kth = wl.at(a.k - 1);
+        if (kth != kEmpty) {
+          const float uw = key_d(kth) * a.upd_f;
+          if (uw < Umin) {
+            Umin = uw;
+            band = Umin * a.band_f;
+          }
+        }
+      }
+    }
+    if (Umin < Upub) {
+      if (lane == 0) atomicMin(a.U + q, __float_as_uint(Umin));
+      Upub = Umin;
+    }
+  }
+  flush_wave_list<R>(a, q, wl, Umin, lane);
+  if (lane == 0 && st_refined && a.stats) atomicAdd(a.stats + 2, st_refined);
+}
+
+// ----------------------------------------------------------------------------
+sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
+                              uint4* xb, float4* meta, float4* leafmeta, hipStream_t st) {
+  const int64_t nrb = ((N + 255) / 256) * 8;  // 32-row blocks, padded to whole 256-row chunks
+  const int KS = n_pad / 16;
+  k_bf16_copy<<<nblk(nrb * KS * 64, 256), 256, 0, st>>>(X, N, n_pad, nrb, xb);
+  k_bf16_meta<<<nblk(N, 4), 256, 0, st>>>(X, N, n_pad, meta);
+  k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st) {
+  const int B = a.B;
+  k_qcount<<<nblk(B, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, b.qcount);
+  k_qsort<<<nblk(B, 256), 256, 0, st>>>(b.qcount, B, b.perm);
+  k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, b.perm, b.G, b.gmask);
+  const int Spad = b.G * kGroup;
+  const int KS = a.n_pad / 16;
+  k_qprep_bf16<<<nblk((int64_t)(Spad / 32) * KS * 64, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
+                                                                           b.perm, b.qb);
+  k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st) {
+  b.dump = d_lb;
+  b.skip = 0;
+  b.chunk_first = 0;
+  b.chunk_stride = 1;
+  b.n_items = (a.N + 255) / 256;
+  SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
+  unsigned grid = 256 * 2;
+  if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
+  switch (a.n_pad / 16) {
+    case 4: k_bf16_tiles<4><<<grid, 256, 0, st>>>(a, b); break;
+    case 8: k_bf16_tiles<8><<<grid, 256, 0, st>>>(a, b); break;
+    case 16: k_bf16_tiles<16><<<grid, 256, 0, st>>>(a, b); break;
+    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
+  }
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t first, int64_t stride,
+                             int64_t n_items, int skip, hipStream_t st) {
+  b.chunk_first = first;
+  b.chunk_stride = stride;
+  b.n_items = n_items;
+  b.skip = skip;
+  if (n_items <= 0) return SOFA_OK;
+  SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
+  SOFA_TRY(launch_fill_u32(b.ccnt, 0u, a.B, st));
+  unsigned grid = 256 * 2;
+  if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
+  switch (a.n_pad / 16) {
+    case 4: k_bf16_tiles<4><<<grid, 256, 0, st>>>(a, b); break;
+    case 8: k_bf16_tiles<8><<<grid, 256, 0, st>>>(a, b); break;
+    case 16: k_bf16_tiles<16><<<grid, 256, 0, st>>>(a, b); break;
+    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256 (padded %d)", a.n_pad);
+  }
+  dim3 gr((unsigned)a.B, kCandSplit);
+  const int R = (a.k + 16 <= 64) ? 1 : 2;
+#define SOFA_RC(NI)                                                     \
+  case NI:                                                              \
+    if (R == 1) k_refine_cand<NI, 1><<<gr, 256, 0, st>>>(a, b);         \
+    else k_refine_cand<NI, 2><<<gr, 256, 0, st>>>(a, b);                \
+    break;
+  switch (a.n_pad / 64) {
+    SOFA_RC(1)
+    SOFA_RC(2)
+    SOFA_RC(4)
+    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
+  }
+#undef SOFA_RC
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+}  // namespace sofa

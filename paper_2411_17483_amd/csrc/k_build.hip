@@ -156,9 +156,8 @@ sofa_status launch_project(const float* X, int64_t m, int n, int64_t ldx, const 
 }
 
 // ----------------------------------------------------------------------------
-// sort key: bit-interleave (most significant first) of the leading 4 bits of
-// every symbol scaled to 8 bits, positions in word order.
-__global__ void k_keys(const uint8_t* __restrict__ words, int64_t N, int l, int alpha,
+// sort key of every row (sfa_key)
+__global__ void k_keys(const uint8_t* __restrict__ words, int64_t N, int l, int alpha, int scheme,
                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -170,12 +169,7 @@ __global__ void k_keys(const uint8_t* __restrict__ words, int64_t N, int l, int 
     uint32_t s = (wv[j >> 2] >> (8 * (j & 3))) & 255u;
     s8[j] = (j < l) ? (s * 256u) / (uint32_t)alpha : 0u;
   }
-  uint64_t key = 0;
-#pragma unroll
-  for (int b = 7; b >= 4; b--)
-#pragma unroll
-    for (int j = 0; j < 16; j++) key = (key << 1) | ((s8[j] >> b) & 1u);
-  keys[i] = key;
+  keys[i] = sfa_key(s8, scheme);
   vals[i] = (uint32_t)i;
 }
 
@@ -364,8 +358,8 @@ sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_i
   const int64_t ntiles = (N + kRsTile - 1) / kRsTile;
   SOFA_TRY(hist.alloc(4 * 256 * ntiles));
   SOFA_TRY(mx.alloc(8));
-  k_keys<<<nblk(N, 256), 256, 0, st>>>(words_in, N, ix->bins.l, ix->bins.alpha, k0.as<uint64_t>(),
-                                       v0.as<uint32_t>());
+  k_keys<<<nblk(N, 256), 256, 0, st>>>(words_in, N, ix->bins.l, ix->bins.alpha, ix->key_scheme,
+                                       k0.as<uint64_t>(), v0.as<uint32_t>());
   uint64_t *ka = k0.as<uint64_t>(), *kb = k1.as<uint64_t>();
   uint32_t *va = v0.as<uint32_t>(), *vb = v1.as<uint32_t>();
   for (int shift = 0; shift < 64; shift += 8) {

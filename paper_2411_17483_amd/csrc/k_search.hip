@@ -31,121 +31,11 @@
 //   LB32 <= U * (1 + 2^-16) (the FP32 table sum overestimates by at most
 //   ~20 ulp).  Distances are kept when d32 <= U * (1 + 3 eps), which contains
 //   every series whose exact distance is <= U.  The final ranking uses FP64.
-#include "search.h"
+#include "search_dev.h"
 
 namespace sofa {
 
 static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
-
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t byte_of(const uint4& w, int j) {
-  uint32_t v = (j < 4) ? w.x : (j < 8) ? w.y : (j < 12) ? w.z : w.w;
-  return (v >> (8 * (j & 3))) & 255u;
-}
-
-__device__ __forceinline__ float lb_word(const float* T, const uint4& w) {
-  // positions 0..15 in order: bytes 0..3 of w.x, then w.y, w.z, w.w
-  float s = 0.0f;
-  const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-  for (int j = 0; j < 16; j++) s += T[j * kAlphaMax + ((wv[j >> 2] >> (8 * (j & 3))) & 255u)];
-  return s;
-}
-
-__device__ __forceinline__ float lb_leaf(const float* T, const uint4& sq, const uint4& lo,
-                                         const uint4& hi) {
-  float s = 0.0f;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    uint32_t q = byte_of(sq, j), a = byte_of(lo, j), b = byte_of(hi, j);
-    uint32_t c = q < a ? a : (q > b ? b : q);
-    s += T[j * kAlphaMax + c];
-  }
-  return s;
-}
-
-__device__ __forceinline__ float key_d(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
-constexpr uint64_t kEmpty = ~0ull;
-
-// Sorted per-wave candidate list: rank r lives in register r/64, lane r%64.
-// `evicted` keeps the smallest key ever pushed out of the list (or refused
-// when the list was full); the search is exact as long as that key lies
-// outside the final error band, which k_finalize checks.
-template <int R>
-struct WaveList {
-  uint64_t e[R];
-  uint64_t evicted;
-  __device__ void reset() {
-#pragma unroll
-    for (int r = 0; r < R; r++) e[r] = kEmpty;
-    evicted = kEmpty;
-  }
-  __device__ uint64_t at(int rank) const {
-    uint64_t v = kEmpty;
-#pragma unroll
-    for (int r = 0; r < R; r++)
-      if (rank / 64 == r) v = __shfl(e[r], rank & 63);
-    return v;
-  }
-  __device__ void insert(uint64_t key, int lane) {
-    int pos = 0;
-    uint64_t top[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      pos += __popcll(__ballot(e[r] < key));
-      top[r] = __shfl(e[r], 63);
-    }
-    if (pos >= 64 * R) {
-      evicted = key < evicted ? key : evicted;
-      return;
-    }
-    const uint64_t last = top[R - 1];
-    evicted = last < evicted ? last : evicted;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      uint64_t up = __shfl_up(e[r], 1);
-      if (lane == 0) up = (r > 0) ? top[r - 1] : e[r];
-      int rank = lane + 64 * r;
-      e[r] = rank < pos ? e[r] : (rank == pos ? key : up);
-    }
-  }
-};
-
-// FP32 squared distance of 4 rows at once: lane group g = lane/16 handles the
-// row at xrow (when active); lane li = lane%16 owns elements li*4 + 64*it.
-// Partial sums are checked every 256 elements against `abandon`; a group whose
-// partial exceeds it stops loading.  Returns the group's sum (all 16 lanes) or
-// +inf when abandoned/inactive.
-template <int NIT>
-__device__ __forceinline__ float dist4(const float* __restrict__ xrow, bool active,
-                                       const float4 (&q)[NIT], int li, float abandon) {
-  float acc = 0.0f;
-  bool live = active;
-#pragma unroll
-  for (int it = 0; it < NIT; it++) {
-    if (live) {
-      float4 x = *reinterpret_cast<const float4*>(xrow + li * 4 + 64 * it);
-      float d0 = q[it].x - x.x, d1 = q[it].y - x.y, d2 = q[it].z - x.z, d3 = q[it].w - x.w;
-      acc = fmaf(d0, d0, acc);
-      acc = fmaf(d1, d1, acc);
-      acc = fmaf(d2, d2, acc);
-      acc = fmaf(d3, d3, acc);
-    }
-    if ((it & 3) == 3 && it + 1 < NIT) {
-      float p = acc;
-      p += __shfl_xor(p, 8);
-      p += __shfl_xor(p, 4);
-      p += __shfl_xor(p, 2);
-      p += __shfl_xor(p, 1);
-      if (p > abandon) live = false;
-    }
-  }
-  acc += __shfl_xor(acc, 8);
-  acc += __shfl_xor(acc, 4);
-  acc += __shfl_xor(acc, 2);
-  acc += __shfl_xor(acc, 1);
-  return live ? acc : INFINITY;
-}
 
 // ----------------------------------------------------------------------------
 // 1. lower-bound tables
@@ -239,15 +129,8 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
     }
     if (lane == 0 && best != kEmpty) atomicMin(reinterpret_cast<unsigned long long*>(a.best) + q, best);
   } else {
-    if (lane == 0 && visited) atomicAdd(a.stats + 0, visited);
+    if (lane == 0 && visited && a.stats) atomicAdd(a.stats + 0, visited);
   }
-}
-
-// q row of a query held in registers by lane li of every 16-lane group
-template <int NIT>
-__device__ __forceinline__ void load_q(const float* qrow, int li, float4 (&q)[NIT]) {
-#pragma unroll
-  for (int it = 0; it < NIT; it++) q[it] = *reinterpret_cast<const float4*>(qrow + li * 4 + 64 * it);
 }
 
 // 3. seed: one wave per query scans the best leaf's rows.
@@ -301,7 +184,6 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
 // b = x mod 8, query-minor: workgroups are dispatched to the 8 XCDs round
 // robin, so the rows that concurrent queries share stay in one XCD's L2.
 constexpr int kSub = 8;                        // leaves per work item
-constexpr int kHistBins = 256;                 // per-query histogram of flushed distances
 constexpr int kSubPerBlock = kLeavesPerItem / kSub;
 constexpr int kQueues = 8;
 
@@ -406,109 +288,17 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
         }
       }
     }
-    // flush the in-band candidates of this wave
-    {
-      const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
-      Umin = ug < Umin ? ug : Umin;
-      const float band = Umin * a.band_f;
-      uint64_t evk = wl.evicted;
-      int cnt = 0;
-      uint64_t bals[R];
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        bals[r] = __ballot(wl.e[r] != kEmpty && key_d(wl.e[r]) <= band);
-        cnt += __popcll(bals[r]);
-      }
-      if (cnt > 0) {
-        uint32_t b0 = 0;
-        if (lane == 0) b0 = atomicAdd(a.rescnt + q, (uint32_t)cnt);
-        b0 = __shfl(b0, 0);
-        int off = 0;
-        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        uint64_t lost = kEmpty;
-        const float hb = a.hbase[q];
-        const bool hist_on = hb > 0.0f && hb < INFINITY;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          if ((bals[r] >> lane) & 1ull) {
-            const uint32_t slot = b0 + off + __popcll(bals[r] & lt);
-            if (slot < (uint32_t)a.cap) a.res[(int64_t)q * a.cap + slot] = wl.e[r];
-            else lost = wl.e[r] < lost ? wl.e[r] : lost;
-            if (hist_on) {
-              int bk = (int)(key_d(wl.e[r]) / hb * (float)kHistBins);
-              bk = bk < 0 ? 0 : (bk >= kHistBins ? kHistBins - 1 : bk);
-              atomicAdd(a.hist + (int64_t)q * kHistBins + bk, 1u);
-            }
-          }
-          off += __popcll(bals[r]);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          uint64_t t = __shfl_xor(lost, o);
-          lost = t < lost ? t : lost;
-        }
-        evk = lost < evk ? lost : evk;
-        if (hist_on) {
-          // the first bucket edge below which at least k candidates lie is a
-          // bound on the k-th distance (one bucket of slack for rounding)
-          uint32_t c4[kHistBins / 64];
-          uint32_t cs = 0;
-#pragma unroll
-          for (int i = 0; i < kHistBins / 64; i++) {
-            c4[i] = __atomic_load_n(a.hist + (int64_t)q * kHistBins + lane * (kHistBins / 64) + i,
-                                    __ATOMIC_RELAXED);
-            cs += c4[i];
-          }
-          uint32_t incl = cs;
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            uint32_t t = __shfl_up(incl, o);
-            if (lane >= o) incl += t;
-          }
-          const uint64_t hit = __ballot(incl >= (uint32_t)a.k);
-          if (hit) {
-            const int hl = __builtin_ctzll(hit);
-            uint32_t run = __shfl(incl - cs, hl);
-            int bk = hl * (kHistBins / 64) + kHistBins / 64 - 1;
-            for (int i = 0; i < kHistBins / 64; i++) {
-              run += __shfl(c4[i], hl);
-              if (run >= (uint32_t)a.k) {
-                bk = hl * (kHistBins / 64) + i;
-                break;
-              }
-            }
-            const float uh = hb * ((float)(bk + 2) / (float)kHistBins) * a.upd_f;
-            if (uh < Umin) {
-              Umin = uh;
-              if (lane == 0) atomicMin(a.U + q, __float_as_uint(uh));
-            }
-          }
-        }
-      }
-      if (lane == 0 && evk != kEmpty && key_d(evk) <= band)
-        atomicMin(reinterpret_cast<unsigned long long*>(a.evmin) + q, evk);
-    }
+    flush_wave_list<R>(a, q, wl, Umin, lane);
     __syncthreads();
   }
   if (lane == 0) {
-    if (st_words) atomicAdd(a.stats + 1, st_words);
-    if (st_refined) atomicAdd(a.stats + 2, st_refined);
+    if (st_words && a.stats) atomicAdd(a.stats + 1, st_words);
+    if (st_refined && a.stats) atomicAdd(a.stats + 2, st_refined);
   }
 }
 
 // 5. finalize: FP64 recomputation of the in-band candidates and ranking.
 constexpr int kSMax = 1024;
-
-__device__ double exact_d2(const float* __restrict__ q, const float* __restrict__ x, int n) {
-#pragma clang fp contract(off)
-  double s = 0.0;
-  for (int t = 0; t < n; t++) {
-    double d = (double)q[t] - (double)x[t];
-    double sq = d * d;
-    s = s + sq;
-  }
-  return s;
-}
 
 __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restrict__ out_ids,
                                                   float* __restrict__ out_d,
@@ -529,6 +319,9 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
   // exact unless a key inside the final band was ever evicted or dropped
   const uint64_t ev = a.evmin[q];
   bool ovf = ev != kEmpty && key_d(ev) <= band;
+  if (a.cevmin && a.cevmin[q] != 0xFFFFFFFFu &&
+      __uint_as_float(a.cevmin[q]) <= __uint_as_float(a.U[q]) * a.lb_f)
+    ovf = true;
   const uint32_t lim = cnt < (uint32_t)a.cap ? cnt : (uint32_t)a.cap;
   for (uint32_t i = t; i < lim; i += 256) {
     uint64_t key = a.res[(int64_t)q * a.cap + i];
@@ -690,13 +483,12 @@ sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st) {
   return SOFA_OK;
 }
 
-static inline void mark(hipEvent_t* ev, int i, hipStream_t st) {
+inline void mark(hipEvent_t* ev, int i, hipStream_t st) {
   if (ev) (void)hipEventRecord(ev[i], st);
 }
 
 template <int NIT, int R>
-static void launch_search_t(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
-                            unsigned refine_grid, hipStream_t st, hipEvent_t* ev) {
+static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) {
   dim3 gl((unsigned)((a.n_leaves + kSegLeaves - 1) / kSegLeaves), (unsigned)a.B);
   mark(ev, 1, st);
   k_leaf_lb<0><<<gl, 256, 0, st>>>(a);
@@ -705,10 +497,6 @@ static void launch_search_t(const SearchArgs& a, int64_t* out_ids, float* out_d,
   mark(ev, 3, st);
   k_leaf_lb<1><<<gl, 256, 0, st>>>(a);
   mark(ev, 4, st);
-  k_refine<NIT, R><<<refine_grid, 256, 0, st>>>(a);
-  mark(ev, 5, st);
-  k_finalize<<<(unsigned)a.B, 256, 0, st>>>(a, out_ids, out_d, status);
-  mark(ev, 6, st);
 }
 
 template <int NIT>
@@ -733,37 +521,72 @@ sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* rad
   return SOFA_OK;
 }
 
-sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
-                          hipStream_t st, hipEvent_t* ev) {
+static sofa_status front_fills(const SearchArgs& a, hipStream_t st) {
   const int64_t B = a.B;
   k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.best, kEmpty, B);
   k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.rescnt, 0u, B);
   k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.evmin, kEmpty, B);
   k_fill_u32<<<nblk(B * kHistBins, 256), 256, 0, st>>>(a.hist, 0u, B * kHistBins);
   k_fill_u32<<<1, 256, 0, st>>>(a.counter, 0u, kQueues);
-  // persistent grid: a multiple of the queue count so every queue has workers
-  unsigned grid = 256 * 6;
-  uint64_t total = (uint64_t)a.n_blocks * kSubPerBlock * (uint64_t)B;
-  if (total < grid) grid = (unsigned)(((total + kQueues - 1) / kQueues) * kQueues);
-  if (grid == 0) grid = kQueues;
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) {
+  SOFA_TRY(front_fills(a, st));
   const int R = (a.k + 16 <= 64) ? 1 : 2;
-  const int nit = a.n_pad / 64;
-#define SOFA_CASE(NI)                                                               \
-  case NI:                                                                          \
-    if (R == 1) launch_search_t<NI, 1>(a, out_ids, out_d, status, grid, st, ev);    \
-    else launch_search_t<NI, 2>(a, out_ids, out_d, status, grid, st, ev);           \
+  switch (a.n_pad / 64) {
+#define SOFA_CASE(NI)                                              \
+  case NI:                                                         \
+    if (R == 1) launch_front_t<NI, 1>(a, st, ev);                  \
+    else launch_front_t<NI, 2>(a, st, ev);                         \
     break;
-  switch (nit) {
     SOFA_CASE(1)
     SOFA_CASE(2)
     SOFA_CASE(4)
     SOFA_CASE(8)
     SOFA_CASE(16)
+#undef SOFA_CASE
     default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
   }
-#undef SOFA_CASE
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
+}
+
+sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                            hipStream_t st, hipEvent_t* ev) {
+  mark(ev, 5, st);
+  k_finalize<<<(unsigned)a.B, 256, 0, st>>>(a, out_ids, out_d, status);
+  mark(ev, 6, st);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                          hipStream_t st, hipEvent_t* ev) {
+  SOFA_TRY(launch_front(a, st, ev));
+  // persistent grid: a multiple of the queue count so every queue has workers
+  unsigned grid = 256 * 6;
+  uint64_t total = (uint64_t)a.n_blocks * kSubPerBlock * (uint64_t)a.B;
+  if (total < grid) grid = (unsigned)(((total + kQueues - 1) / kQueues) * kQueues);
+  if (grid == 0) grid = kQueues;
+  const int R = (a.k + 16 <= 64) ? 1 : 2;
+  switch (a.n_pad / 64) {
+#define SOFA_CASE(NI)                                              \
+  case NI:                                                         \
+    if (R == 1) k_refine<NI, 1><<<grid, 256, 0, st>>>(a);          \
+    else k_refine<NI, 2><<<grid, 256, 0, st>>>(a);                 \
+    break;
+    SOFA_CASE(1)
+    SOFA_CASE(2)
+    SOFA_CASE(4)
+    SOFA_CASE(8)
+    SOFA_CASE(16)
+#undef SOFA_CASE
+    default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
+  }
+  SOFA_HIP(hipGetLastError());
+  return launch_finalize(a, out_ids, out_d, status, st, ev);
 }
 
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,

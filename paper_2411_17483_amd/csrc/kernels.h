@@ -18,6 +18,23 @@ sofa_status launch_project(const float* X, int64_t m, int n, int64_t ldx, const 
                            int n_pad, float* out, int ld_out, const float* beta32, int l,
                            uint8_t* words, double* norm2, unsigned* bad, hipStream_t st);
 
+// Sort key of a word (used by the build and by the query routing): the
+// symbols are scaled to 8 bits and their bits interleaved most significant
+// first.  Scheme 0 gives word positions 0-3 eight bits each, 4-7 four bits,
+// 8-15 two bits (positions are in decreasing-variance order, so the leaves
+// split first where the Fourier values spread most); scheme 1 gives every
+// position its top four bits.
+__host__ __device__ inline uint64_t sfa_key(const uint32_t (&s8)[16], int scheme) {
+  uint64_t key = 0;
+  for (int b = 7; b >= 0; b--) {
+    for (int j = 0; j < 16; j++) {
+      int nbits = scheme == 1 ? 4 : (j < 4 ? 8 : (j < 8 ? 4 : 2));
+      if (b >= 8 - nbits) key = (key << 1) | ((s8[j] >> b) & 1u);
+    }
+  }
+  return key;
+}
+
 // Index layout (k_build.hip): sort by the interleaved key, permute, envelopes.
 sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_in,
                           const double* norm2_in, hipStream_t st);

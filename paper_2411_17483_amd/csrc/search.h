@@ -29,6 +29,7 @@ struct SearchArgs {
   uint64_t* evmin;       // B smallest candidate key evicted from a list or dropped
   uint32_t* hist;        // B x 256 counts of flushed candidate distances
   float* hbase;          // B histogram range [0, hbase) (the bound after the seed)
+  const uint32_t* cevmin;  // nullable: B smallest lower bound of a dropped BF16 candidate
   unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
   // factors derived from the FP32 error bounds
   float lb_f, band_f, upd_f, abandon_f;
@@ -38,9 +39,13 @@ struct SearchArgs {
 sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* radius,
                            const sofa_bins& bins, float* pool, double* qnorm2, unsigned* bad,
                            hipStream_t st);
-// ev (nullable): 6 events recorded around the stages (see sofa_knn_stats)
+// ev (nullable): 6 events recorded around the stages (see sofa_knn_stats).
+// launch_search = launch_front + the SFA refinement + launch_finalize.
 sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                           hipStream_t st, hipEvent_t* ev);
+sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev);
+sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
+                            hipStream_t st, hipEvent_t* ev);
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,

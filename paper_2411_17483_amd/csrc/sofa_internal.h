@@ -81,7 +81,7 @@ struct sofa_index {
   const sofa_bins* bins_ref = nullptr;  // not owned; copied below
   sofa_bins bins;                       // private copy (device tables included)
   int64_t N = 0;
-  int32_t n = 0, n_pad = 0, L = 256;
+  int32_t n = 0, n_pad = 0, L = 256, key_scheme = 0;
   int64_t n_leaves = 0, n_blocks = 0;
   double eta_x = 0;            // |c32 - c| bound for every data row
   double max_norm = 0;
@@ -95,6 +95,7 @@ struct sofa_index {
   int has_bf16 = 0;
   sofa::DevBuf xb;             // BF16 copy, MFMA-tile order
   sofa::DevBuf xb_meta;        // per row: ||x||^2 (rd), r_x (ru), ||xhat|| (ru) as float4
+  sofa::DevBuf xb_leafmeta;    // per leaf: max ||xhat||, max r_x, max ||x||^2
   sofa_workspace* own_ws = nullptr;
   int64_t device_bytes() const;
 };

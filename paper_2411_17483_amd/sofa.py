@@ -23,6 +23,7 @@ EXPORTED = [
     "sofa_transform", "sofa_bins_eta_per_norm", "sofa_build", "sofa_index_get_info",
     "sofa_index_export", "sofa_index_free", "sofa_workspace_create", "sofa_workspace_bytes_for",
     "sofa_workspace_free", "sofa_knn", "sofa_knn_get_stats", "sofa_lower_bounds",
+    "sofa_bf16_lower_bounds",
 ]
 
 
@@ -37,7 +38,7 @@ class BinParams(ctypes.Structure):
 
 
 class BuildParams(ctypes.Structure):
-    _fields_ = [("leaf_size", _i32), ("precision", _i32)]
+    _fields_ = [("leaf_size", _i32), ("precision", _i32), ("key_scheme", _i32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -95,6 +96,7 @@ def load():
     L.sofa_knn.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(KnnParams), _vp, _vp, _vp]
     L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
     L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+    L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
     _lib = L
     return L
 
@@ -206,12 +208,12 @@ class Workspace:
 class Index:
     """A built index (sofa_build) and exact k-NN queries (sofa_knn)."""
 
-    def __init__(self, bins, X, leaf_size=256, precision=0):
+    def __init__(self, bins, X, leaf_size=256, precision=0, key_scheme=0):
         import torch
         L = load()
         N, n = X.shape
         h = _vp()
-        p = BuildParams(leaf_size, precision)
+        p = BuildParams(leaf_size, precision, key_scheme)
         _check(L.sofa_build(bins._h, _dev(X, torch.float32), N, n, ctypes.byref(p), _stream(),
                             ctypes.byref(h)))
         self._h = h
@@ -267,6 +269,15 @@ class Index:
                                         None if T is None else _dev(T),
                                         None if LB is None else _dev(LB), _stream()))
         return T, LB
+
+    def bf16_lower_bounds(self, Q):
+        """B x N batched-distance lower bounds (leaf order) from the BF16 MFMA kernel."""
+        import torch
+        B = Q.shape[0]
+        N = self.info()["N"]
+        LB = torch.empty((B, N), dtype=torch.float32, device=Q.device)
+        _check(load().sofa_bf16_lower_bounds(self._h, _dev(Q, torch.float32), B, _dev(LB), _stream()))
+        return LB
 
     def __del__(self):
         if _lib is not None and getattr(self, "_h", None) and self._h.value:

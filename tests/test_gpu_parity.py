@@ -87,7 +87,7 @@ def test_index_layout_properties(gpu_lib):
     N, n, L = 10000 + 37, 128, 128
     X = synth.collection(N, n, "mix", seed=9)
     bins = _bins(gpu_lib, X, 2000)
-    ix = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L, key_scheme=1)
     W, ids, env, keys = (t.cpu().numpy() for t in ix.export())
     info = ix.info()
     assert info["n_leaves"] == (N + L - 1) // L
@@ -110,6 +110,18 @@ def test_index_layout_properties(gpu_lib):
         blk = W[leaf * L:(leaf + 1) * L]
         assert np.array_equal(env[leaf, :16], blk.min(axis=0))
         assert np.array_equal(env[leaf, 16:], blk.max(axis=0))
+    # default scheme: 8 bits for positions 0-3, 4 for 4-7, 2 for 8-15
+    ix0 = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    W0l, ids0, _, keys0 = (t.cpu().numpy() for t in ix0.export())
+    nb = [8] * 4 + [4] * 4 + [2] * 8
+    s8 = W0l.astype(np.uint64)
+    k = np.zeros(N, dtype=np.uint64)
+    for b in range(7, -1, -1):
+        for j in range(16):
+            if b >= 8 - nb[j]:
+                k = (k << np.uint64(1)) | ((s8[:, j] >> np.uint64(b)) & np.uint64(1))
+    assert np.array_equal(keys0.view(np.uint64), k)
+    assert np.all(keys0.view(np.uint64)[1:] >= keys0.view(np.uint64)[:-1])
 
 
 @pytest.mark.parametrize("binning", [0, 1])
@@ -304,3 +316,106 @@ def test_errors_are_reported(gpu_lib):
     with pytest.raises(gpu_lib.SofaError) as e:
         ix.knn(_t(X[:4]), 1, ws=ws)
     assert e.value.status == gpu_lib.SOFA_ENOMEM
+
+
+# --------------------------------------------------------------------------- #
+# BF16 batched-distance prune
+def _bf16_index(gpu_lib, X, m=2000, L=256):
+    bins = _bins(gpu_lib, X, m)
+    return bins, gpu_lib.Index(bins, _t(X), leaf_size=L, precision=1)
+
+
+def test_bf16_lower_bounds_never_exceed_distance(gpu_lib):
+    """The MFMA bound is below the FP64 distance on every pair, including
+    near-duplicates, rows far from unit scale and values on BF16 ties."""
+    N, n, B = 4096 + 17, 256, 40
+    X = synth.collection(N, n, "mix", seed=201)
+    rng = np.random.default_rng(5)
+    X[10] *= np.float32(300.0)                       # large magnitude
+    X[11] *= np.float32(1e-3)                        # small magnitude
+    X[12] = (np.round(X[12] * 128) / 128 + 2.0 ** -9).astype(np.float32)  # BF16 ties
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=202)
+    Q[0] = X[7]                                                  # exact copy
+    Q[1] = X[8] + np.float32(1e-4) * rng.standard_normal(n).astype(np.float32)  # near copy
+    Q[2] = X[10] * np.float32(1.0001)                            # near the large row
+    Q[3] = X[12]
+    Q[4] = X[11]
+    bins, ix = _bf16_index(gpu_lib, X)
+    LB = ix.bf16_lower_bounds(_t(Q)).cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    ids = ids.cpu().numpy()
+    Xd = X.astype(np.float64)[ids]
+    rel = []
+    for b in range(B):
+        d2 = np.sum((Xd - Q[b].astype(np.float64)) ** 2, axis=1)
+        assert np.all(LB[b] <= d2 * (1 + 1e-12) + 1e-30), (b, float(np.max(LB[b] - d2)))
+        rel.append((d2 - LB[b]) / np.maximum(d2, 1.0))
+    # useful on typical pairs (the leaf holding the scaled row is loose by design:
+    # its bound uses the leaf's largest BF16 residual)
+    assert np.median(np.concatenate(rel)) < 0.02
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_bf16_knn_matches_oracle(gpu_lib, k):
+    N, n, B = 30000 + 11, 256, 48
+    X = synth.collection(N, n, "mix", seed=211)
+    X[1000] = X[20]
+    X[29000] = X[20]
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=212)
+    Q[0] = X[20]
+    Q[1] = synth.collection(1, n, "hf", seed=4321)[0]
+    bins, ix = _bf16_index(gpu_lib, X)
+    ids, d = ix.knn(_t(Q), k, prune=1)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    st = ix.stats()
+    assert st["series_bf16_checked"] > 0
+    assert st["overflow_fallbacks"] == 0
+
+
+def test_bf16_knn_radius_and_capacity_paths(gpu_lib):
+    N, n, B, k = 40000, 256, 40, 10
+    X = synth.collection(N, n, "mix", seed=221)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=222)
+    bins, ix = _bf16_index(gpu_lib, X, L=512)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    kth = np.sqrt(ref_d2[:, -1]).astype(np.float32)
+    for radius in (None, np.full(B, 1e-3, np.float32), np.full(B, 1e3, np.float32),
+                   kth * np.float32(1.0005), kth * np.float32(0.999)):
+        ids, d = ix.knn(_t(Q), k, prune=1, radius=None if radius is None else _t(radius))
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    ids, d = ix.knn(_t(Q), k, prune=1, radius=_t(kth * np.float32(1.0005)))
+    tight = ix.stats()
+    ids, d = ix.knn(_t(Q), k, prune=1)
+    loose = ix.stats()
+    assert tight["radius_fallbacks"] == 0
+    assert tight["series_refined"] <= loose["series_refined"]
+    ids, d = ix.knn(_t(Q), k, prune=1, candidate_capacity=8)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    assert ix.stats()["overflow_fallbacks"] > 0
+
+
+def test_bf16_small_n_and_ragged(gpu_lib):
+    for n, N in ((64, 9000 + 7), (128, 7000 + 3)):
+        X = synth.collection(N, n, "mix", seed=231 + n)
+        Q, _ = synth.queries(X, 20, sigma=0.1, seed=232)
+        bins = _bins(gpu_lib, X, 2000, pool=min(16, n // 2 - 1))
+        ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=1)
+        for k in (1, 9):
+            ids, d = ix.knn(_t(Q), k, prune=1)
+            ref_ids, ref_d2 = oracle.knn(X, Q, k)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
+def test_bf16_argument_errors(gpu_lib):
+    X = synth.collection(3000, 256, "rw", seed=241)
+    bins = _bins(gpu_lib, X, 1000)
+    plain = gpu_lib.Index(bins, _t(X))
+    with pytest.raises(gpu_lib.SofaError):
+        plain.knn(_t(X[:2]), 1, prune=1)
+    with pytest.raises(gpu_lib.SofaError):
+        gpu_lib.Index(bins, _t(X), leaf_size=64, precision=1)
+    X5 = synth.collection(3000, 512, "rw", seed=242)
+    b5 = _bins(gpu_lib, X5, 1000)
+    with pytest.raises(gpu_lib.SofaError):
+        gpu_lib.Index(b5, _t(X5), precision=1)
