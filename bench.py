@@ -4,13 +4,16 @@
 Workload: 10,000,000 series x 256 FP32, half random walks and half
 high-frequency series (8 sinusoids + noise), z-normalised; SFA with l = 16,
 alpha = 256, equi-depth bins learned on a 1% stride sample; leaves of 256
-rows; a batch of 1,000 noisy-copy queries (sigma 0.1).  One step is one
-sofa_knn call over the whole batch at k = 10 (the timed metric); k = 1 and
-batch-1 latency (p50/p99) are measured beside it.
+rows; a batch of 1,000 noisy-copy queries (sigma 0.1).
 
-Prints one JSON line.  `value` is queries per second of the step with the
-inputs resident in HBM.  `roofline` describes the dominant kernel (the
-refinement kernel) from its live HIP-event duration; `cpu_baseline` times the
+One step is one sofa_knn call over the whole batch at k = 10 on the headline
+path; every path (plain SFA search, BF16 prune, ...) is also timed at k = 10
+and k = 1 with the same steps, and the headline path's batch-1 latency
+(p50/p99) is measured.  All paths return the same (exact) neighbours.
+
+Prints one JSON line.  `value` is queries per second of the headline step
+with the inputs resident in HBM.  `roofline` describes the headline path's
+dominant kernel from its live HIP-event duration; `cpu_baseline` times the
 FP64 oracle brute force on a bounded sample of the same queries.
 """
 import argparse
@@ -25,8 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published dense FP32 vector peak
-PEAK_HBM = 8.0e12             # B/s
+PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published FP32 vector peak
+PEAK_BF16_MFMA = 2.5e15       # FLOP/s, MI355X published dense BF16 matrix peak
 
 
 def log(*a):
@@ -46,6 +49,8 @@ def main():
     ap.add_argument("--latency-queries", type=int, default=200)
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline path at k (for profiling runs)")
     ap.add_argument("--seed", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -71,58 +76,86 @@ def main():
     bins = sofa.Bins.learn(Xd, max(1, N // 100))
     t_bins = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ix = sofa.Index(bins, Xd, leaf_size=args.leaf)
+    ix = sofa.Index(bins, Xd, leaf_size=args.leaf, precision=1)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del Xd
     torch.cuda.empty_cache()
     log(f"bins {t_bins:.2f}s build {t_build:.2f}s")
 
-    def run_steps(kk, steps, warmup):
+    paths = {"plain": dict(prune=0), "bf16": dict(prune=1)}
+    headline = "bf16"
+
+    def run_steps(kk, kw, steps, warmup):
         for _ in range(warmup):
-            ix.knn(Qd, kk)
+            ix.knn(Qd, kk, **kw)
         torch.cuda.synchronize()
-        refine, stats = [], []
+        stats, ids = [], None
         t0 = time.perf_counter()
         for _ in range(steps):
-            ids, d = ix.knn(Qd, kk)
-            st = ix.stats()
-            refine.append(st["ms_refine"])
-            stats.append(st)
+            ids, d = ix.knn(Qd, kk, **kw)
+            stats.append(ix.stats())
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, refine, stats, ids
+        return (time.perf_counter() - t0) / steps, stats, ids
 
-    sec, refine_ms, stats, ids10 = run_steps(k, args.steps, args.warmup)
-    log(f"k={k}: {sec * 1e3:.2f} ms/step, refine {np.mean(refine_ms):.2f} ms")
-    sec1, refine1, stats1, _ = run_steps(1, max(1, args.steps // 2), 1)
-    log(f"k=1: {sec1 * 1e3:.2f} ms/step")
+    results, ids_by_path = {}, {}
+    for name, kw in paths.items():
+        if args.headline_only and name != headline:
+            continue
+        res = {}
+        for kk in ((k,) if args.headline_only else (k, 1)):
+            sec, stats, ids = run_steps(kk, kw, args.steps, args.warmup)
+            st = stats[-1]
+            res[f"k{kk}"] = {
+                "queries_per_s": B / sec, "ms_per_step": sec * 1e3,
+                "stages_ms": {s: float(np.mean([x[s] for x in stats])) for s in
+                              ("ms_prepare", "ms_leaf", "ms_seed", "ms_refine", "ms_finalize",
+                               "ms_bf16_tiles", "ms_bf16_refine")},
+                "counters": {s: st[s] for s in ("leaves_total", "leaves_visited", "series_lb_checked",
+                                                 "series_refined", "series_bf16_checked",
+                                                 "radius_fallbacks", "overflow_fallbacks")},
+            }
+            if kk == k:
+                ids_by_path[name] = ids.cpu().numpy()
+            log(f"{name} k={kk}: {sec * 1e3:.2f} ms/step ({B / sec:.0f} q/s)")
+        results[name] = res
+    agree = all(np.array_equal(v, ids_by_path[headline]) for v in ids_by_path.values())
 
-    # batch-1 latency
+    # batch-1 latency of the headline path
+    kw = paths[headline]
     lat = []
     for i in range(min(args.latency_queries, B)):
         q = Qd[i:i + 1]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ix.knn(q, k)
+        ix.knn(q, k, **kw)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.zeros(1)
 
-    # dominant kernel: refinement; algorithmic work per launch from its counters
-    st = stats[-1]
-    words, rows = st["series_lb_checked"], st["series_refined"]
-    leaves = st["leaves_visited"]
-    flops = 16.0 * words + 3.0 * n * rows
-    bytes_alg = 16.0 * words + 4.0 * n * rows + 32.0 * leaves
-    r_ms = float(np.mean(refine_ms))
-    achieved = flops / (r_ms * 1e-3)
-    roofline = {
-        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-        "kernel": "k_refine", "ms_per_launch": r_ms,
-        "work_per_launch": {"flop": flops, "words_checked": words, "rows_refined": rows,
-                            "leaves_visited": leaves, "bytes_if_uncached": bytes_alg},
-    }
+    h = results[headline][f"k{k}"]
+    cnt, stg = h["counters"], h["stages_ms"]
+    if headline == "plain":
+        words, rows, leaves = cnt["series_lb_checked"], cnt["series_refined"], cnt["leaves_visited"]
+        flops = 16.0 * words + 3.0 * n * rows
+        ms = stg["ms_refine"]
+        ach = flops / (ms * 1e-3)
+        roofline = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VECTOR, "traffic": None,
+                    "kernel": "k_refine", "ms_per_launch": ms,
+                    "work_per_launch": {"flop": flops, "words_checked": words, "rows_refined": rows}}
+    else:
+        # algorithmic work: 2n flop for every (query, row) pair whose leaf
+        # survived the envelope bound
+        pairs = cnt["leaves_visited"] * args.leaf
+        flops = 2.0 * n * pairs
+        ms = stg["ms_bf16_tiles"]
+        ach = flops / (ms * 1e-3)
+        roofline = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA, "traffic": None,
+                    "kernel": "k_bf16_tiles", "ms_per_launch": ms,
+                    "work_per_launch": {"flop": flops, "pairs_needed": pairs,
+                                        "pairs_computed": cnt["series_bf16_checked"]}}
 
     cpu = None
     parity = None
@@ -136,27 +169,24 @@ def main():
         cpu = {"value": m / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
                "sample": f"first {m} of the {B} queries, k={k}, FP64 brute force over all "
                          f"{N} rows ({dt:.1f} s)"}
-        got = ids10[:m].cpu().numpy()
+        got = ids_by_path[headline][:m]
         parity = f"{int(np.sum(np.all(got == ref_ids, axis=1)))}/{m} queries with ids identical to the oracle"
         log(parity)
 
     out = {
-        "metric": "exact k-NN queries/s @10M x 256 (plain GPU path; learned-radius + BF16 not yet built)",
-        "value": B / sec, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "metric": "exact k-NN queries/s @10M x 256 (BF16-prune path; learned radius not yet built)",
+        "value": h["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
         "config": {"workload": f"{N} x {n} FP32 mix (even rows random walk, odd rows 8-sinusoid "
                                f"high-frequency), {B} noisy-copy queries (sigma 0.1), k={k}, "
-                               f"l=16 alpha=256 equi-depth, 1% sample, leaf {args.leaf}, plain path",
-                   "N": N, "n": n, "batch": B, "k": k, "leaf_size": args.leaf, "path": "plain"},
+                               f"l=16 alpha=256 equi-depth, 1% sample, leaf {args.leaf}",
+                   "N": N, "n": n, "batch": B, "k": k, "leaf_size": args.leaf, "path": headline},
         "roofline": roofline, "cpu_baseline": cpu,
-        "k1_queries_per_s": B / sec1, "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)),
-                                                           "p99": float(np.percentile(lat, 99)),
-                                                           "k": k, "queries": int(lat.size)},
+        "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                              "k": k, "queries": int(len(lat)), "path": headline},
+        "paths": results, "paths_ids_identical": agree,
         "parity_sample": parity,
-        "stages_ms": {s: st[s] for s in ("ms_prepare", "ms_leaf", "ms_seed", "ms_refine", "ms_finalize")},
-        "counters": {s: st[s] for s in ("leaves_total", "leaves_visited", "series_lb_checked",
-                                         "series_refined", "radius_fallbacks", "overflow_fallbacks")},
         "build_s": {"bins": t_bins, "index": t_build},
     }
     print(json.dumps(out), flush=True)

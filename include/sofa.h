@@ -215,6 +215,14 @@ typedef struct {
    * projection, tables), envelope bounds (both passes), seed, refinement,
    * final FP64 ranking */
   double ms_prepare, ms_leaf, ms_seed, ms_refine, ms_finalize;
+  /* with the BF16 prune, the refinement stage splits into the MFMA tile
+   * kernel(s) and the exact refinement of their candidates */
+  double ms_bf16_tiles, ms_bf16_refine;
+  /* why queries took the exhaustive pass: a candidate inside the final band
+   * was evicted or dropped; a BF16 candidate was dropped; the final band
+   * held more rows than the ranking buffer.  max_candidates: the largest
+   * BF16 candidate count of one query in one pass. */
+  int64_t overflow_evicted, overflow_bf16_drop, overflow_band, max_candidates;
 } sofa_knn_stats;
 
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,

@@ -333,7 +333,7 @@ struct sofa_workspace {
   DevBuf exh;
   std::mutex mu;
   sofa_knn_stats stats{};
-  hipEvent_t ev[7] = {};
+  hipEvent_t ev[16] = {};
   bool ev_ok = false;
   ~sofa_workspace() {
     if (ev_ok)
@@ -389,7 +389,9 @@ constexpr int kBf16Cap = 32768;  // BF16 candidates per query and pass
 int bf16_cap(const sofa_knn_params* p) {
   return (p && p->candidate_capacity > 0) ? p->candidate_capacity : kBf16Cap;
 }
-constexpr int kSampleStride = 32;  // no-radius BF16 search: every 32nd chunk first
+// no-radius BF16 search: chunk samples of stride 1024, then 32, then the
+// rest, each pass pruning with the bound the previous passes established
+constexpr int kSample0 = 1024, kSample1 = 32;
 
 Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
   size_t sz[W_END];
@@ -480,6 +482,7 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
   stats.ms_total = ms;
   ws->stats = stats;
   return s;
@@ -542,6 +545,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
   const bool bf = p && p->prune == 1;
+  int bf_passes = 0;
   if (!bf) {
     SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
   } else {
@@ -567,12 +571,17 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_bf16_queries(a, b, st));
     const int64_t n_chunks = (ix->N + 255) / 256;
     if (p->d_radius) {
-      SOFA_TRY(launch_bf16_pass(a, b, 0, 1, n_chunks, 0, st));
+      SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, st, ev ? ev + 7 : nullptr));
+      bf_passes = 1;
     } else {
-      // a systematic sample of chunks first gives a tight bound for the rest
-      const int64_t n1 = (n_chunks + kSampleStride - 1) / kSampleStride;
-      SOFA_TRY(launch_bf16_pass(a, b, 0, kSampleStride, n1, 0, st));
-      SOFA_TRY(launch_bf16_pass(a, b, 0, 0, n_chunks - n1, kSampleStride, st));
+      const int64_t n0 = (n_chunks + kSample0 - 1) / kSample0;
+      const int64_t n01 = (n_chunks + kSample1 - 1) / kSample1;
+      // multiples of 1024; multiples of 32 that are not multiples of 1024; the rest
+      SOFA_TRY(launch_bf16_pass(a, b, kSample0, 0, 1, n0, 0, st, ev ? ev + 7 : nullptr));
+      SOFA_TRY(launch_bf16_pass(a, b, kSample1, 0, 0, n01 - n0, kSample0 / kSample1, st,
+                                ev ? ev + 10 : nullptr));
+      SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 0, n_chunks - n01, kSample1, st, ev ? ev + 13 : nullptr));
+      bf_passes = 3;
     }
     SOFA_TRY(launch_finalize(a, d_ids, d_d, status, st, ev));
   }
@@ -594,6 +603,14 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.ms_seed = t[2];
     stats.ms_refine = t[4];
     stats.ms_finalize = t[5];
+    for (int ps = 0; ps < bf_passes; ps++) {
+      float tt = 0, tc = 0;
+      (void)hipEventElapsedTime(&tt, ev[7 + 3 * ps], ev[8 + 3 * ps]);
+      (void)hipEventElapsedTime(&tc, ev[8 + 3 * ps], ev[9 + 3 * ps]);
+      stats.ms_bf16_tiles += tt;
+      stats.ms_bf16_refine += tc;
+    }
+    (void)hipGetLastError();  // timer queries must not leave an error behind
   }
   stats.queries += B;
   stats.leaves_total += B * ix->n_leaves;
@@ -601,6 +618,12 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   stats.series_lb_checked += (int64_t)hstats[1];
   stats.series_refined += (int64_t)hstats[2];
   stats.series_bf16_checked += (int64_t)hstats[3];
+  stats.max_candidates = std::max<int64_t>(stats.max_candidates, (int64_t)hstats[4]);
+  for (int64_t q = 0; q < B; q++) {
+    if (hst[q] == 2) stats.overflow_evicted++;
+    if (hst[q] == 4) stats.overflow_bf16_drop++;
+    if (hst[q] == 5) stats.overflow_band++;
+  }
   std::vector<int64_t> redo;
   for (int64_t q = 0; q < B; q++) {
     int st_q = hst[q];
@@ -651,6 +674,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.series_refined += s2.series_refined;
     stats.series_bf16_checked += s2.series_bf16_checked;
     stats.overflow_fallbacks += s2.overflow_fallbacks;
+    stats.overflow_evicted += s2.overflow_evicted;
+    stats.overflow_bf16_drop += s2.overflow_bf16_drop;
+    stats.overflow_band += s2.overflow_band;
   }
   return SOFA_OK;
 }

@@ -24,6 +24,7 @@ struct Bf16Args {
   uint32_t* counter;
   int64_t chunk_first, chunk_stride, n_items;  // 256-row chunks of this pass
   int skip;                 // > 0: the pass enumerates the chunks that are not multiples of skip
+  int64_t chunk_mult;       // chunk = chunk_mult * (enumerated index)
   float* dump;              // inspection only: B x N lower bounds of every pair (no pruning)
 };
 
@@ -31,7 +32,10 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
                               uint4* xb, float4* meta, float4* leafmeta, hipStream_t st);
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
-sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t first, int64_t stride,
-                             int64_t n_items, int skip, hipStream_t st);
+// ev (nullable): events recorded before the tile kernel, between it and the
+// candidate refinement, and after
+sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
+                             int64_t stride, int64_t n_items, int skip, hipStream_t st,
+                             hipEvent_t* ev);
 
 }  // namespace sofa

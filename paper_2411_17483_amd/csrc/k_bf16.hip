@@ -217,8 +217,9 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     __syncthreads();
     if ((int64_t)it >= b.n_items) break;
     // skip > 0: enumerate the chunks that are not multiples of skip
-    const int64_t chunk = b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
-                                     : (int64_t)it * b.chunk_stride + b.chunk_first;
+    const int64_t chunk =
+        b.chunk_mult * (b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
+                                   : (int64_t)it * b.chunk_stride + b.chunk_first);
     const int64_t c0 = chunk * 256;
     const int64_t leaf = c0 / a.L;
     const int64_t blk = leaf / kLeavesPerItem;
@@ -345,6 +346,7 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const uint32_t cnt_all = b.ccnt[q];
   const uint32_t cnt = cnt_all < (uint32_t)b.cap ? cnt_all : (uint32_t)b.cap;
+  if (z == 0 && threadIdx.x == 0 && a.stats) atomicMax(a.stats + 4, (unsigned long long)cnt_all);
   if ((uint32_t)(z * 4 + wave) * 64 >= cnt) return;
   float4 qr[NIT];
   load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
@@ -441,6 +443,7 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st) {
   b.dump = d_lb;
   b.skip = 0;
+  b.chunk_mult = 1;
   b.chunk_first = 0;
   b.chunk_stride = 1;
   b.n_items = (a.N + 255) / 256;
@@ -457,23 +460,32 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   return SOFA_OK;
 }
 
-sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t first, int64_t stride,
-                             int64_t n_items, int skip, hipStream_t st) {
+sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
+                             int64_t stride, int64_t n_items, int skip, hipStream_t st,
+                             hipEvent_t* ev) {
+  b.chunk_mult = mult;
   b.chunk_first = first;
   b.chunk_stride = stride;
   b.n_items = n_items;
   b.skip = skip;
-  if (n_items <= 0) return SOFA_OK;
+  if (n_items <= 0) {
+    // keep the pass's timers valid (zero length)
+    if (ev)
+      for (int i = 0; i < 3; i++) (void)hipEventRecord(ev[i], st);
+    return SOFA_OK;
+  }
   SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
   SOFA_TRY(launch_fill_u32(b.ccnt, 0u, a.B, st));
   unsigned grid = 256 * 2;
   if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
+  if (ev) (void)hipEventRecord(ev[0], st);
   switch (a.n_pad / 16) {
     case 4: k_bf16_tiles<4><<<grid, 256, 0, st>>>(a, b); break;
     case 8: k_bf16_tiles<8><<<grid, 256, 0, st>>>(a, b); break;
     case 16: k_bf16_tiles<16><<<grid, 256, 0, st>>>(a, b); break;
     default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256 (padded %d)", a.n_pad);
   }
+  if (ev) (void)hipEventRecord(ev[1], st);
   dim3 gr((unsigned)a.B, kCandSplit);
   const int R = (a.k + 16 <= 64) ? 1 : 2;
 #define SOFA_RC(NI)                                                     \
@@ -488,6 +500,7 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t first, int
     default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
   }
 #undef SOFA_RC
+  if (ev) (void)hipEventRecord(ev[2], st);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }

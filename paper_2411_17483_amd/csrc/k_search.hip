@@ -318,10 +318,12 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
   const float band = __uint_as_float(a.U[q]) * a.band_f;
   // exact unless a key inside the final band was ever evicted or dropped
   const uint64_t ev = a.evmin[q];
-  bool ovf = ev != kEmpty && key_d(ev) <= band;
+  // overflow reasons: 2 an evicted or dropped candidate lies in the final
+  // band, 4 a BF16 candidate was dropped, 5 the band holds more than kSMax rows
+  int ovf = (ev != kEmpty && key_d(ev) <= band) ? 2 : 0;
   if (a.cevmin && a.cevmin[q] != 0xFFFFFFFFu &&
       __uint_as_float(a.cevmin[q]) <= __uint_as_float(a.U[q]) * a.lb_f)
-    ovf = true;
+    ovf = 4;
   const uint32_t lim = cnt < (uint32_t)a.cap ? cnt : (uint32_t)a.cap;
   for (uint32_t i = t; i < lim; i += 256) {
     uint64_t key = a.res[(int64_t)q * a.cap + i];
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
   __syncthreads();
   const uint32_t s = scount;
   if (ovf || s > kSMax) {
-    if (t == 0) status[q] = 2;
+    if (t == 0) status[q] = ovf ? ovf : 5;
     return;
   }
   const float* qrow = a.Qp + (int64_t)q * a.n_pad;

@@ -59,7 +59,9 @@ class KnnStats(ctypes.Structure):
                 ("overflow_fallbacks", _i64), ("ms_total", ctypes.c_double),
                 ("ms_prepare", ctypes.c_double), ("ms_leaf", ctypes.c_double),
                 ("ms_seed", ctypes.c_double), ("ms_refine", ctypes.c_double),
-                ("ms_finalize", ctypes.c_double)]
+                ("ms_finalize", ctypes.c_double), ("ms_bf16_tiles", ctypes.c_double),
+                ("ms_bf16_refine", ctypes.c_double), ("overflow_evicted", _i64),
+                ("overflow_bf16_drop", _i64), ("overflow_band", _i64), ("max_candidates", _i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
