@@ -43,6 +43,12 @@ typedef enum {
 /* Thread-local message describing the last non-OK status of this thread. */
 const char* sofa_last_error(void);
 
+/* Opaque handles (defined with their entry points below). */
+typedef struct sofa_bins sofa_bins;
+typedef struct sofa_index sofa_index;
+typedef struct sofa_workspace sofa_workspace;
+typedef struct sofa_radius sofa_radius;
+
 /* ------------------------------------------------------------------------ */
 /* Learned SFA quantisation (Section IV-C; Algorithm 1, MCB).
  *
@@ -54,8 +60,6 @@ const char* sofa_last_error(void);
  * per kept value: equi-depth beta(a) = v_(floor(a*m/alpha)) of the sorted
  * sample, or equi-width beta(a) = min + a*(max-min)/alpha.  Bins are
  * half-open [beta(a-1), beta(a)); the outer bins are open to -inf / +inf. */
-typedef struct sofa_bins sofa_bins;
-
 typedef struct {
   int32_t l;       /* kept values per word, 1..16 (default 16) */
   int32_t alpha;   /* symbols per value, 1..256 (default 256) */
@@ -111,8 +115,6 @@ double sofa_bins_eta_per_norm(const sofa_bins* bins);
  * smallest and largest symbol of each word position (its envelope).  It
  * keeps its own permuted copy of the rows, so d_series may be freed after
  * the call returns. */
-typedef struct sofa_index sofa_index;
-
 typedef struct {
   int32_t leaf_size; /* rows per leaf, a multiple of 64 in [64, 4096] (default 256) */
   int32_t precision; /* bit 0: keep a BF16 copy for the batched-distance prune */
@@ -163,8 +165,6 @@ void sofa_index_free(sofa_index* index);
  * A workspace holds the per-batch scratch memory.  Create one per concurrent
  * stream; sofa_knn returns SOFA_ENOMEM when a batch does not fit its byte
  * limit (the serving layer treats that as "not admitted"). */
-typedef struct sofa_workspace sofa_workspace;
-
 /* max_bytes = 0: no limit (grows on demand). */
 sofa_status sofa_workspace_create(int64_t max_bytes, sofa_workspace** out);
 /* Bytes a batch of B queries with k needs on index (no allocation). */
@@ -181,6 +181,10 @@ typedef struct {
    * pass already prunes.  A query for which fewer than k results lie within
    * its radius is searched again without it, so results stay exact. */
   const float* d_radius;
+  /* Nullable learned-radius model (its k must equal k): when set and
+   * d_radius is NULL, the radii come from the model applied to the queries'
+   * Fourier pool values, computed inside the call. */
+  const sofa_radius* radius_model;
   /* 0 (default): seed the bound with the exact distances of the leaf with
    * the smallest envelope bound (the approximate search of Section IV-A);
    * 1: skip that seed. */
@@ -235,6 +239,76 @@ sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index
  *  d_tables (nullable) B x 16 x 256 FP32;  d_lb (nullable) B x N FP32. */
 sofa_status sofa_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
                               float* d_tables, float* d_lb, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned radius.  A small network predicts ln(d_k), the logarithm of a
+ * query's k-th nearest-neighbour distance, from the query's Fourier pool
+ * values; sofa_knn seeds its best-so-far bound with the predicted radius so
+ * the first pass already prunes, and searches a query again without the
+ * radius when fewer than k results fall inside it (results stay exact).
+ *
+ * Network: y = W3 g(W2 g(W1 xs + b1) + b2) + b3 with xs the standardised
+ * input ((x - mu) / sd per feature), g(z) = z Phi(z) (exact GELU).  Weights
+ * W1 [H1][D], W2 [H2][H1], W3 [H2] are kept in FP32 (master) and used
+ * rounded to BF16 (round to nearest even); biases stay FP32; all sums
+ * accumulate in FP32.  Training minimises the mean squared error to ln(d_k)
+ * with Adam (Kingma & Ba 2015, bias-corrected) on the FP32 master; gradients
+ * are taken at the BF16-rounded weights.  Parameters are one flat FP32
+ * vector: W1, b1, W2, b2, W3, b3 (74,497 values for D=32, H1=H2=256). */
+typedef struct {
+  int32_t in_dim;   /* D: features = the 2*pool Fourier pool values (default 32) */
+  int32_t hidden1;  /* H1 (default 256) */
+  int32_t hidden2;  /* H2 (default 256) */
+  int32_t k;        /* the k the model predicts d_k for */
+  float lr, beta1, beta2, eps;  /* Adam (defaults 1e-3, 0.9, 0.999, 1e-8 when 0) */
+  uint64_t seed;    /* initial weights: Philox4x32-10 normal draws, He scaling */
+} sofa_radius_params;
+
+sofa_status sofa_radius_create(const sofa_radius_params* params, sofa_radius** out);
+void sofa_radius_free(sofa_radius* model);
+int64_t sofa_radius_num_params(const sofa_radius* model);
+
+/* Host copies in and out: params[num_params] FP32 master, mu[D], sd[D],
+ * margin (log units), step (Adam steps taken).  Any pointer may be NULL. */
+sofa_status sofa_radius_get(const sofa_radius* model, float* params, float* mu, float* sd,
+                            float* margin, int64_t* step);
+sofa_status sofa_radius_set(sofa_radius* model, const float* params, const float* mu,
+                            const float* sd, const float* margin, const int64_t* step);
+
+/* Feature standardisation from n training rows d_feat (n x D, device):
+ * mu = mean, sd = population standard deviation (1 where it is 0). */
+sofa_status sofa_radius_standardize(sofa_radius* model, const float* d_feat, int64_t n,
+                                    void* stream);
+
+/* Gradients of the loss mean_b (y_b - t_b)^2 over a batch (no update):
+ * d_grad[num_params] FP32, d_loss (nullable) the loss.  B <= 65536. */
+sofa_status sofa_radius_gradients(sofa_radius* model, const float* d_feat, const float* d_target,
+                                  int64_t B, float* d_grad, float* d_loss, void* stream);
+
+/* One training step: forward, backward and one Adam update. */
+sofa_status sofa_radius_train_step(sofa_radius* model, const float* d_feat,
+                                   const float* d_target, int64_t B, float* d_loss,
+                                   void* stream);
+
+/* Epochs of train steps over n rows in order, in batches of `batch`;
+ * h_epoch_loss[epochs] (nullable) receives the mean batch loss per epoch.
+ * Synchronous. */
+sofa_status sofa_radius_fit(sofa_radius* model, const float* d_feat, const float* d_target,
+                            int64_t n, int32_t epochs, int32_t batch, float* h_epoch_loss,
+                            void* stream);
+
+/* Predicted ln(d_k) (no margin), d_y[B]. */
+sofa_status sofa_radius_forward(const sofa_radius* model, const float* d_feat, int64_t B,
+                                float* d_y, void* stream);
+
+/* Margin = the given quantile of the residuals t - y over held-out rows;
+ * the radius is exp(y + margin).  Synchronous. */
+sofa_status sofa_radius_calibrate(sofa_radius* model, const float* d_feat, const float* d_target,
+                                  int64_t n, double quantile, void* stream);
+
+/* Radii exp(y + margin) for B feature rows. */
+sofa_status sofa_radius_predict(const sofa_radius* model, const float* d_feat, int64_t B,
+                                float* d_radius, void* stream);
 
 /* Batched-distance lower bounds for inspection (index built with the BF16
  * copy): for every (query, leaf-order row) pair the bound

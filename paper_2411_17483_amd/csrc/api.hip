@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "bf16.h"
+#include "mlp.h"
 
 namespace sofa {
 
@@ -382,7 +383,7 @@ struct Layout {
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
   W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
-  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_QB, W_QMETA, W_BCTR, W_END
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_QB, W_QMETA, W_BCTR, W_MLP, W_END
 };
 
 constexpr int kBf16Cap = 32768;  // BF16 candidates per query and pass
@@ -424,6 +425,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
   sz[W_QMETA] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_BCTR] = bf ? 64 : 0;
+  sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
   Layout L;
   size_t o = 0;
   for (int i = 0; i < W_END; i++) {
@@ -458,6 +460,13 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
     return set_error(SOFA_EINVAL, "k=%d outside [1, min(N, %d)]", k, kMaxK);
   if (B == 0) return SOFA_OK;
   if (!d_queries || !d_ids || !d_dists) return set_error(SOFA_EINVAL, "null array");
+  if (params && params->radius_model && !params->d_radius) {
+    const sofa_radius* m = params->radius_model;
+    if (m->k != k) return set_error(SOFA_EINVAL, "the radius model predicts k=%d, asked k=%d", m->k, k);
+    if (m->dims.D != 2 * ix->bins.pool)
+      return set_error(SOFA_EINVAL, "the radius model takes %d features, the index has %d pool values",
+                       m->dims.D, 2 * ix->bins.pool);
+  }
   if (params && params->prune != 0) {
     if (params->prune != 1) return set_error(SOFA_EINVAL, "prune must be 0 (off) or 1 (BF16)");
     if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
@@ -544,6 +553,11 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
+  const bool use_model = p && p->radius_model && !p->d_radius;
+  if (use_model)
+    SOFA_TRY(launch_model_radius(p->radius_model, (const float*)at(W_POOL), ix->bins.ncol_pool, B,
+                                 (float*)at(W_MLP), a.U0, st));
+  const bool has_radius = p && (p->d_radius || use_model);
   const bool bf = p && p->prune == 1;
   int bf_passes = 0;
   if (!bf) {
@@ -570,7 +584,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.counter = (uint32_t*)at(W_BCTR);
     SOFA_TRY(launch_bf16_queries(a, b, st));
     const int64_t n_chunks = (ix->N + 255) / 256;
-    if (p->d_radius) {
+    if (has_radius) {
       SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, st, ev ? ev + 7 : nullptr));
       bf_passes = 1;
     } else {

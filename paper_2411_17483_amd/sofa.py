@@ -23,7 +23,10 @@ EXPORTED = [
     "sofa_transform", "sofa_bins_eta_per_norm", "sofa_build", "sofa_index_get_info",
     "sofa_index_export", "sofa_index_free", "sofa_workspace_create", "sofa_workspace_bytes_for",
     "sofa_workspace_free", "sofa_knn", "sofa_knn_get_stats", "sofa_lower_bounds",
-    "sofa_bf16_lower_bounds",
+    "sofa_bf16_lower_bounds", "sofa_radius_create", "sofa_radius_free", "sofa_radius_num_params",
+    "sofa_radius_get", "sofa_radius_set", "sofa_radius_standardize", "sofa_radius_gradients",
+    "sofa_radius_train_step", "sofa_radius_fit", "sofa_radius_forward", "sofa_radius_calibrate",
+    "sofa_radius_predict",
 ]
 
 
@@ -48,8 +51,14 @@ class IndexInfo(ctypes.Structure):
 
 
 class KnnParams(ctypes.Structure):
-    _fields_ = [("prune", _i32), ("d_radius", _vp), ("no_seed_leaf", _i32), ("ws", _vp),
-                ("candidate_capacity", _i32)]
+    _fields_ = [("prune", _i32), ("d_radius", _vp), ("radius_model", _vp), ("no_seed_leaf", _i32),
+                ("ws", _vp), ("candidate_capacity", _i32)]
+
+
+class RadiusParams(ctypes.Structure):
+    _fields_ = [("in_dim", _i32), ("hidden1", _i32), ("hidden2", _i32), ("k", _i32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
 class KnnStats(ctypes.Structure):
@@ -99,6 +108,20 @@ def load():
     L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
     L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
     L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.sofa_radius_create.argtypes = [ctypes.POINTER(RadiusParams), ctypes.POINTER(_vp)]
+    L.sofa_radius_free.argtypes = [_vp]
+    L.sofa_radius_free.restype = None
+    L.sofa_radius_num_params.argtypes = [_vp]
+    L.sofa_radius_num_params.restype = _i64
+    L.sofa_radius_get.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.sofa_radius_set.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.sofa_radius_standardize.argtypes = [_vp, _vp, _i64, _vp]
+    L.sofa_radius_gradients.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    L.sofa_radius_train_step.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+    L.sofa_radius_fit.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+    L.sofa_radius_forward.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.sofa_radius_calibrate.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_double, _vp]
+    L.sofa_radius_predict.argtypes = [_vp, _vp, _i64, _vp, _vp]
     _lib = L
     return L
 
@@ -237,15 +260,16 @@ class Index:
         _check(load().sofa_index_export(self._h, _dev(W), _dev(ids), _dev(env), _dev(keys), _stream()))
         return W, ids, env, keys
 
-    def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0):
+    def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0,
+            model=None):
         """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors."""
         import torch
         B = Q.shape[0]
         ids = torch.empty((B, k), dtype=torch.int64, device=Q.device)
         d = torch.empty((B, k), dtype=torch.float32, device=Q.device)
         p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
-                      1 if no_seed_leaf else 0, None if ws is None else ws._h,
-                      int(candidate_capacity))
+                      None if model is None else model._h, 1 if no_seed_leaf else 0,
+                      None if ws is None else ws._h, int(candidate_capacity))
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
         return ids, d
@@ -284,4 +308,86 @@ class Index:
     def __del__(self):
         if _lib is not None and getattr(self, "_h", None) and self._h.value:
             _lib.sofa_index_free(self._h)
+            self._h = _vp()
+
+
+class RadiusModel:
+    """The learned-radius network (sofa_radius_*): predicts ln d_k from a
+    query's Fourier pool values; trained with the library's own kernels."""
+
+    def __init__(self, k, in_dim=32, hidden1=256, hidden2=256, lr=1e-3, seed=0):
+        h = _vp()
+        p = RadiusParams(in_dim, hidden1, hidden2, k, lr, 0.9, 0.999, 1e-8, seed)
+        _check(load().sofa_radius_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.k, self.in_dim = k, in_dim
+
+    @property
+    def num_params(self):
+        return load().sofa_radius_num_params(self._h)
+
+    def get(self):
+        P = self.num_params
+        params = np.zeros(P, dtype=np.float32)
+        mu = np.zeros(self.in_dim, dtype=np.float32)
+        sd = np.zeros(self.in_dim, dtype=np.float32)
+        margin = ctypes.c_float()
+        step = _i64()
+        _check(load().sofa_radius_get(self._h, params.ctypes.data, mu.ctypes.data, sd.ctypes.data,
+                                      ctypes.byref(margin), ctypes.byref(step)))
+        return {"params": params, "mu": mu, "sd": sd, "margin": margin.value, "step": step.value}
+
+    def set(self, params=None, mu=None, sd=None, margin=None, step=None):
+        def f32(a):
+            return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        params, mu, sd = f32(params), f32(mu), f32(sd)
+        mg = None if margin is None else ctypes.byref(ctypes.c_float(margin))
+        sp = None if step is None else ctypes.byref(_i64(step))
+        _check(load().sofa_radius_set(self._h, None if params is None else params.ctypes.data,
+                                      None if mu is None else mu.ctypes.data,
+                                      None if sd is None else sd.ctypes.data, mg, sp))
+
+    def standardize(self, feat):
+        _check(load().sofa_radius_standardize(self._h, _dev(feat), feat.shape[0], _stream()))
+
+    def gradients(self, feat, target):
+        import torch
+        g = torch.empty(self.num_params, dtype=torch.float32, device=feat.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _check(load().sofa_radius_gradients(self._h, _dev(feat), _dev(target), feat.shape[0], _dev(g),
+                                            _dev(loss), _stream()))
+        return g, loss
+
+    def train_step(self, feat, target):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _check(load().sofa_radius_train_step(self._h, _dev(feat), _dev(target), feat.shape[0],
+                                             _dev(loss), _stream()))
+        return loss
+
+    def fit(self, feat, target, epochs, batch):
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(load().sofa_radius_fit(self._h, _dev(feat), _dev(target), feat.shape[0], epochs, batch,
+                                      losses.ctypes.data, _stream()))
+        return losses
+
+    def forward(self, feat):
+        import torch
+        y = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        _check(load().sofa_radius_forward(self._h, _dev(feat), feat.shape[0], _dev(y), _stream()))
+        return y
+
+    def calibrate(self, feat, target, quantile):
+        _check(load().sofa_radius_calibrate(self._h, _dev(feat), _dev(target), feat.shape[0],
+                                            float(quantile), _stream()))
+
+    def predict(self, feat):
+        import torch
+        r = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        _check(load().sofa_radius_predict(self._h, _dev(feat), feat.shape[0], _dev(r), _stream()))
+        return r
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
+            _lib.sofa_radius_free(self._h)
             self._h = _vp()

@@ -419,3 +419,118 @@ def test_bf16_argument_errors(gpu_lib):
     b5 = _bins(gpu_lib, X5, 1000)
     with pytest.raises(gpu_lib.SofaError):
         gpu_lib.Index(b5, _t(X5), precision=1)
+
+
+# --------------------------------------------------------------------------- #
+# learned radius network
+def _mlp_params(seed, D=32, H1=256, H2=256):
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((H1, D)) * np.sqrt(2.0 / D)
+    b1 = rng.standard_normal(H1) * 0.1
+    W2 = rng.standard_normal((H2, H1)) * np.sqrt(2.0 / H1)
+    b2 = rng.standard_normal(H2) * 0.1
+    W3 = rng.standard_normal(H2) * np.sqrt(1.0 / H2)
+    b3 = 0.7
+    flat = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, [b3]]).astype(np.float32)
+    return flat
+
+
+def _unflat(flat, D=32, H1=256, H2=256, bf16=True):
+    f = flat.astype(np.float64)
+    o = 0
+    W1 = f[o:o + H1 * D].reshape(H1, D); o += H1 * D
+    b1 = f[o:o + H1]; o += H1
+    W2 = f[o:o + H2 * H1].reshape(H2, H1); o += H2 * H1
+    b2 = f[o:o + H2]; o += H2
+    W3 = f[o:o + H2]; o += H2
+    b3 = f[o]
+    if bf16:
+        W1, W2, W3 = oracle.to_bf16(W1), oracle.to_bf16(W2), oracle.to_bf16(W3)
+    return oracle.MLPParams(W1, b1, W2, b2, W3, b3)
+
+
+def _mlp_data(seed, B, D=32):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((B, D)).astype(np.float32)
+    t = (rng.standard_normal(B) * 0.5 + 1.0).astype(np.float32)
+    return x, t
+
+
+def test_mlp_forward_matches_oracle(gpu_lib):
+    flat = _mlp_params(1)
+    m = gpu_lib.RadiusModel(k=10)
+    m.set(params=flat, mu=np.zeros(32), sd=np.ones(32), margin=0.0)
+    x, _ = _mlp_data(2, 300)
+    y = m.forward(_t(x)).cpu().numpy().astype(np.float64)
+    ref = oracle.mlp_forward(_unflat(flat), x)
+    assert np.max(np.abs(y - ref) / (1 + np.abs(ref))) < 1e-4
+    # standardisation: (x - mu) / sd applied to the inputs
+    mu = np.linspace(-1, 1, 32).astype(np.float32)
+    sd = np.linspace(0.5, 2, 32).astype(np.float32)
+    m.set(mu=mu, sd=sd)
+    y2 = m.forward(_t(x)).cpu().numpy().astype(np.float64)
+    ref2 = oracle.mlp_forward(_unflat(flat), ((x - mu) / sd).astype(np.float32))
+    assert np.max(np.abs(y2 - ref2) / (1 + np.abs(ref2))) < 1e-4
+
+
+def test_mlp_gradients_match_oracle(gpu_lib):
+    flat = _mlp_params(3)
+    m = gpu_lib.RadiusModel(k=10)
+    m.set(params=flat, mu=np.zeros(32), sd=np.ones(32))
+    x, t = _mlp_data(4, 257)
+    g, loss = m.gradients(_t(x), _t(t))
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, rg = oracle.mlp_backward(_unflat(flat), x, t)
+    assert abs(float(loss.cpu()[0]) - ref_loss) <= 1e-4 * ref_loss
+    ref = np.concatenate([rg["W1"].ravel(), rg["b1"], rg["W2"].ravel(), rg["b2"], rg["W3"], rg["b3"]])
+    bounds = np.cumsum([0, 256 * 32, 256, 256 * 256, 256, 256, 1])
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        scale = np.max(np.abs(ref[a:b]))
+        assert np.max(np.abs(g[a:b] - ref[a:b])) <= 1e-3 * scale + 1e-9, (a, b)
+
+
+def test_mlp_adam_steps_match_oracle(gpu_lib):
+    flat = _mlp_params(5)
+    lr = 1e-3
+    m = gpu_lib.RadiusModel(k=1, lr=lr)
+    m.set(params=flat, mu=np.zeros(32), sd=np.ones(32))
+    p = flat.astype(np.float64).copy()
+    mom, vel = np.zeros_like(p), np.zeros_like(p)
+    for step in (1, 2):
+        x, t = _mlp_data(10 + step, 200)
+        m.train_step(_t(x), _t(t))
+        _, rg = oracle.mlp_backward(_unflat(p.astype(np.float32)), x, t)
+        g = np.concatenate([rg["W1"].ravel(), rg["b1"], rg["W2"].ravel(), rg["b2"], rg["W3"], rg["b3"]])
+        oracle.adam(p, g, mom, vel, step, lr=lr)
+        got = m.get()["params"].astype(np.float64)
+        assert m.get()["step"] == step
+        # elements whose gradient is clear of zero move exactly as the oracle's
+        clear = np.abs(g) > 1e-3 * np.max(np.abs(g))
+        assert np.max(np.abs(got - p)[clear]) <= 2e-6
+        assert np.mean(np.abs(got - p) <= 2.5 * lr) == 1.0
+
+
+def test_learned_radius_search_is_exact(gpu_lib):
+    import torch
+    N, n, k = 40000, 256, 10
+    X = synth.collection(N, n, "mix", seed=301)
+    bins, ix = _bf16_index(gpu_lib, X)
+    Qtr, _ = synth.queries(X, 3000, sigma=0.1, seed=302)
+    Qte, _ = synth.queries(X, 64, sigma=0.1, seed=303)
+    ids_tr, d_tr = ix.knn(_t(Qtr), k)                   # labels from the plain path
+    target = torch.log(d_tr[:, -1]).contiguous()
+    feat, _, _ = bins.transform(_t(Qtr), sel=False, words=False)
+    m = gpu_lib.RadiusModel(k=k, seed=7)
+    m.standardize(feat)
+    losses = m.fit(feat[:2500].contiguous(), target[:2500].contiguous(), epochs=30, batch=250)
+    assert losses[-1] < losses[0]
+    m.calibrate(feat[2500:].contiguous(), target[2500:].contiguous(), 0.99)
+    ref_ids, ref_d2 = oracle.knn(X, Qte, k)
+    for prune in (0, 1):
+        ids, d = ix.knn(_t(Qte), k, prune=prune, model=m)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    st = ix.stats()
+    assert st["radius_fallbacks"] <= 16
+    m1 = gpu_lib.RadiusModel(k=1)
+    with pytest.raises(gpu_lib.SofaError):
+        ix.knn(_t(Qte), k, model=m1)
