@@ -52,6 +52,10 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path at k (for profiling runs)")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--train-queries", type=int, default=1_000_000,
+                    help="noisy-copy training queries for the radius network")
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--quantile", type=float, default=0.999)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -83,10 +87,49 @@ def main():
     torch.cuda.empty_cache()
     log(f"bins {t_bins:.2f}s build {t_build:.2f}s")
 
-    paths = {"plain": dict(prune=0), "bf16": dict(prune=1)}
-    headline = "bf16"
+    # learned radius: one network per k, trained on the exact k-th distances
+    # of noisy-copy training queries (own seed).  The labels come from the
+    # BF16-prune search, which returns the same exact neighbours as the plain
+    # search (checked below on the benchmark batch) in a fraction of the time.
+    t0 = time.perf_counter()
+    ntr = args.train_queries
+    Qtr, _ = synth.queries(X, ntr, sigma=0.1, seed=args.seed + 2)
+    Qtr_d = torch.from_numpy(Qtr).to(dev)
+    feat, _, _ = bins.transform(Qtr_d, sel=False, words=False)
+    n_fit = ntr - min(10000, ntr // 10)
+    models, model_info = {}, {}
+    for kk in (k, 1):
+        lab = []
+        for i in range(0, ntr, 4096):
+            _, dd = ix.knn(Qtr_d[i:i + 4096].contiguous(), kk, prune=1)
+            lab.append(torch.log(dd[:, -1]))
+        target = torch.cat(lab).contiguous()
+        m = sofa.RadiusModel(k=kk, seed=11 + kk)
+        m.standardize(feat[:n_fit].contiguous())
+        losses = m.fit(feat[:n_fit].contiguous(), target[:n_fit].contiguous(), epochs=args.epochs,
+                       batch=1024)
+        m.calibrate(feat[n_fit:].contiguous(), target[n_fit:].contiguous(), args.quantile)
+        pred = m.forward(feat[n_fit:].contiguous())
+        resid = (target[n_fit:] - pred).cpu().numpy()
+        models[kk] = m
+        model_info[f"k{kk}"] = {"train_loss_first": float(losses[0]), "train_loss_last": float(losses[-1]),
+                                "heldout_rmse": float(np.sqrt(np.mean(resid ** 2))),
+                                "margin": m.get()["margin"]}
+        log(f"radius model k={kk}: loss {losses[0]:.4f} -> {losses[-1]:.4f}, held-out rmse "
+            f"{model_info[f'k{kk}']['heldout_rmse']:.4f}, margin {m.get()['margin']:.4f}")
+    t_train = time.perf_counter() - t0
+    del Qtr_d, feat
+    log(f"radius training {t_train:.1f}s")
+
+    paths = {"plain": dict(prune=0), "bf16": dict(prune=1),
+             "learned_bf16": dict(prune=1, model="learned", sampling=1),
+             "learned_bf16_1pass": dict(prune=1, model="learned", sampling=2)}
+    headline = "learned_bf16"
 
     def run_steps(kk, kw, steps, warmup):
+        kw = dict(kw)
+        if kw.get("model") == "learned":
+            kw["model"] = models[kk]
         for _ in range(warmup):
             ix.knn(Qd, kk, **kw)
         torch.cuda.synchronize()
@@ -122,7 +165,9 @@ def main():
     agree = all(np.array_equal(v, ids_by_path[headline]) for v in ids_by_path.values())
 
     # batch-1 latency of the headline path
-    kw = paths[headline]
+    kw = dict(paths[headline])
+    if kw.get("model") == "learned":
+        kw["model"] = models[k]
     lat = []
     for i in range(min(args.latency_queries, B)):
         q = Qd[i:i + 1]
@@ -174,7 +219,7 @@ def main():
         log(parity)
 
     out = {
-        "metric": "exact k-NN queries/s @10M x 256 (BF16-prune path; learned radius not yet built)",
+        "metric": "exact k-NN queries/s @10M x 256: learned-radius + BF16 vs plain GPU; p99 ms",
         "value": h["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
@@ -187,7 +232,11 @@ def main():
                               "k": k, "queries": int(len(lat)), "path": headline},
         "paths": results, "paths_ids_identical": agree,
         "parity_sample": parity,
-        "build_s": {"bins": t_bins, "index": t_build},
+        "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
+        "radius_models": model_info,
+        "speedup_vs_plain": {f"k{kk}": results[headline][f"k{kk}"]["queries_per_s"] /
+                             results["plain"][f"k{kk}"]["queries_per_s"]
+                             for kk in (k, 1) if "plain" in results and f"k{kk}" in results[headline]},
     }
     print(json.dumps(out), flush=True)
 

@@ -194,6 +194,11 @@ typedef struct {
    * smaller value only costs time: when in-band candidates are dropped the
    * query is finished by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
+  /* BF16 prune only: 0 (default) runs chunk samples of stride 1024 and 32
+   * before the remaining chunks when no radius is given (each pass prunes
+   * with the bound the earlier ones established) and one pass with a radius;
+   * 1 always runs the sampled passes; 2 always runs one pass. */
+  int32_t sampling;
 } sofa_knn_params;
 
 /* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 128).

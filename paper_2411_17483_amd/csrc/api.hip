@@ -375,15 +375,17 @@ int cap_for(int k, const sofa_knn_params* p) {
   return k <= 16 ? 32768 : 65536;
 }
 
-struct Layout {
-  size_t off[24];
-  size_t total;
-};
-
+// workspace regions of one batch
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
   W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
-  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_QB, W_QMETA, W_BCTR, W_MLP, W_END
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_BCTR, W_MLP,
+  W_END
+};
+
+struct Layout {
+  size_t off[W_END];  // one offset per region; total = the bytes of all regions
+  size_t total;
 };
 
 constexpr int kBf16Cap = 32768;  // BF16 candidates per query and pass
@@ -422,11 +424,14 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_QCNT] = bf ? (size_t)B * 4 : 0;
   sz[W_PERM] = bf ? (size_t)B * 4 : 0;
   sz[W_GMASK] = bf ? (size_t)ix->n_blocks * G * 8 : 0;
+  sz[W_SMASK] = bf ? (size_t)ix->n_blocks * G * kGroup * 8 : 0;
+  sz[W_SLOTC] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
   sz[W_QMETA] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_BCTR] = bf ? 64 : 0;
   sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
   Layout L;
+  static_assert(sizeof(L.off) / sizeof(L.off[0]) == W_END, "one offset per workspace region");
   size_t o = 0;
   for (int i = 0; i < W_END; i++) {
     L.off[i] = o;
@@ -469,6 +474,7 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
   }
   if (params && params->prune != 0) {
     if (params->prune != 1) return set_error(SOFA_EINVAL, "prune must be 0 (off) or 1 (BF16)");
+    if (params->sampling < 0 || params->sampling > 2) return set_error(SOFA_EINVAL, "sampling must be 0, 1 or 2");
     if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
   }
   sofa_workspace* ws = params ? params->ws : nullptr;
@@ -576,6 +582,8 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.perm = (int32_t*)at(W_PERM);
     b.qcount = (uint32_t*)at(W_QCNT);
     b.gmask = (uint64_t*)at(W_GMASK);
+    b.smask = (uint64_t*)at(W_SMASK);
+    b.slotc = (float4*)at(W_SLOTC);
     b.G = (int)((B + kGroup - 1) / kGroup);
     b.cand = (uint32_t*)at(W_CAND);
     b.ccnt = (uint32_t*)at(W_CCNT);
@@ -584,7 +592,8 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.counter = (uint32_t*)at(W_BCTR);
     SOFA_TRY(launch_bf16_queries(a, b, st));
     const int64_t n_chunks = (ix->N + 255) / 256;
-    if (has_radius) {
+    const int sampling = p->sampling;
+    if (sampling == 2 || (sampling == 0 && has_radius)) {
       SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, st, ev ? ev + 7 : nullptr));
       bf_passes = 1;
     } else {
@@ -672,6 +681,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     if (p) {
       p2.candidate_capacity = p->candidate_capacity;
       p2.prune = p->prune;
+      p2.sampling = p->sampling == 2 ? 0 : p->sampling;  // without a radius, sample first
     }
     sofa_knn_stats s2{};
     SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2));
@@ -753,7 +763,7 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   if (B > 65535) return set_error(SOFA_EINVAL, "B too large");
   hipStream_t st = S(stream);
   const int64_t G = (B + kGroup - 1) / kGroup;
-  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, perm, qb, qmeta, ctr, U, stats;
+  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, sm, sc, perm, qb, qmeta, ctr, U, stats;
   SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
   SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
   SOFA_TRY(qn.alloc((size_t)B * 8));
@@ -764,6 +774,8 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   SOFA_TRY(bad.alloc(4));
   SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8));
   SOFA_TRY(gm.alloc((size_t)ix->n_blocks * G * 8));
+  SOFA_TRY(sm.alloc((size_t)ix->n_blocks * G * kGroup * 8));
+  SOFA_TRY(sc.alloc((size_t)G * kGroup * 16));
   SOFA_TRY(perm.alloc((size_t)B * 4));
   SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2));
   SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16));
@@ -802,6 +814,8 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   b.perm = perm.as<int32_t>();
   b.qcount = u0.as<uint32_t>();  // scratch for the density sort
   b.gmask = gm.as<uint64_t>();
+  b.smask = sm.as<uint64_t>();
+  b.slotc = sc.as<float4>();
   b.G = (int)G;
   b.counter = ctr.as<uint32_t>();
   SOFA_TRY(launch_bf16_queries(a, b, st));

@@ -16,6 +16,8 @@ struct Bf16Args {
   int32_t* perm;            // sorted slot -> query
   uint32_t* qcount;         // surviving leaves per query
   uint64_t* gmask;          // n_blocks x G group survivor masks
+  uint64_t* smask;          // n_blocks x (64 G) survivor masks in sorted-slot order
+  float4* slotc;            // per slot and pass: bound terms (a, b, c) and the query id
   int G;                    // query groups
   uint32_t* cand;           // B x cap candidate rows
   uint32_t* ccnt;           // B

@@ -147,16 +147,46 @@ __global__ void k_qsort(const uint32_t* __restrict__ cnt, int B, int32_t* __rest
   perm[rank] = q;
 }
 
+// smask[blk][s]: the survivor mask of the query in sorted slot s (0 past B)
+__global__ void k_smask(const uint64_t* __restrict__ masks, int64_t n_blocks, int B, int Spad,
+                        const int32_t* __restrict__ perm, uint64_t* __restrict__ smask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_blocks * Spad) return;
+  int64_t b = i / Spad;
+  int s = (int)(i % Spad);
+  smask[i] = s < B ? masks[b * B + perm[s]] : 0ull;
+}
+
 // gmask[blk][g]: bit i set when leaf blk*64+i survives for some query of group g
-__global__ void k_gmask(const uint64_t* __restrict__ masks, int64_t n_blocks, int B,
-                        const int32_t* __restrict__ perm, int G, uint64_t* __restrict__ gmask) {
+__global__ void k_gmask(const uint64_t* __restrict__ smask, int64_t n_blocks, int G,
+                        uint64_t* __restrict__ gmask) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_blocks * G) return;
   int64_t b = i / G;
   int g = (int)(i % G);
   uint64_t m = 0;
-  for (int s = g * kGroup; s < (g + 1) * kGroup && s < B; s++) m |= masks[b * B + perm[s]];
+  const uint64_t* sm = smask + b * (int64_t)G * kGroup + (int64_t)g * kGroup;
+  for (int s = 0; s < kGroup; s++) m |= sm[s];
   gmask[i] = m;
+}
+
+// per slot, for the current pass: with t = |x|^2 - 2P, a row survives when
+//   t <= a + b * max|xh| + c * max r_x + 2^-20 * max|x|^2   (leaf maxima)
+// where a = U lb_f - |q|^2 (1 - 2^-20), b = 2 (g |qh| + r_q), c = 2 |q|; .w = query id
+__global__ void k_slotc(const float4* __restrict__ qmeta, const int32_t* __restrict__ perm, int B,
+                        int Spad, const uint32_t* __restrict__ U, float lb_f, float gam,
+                        float4* __restrict__ slotc) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= Spad) return;
+  float4 c = make_float4(-INFINITY, 0.0f, 0.0f, __int_as_float(-1));
+  if (s < B) {
+    const int q = perm[s];
+    const float4 qm = qmeta[s];
+    const float u = __uint_as_float(U[q]);
+    c = make_float4(u * lb_f - qm.x * (1.0f - 0x1p-20f), 2.0f * (gam * qm.z + qm.y), 2.0f * qm.w,
+                    __int_as_float(q));
+  }
+  slotc[s] = c;
 }
 
 // swizzled BF16 query fragments per sorted slot and the query bound terms
@@ -201,7 +231,15 @@ __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp
 
 // ----------------------------------------------------------------------------
 // tiles: one 256-row chunk per work item
-template <int KS>
+//
+// Per group, the two 32-query column blocks are taken one after the other
+// (32 accumulators live instead of 64; each BF16 query fragment is still read
+// from LDS once).  The usual fragment has no hit, so the epilogue first tests
+// a superset: for the 16 rows e of a lane's fragment,
+//   min_e fl(|x_e|^2 - 2 P_e) >= fl(min_e |x_e|^2 - 2 max_e P_e)
+// (rounding is monotone), and only when that value passes the per-query
+// threshold for some lane of the wave are the 16 pairs tested one by one.
+template <int KS, bool DUMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_bf16_tiles(SearchArgs a, Bf16Args b) {
   __shared__ __attribute__((aligned(16))) uint4 Bs[2 * KS * 64];
@@ -235,101 +273,117 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
         av[r][ks] = *reinterpret_cast<bf8v*>(&v);
       }
     {
+      // rows past N (zero in the copy) get a NaN |x|^2: no compare passes
       const int64_t row = c0 + threadIdx.x;
-      xn2s[threadIdx.x] = row < a.N ? b.meta[row].x : 0.0f;
+      xn2s[threadIdx.x] = row < a.N ? b.meta[row].x : __builtin_nanf("");
     }
     const float4 lmx = b.leafmeta[leaf];
-    for (int g = 0; g < b.G; g++) {
-      if (!((b.gmask[blk * b.G + g] >> bit) & 1ull)) continue;
-      __syncthreads();
-      const uint4* src = b.qb + (int64_t)(2 * g) * KS * 64;
-      for (int i = threadIdx.x; i < 2 * KS * 64; i += 256) Bs[i] = src[i];
-      // per-lane query terms for the two 32-query blocks of the group
-      float cq[2], oq[2];
-      int qo[2];
+    const float lead = lmx.z * 0x1p-20f;
+    __syncthreads();
+    // smallest |x|^2 over the 16 rows of this lane's fragment, per row block
+    float xmin[2];
 #pragma unroll
-      for (int cb = 0; cb < 2; cb++) {
-        const int s = g * kGroup + cb * 32 + (lane & 31);
-        qo[cb] = s < a.B ? b.perm[s] : -1;
-        const float4 qm = b.qmeta[s];
-        const float U = qo[cb] >= 0 ? __uint_as_float(__atomic_load_n(a.U + qo[cb], __ATOMIC_RELAXED)) : -1.0f;
-        // offset o: LB = t - o with t = |x|^2 - 2P
-        const float o = -qm.x + 2.0f * (gam * qm.z + qm.y) * lmx.x + 2.0f * qm.w * lmx.y +
-                        (qm.x + lmx.z) * 0x1p-20f;
-        cq[cb] = qo[cb] >= 0 ? U * a.lb_f + o : -INFINITY;
-        oq[cb] = o;
+    for (int r = 0; r < 2; r++) {
+      float m = INFINITY;  // NaN rows are skipped; all-NaN leaves +inf (a superset)
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const float v = xn2s[64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4)];
+        m = v < m ? v : m;
       }
-      __syncthreads();
-      f16v acc[2][2];
+      xmin[r] = m;
+    }
+    // the chunk's groups with work: one load per lane and a ballot per 64 groups
+    for (int w0 = 0; w0 < b.G; w0 += 64) {
+      const bool has = w0 + lane < b.G && ((b.gmask[blk * b.G + w0 + lane] >> bit) & 1ull);
+      uint64_t glist = __ballot(has);
+      while (glist) {
+        const int g = w0 + __builtin_ctzll(glist);
+        glist &= glist - 1;
+        __syncthreads();
+        const uint4* src = b.qb + (int64_t)(2 * g) * KS * 64;
+        for (int i = threadIdx.x; i < 2 * KS * 64; i += 256) Bs[i] = src[i];
+        __syncthreads();
+        st_pairs += 64 * 64;
+#pragma nounroll
+        for (int cb = 0; cb < 2; cb++) {
+          // this lane's query column: threshold cq on t = |x|^2 - 2P
+          const int s = g * kGroup + cb * 32 + (lane & 31);
+          const float4 c = b.slotc[s];
+          const int q = __float_as_int(c.w);
+          const float cq = c.x + c.y * lmx.x + c.z * lmx.y + lead;
+          const bool mbit = q >= 0 && ((b.smask[blk * (int64_t)b.G * kGroup + s] >> bit) & 1ull);
+          f16v acc[2];
 #pragma unroll
-      for (int r = 0; r < 2; r++)
+          for (int r = 0; r < 2; r++)
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++)
+            for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
 #pragma unroll
-          for (int e = 0; e < 16; e++) acc[r][cb][e] = 0.0f;
+          for (int ks = 0; ks < KS; ks++) {
+            uint4 u = Bs[(cb * KS + ks) * 64 + lane];
+            bf8v bq = *reinterpret_cast<bf8v*>(&u);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], bq, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], bq, acc[1], 0, 0, 0);
+          }
+          // D[i][j]: j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row)
+          if (DUMP) {
+            // inspection: the lower bound t - o of every pair
+            const float4 qm = b.qmeta[s];
+            const float o = -qm.x + 2.0f * (gam * qm.z + qm.y) * lmx.x + 2.0f * qm.w * lmx.y +
+                            (qm.x + lmx.z) * 0x1p-20f;
 #pragma unroll
-      for (int ks = 0; ks < KS; ks++) {
-        uint4 u0 = Bs[(0 * KS + ks) * 64 + lane];
-        uint4 u1 = Bs[(1 * KS + ks) * 64 + lane];
-        bf8v b0 = *reinterpret_cast<bf8v*>(&u0);
-        bf8v b1 = *reinterpret_cast<bf8v*>(&u1);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], b1, acc[1][1], 0, 0, 0);
-      }
-      st_pairs += 64 * 64;
-      // epilogue: D[i][j], j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row).
-      // Unrolled compares build a hit mask; the rare hits are appended in a
-      // loop that only needs the row index.
-      if (b.dump) {
-        // inspection: the lower bound of every pair, t - o
+            for (int r = 0; r < 2; r++)
 #pragma unroll
-        for (int r = 0; r < 2; r++)
+              for (int e = 0; e < 16; e++) {
+                const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+                const float t = fmaf(-2.0f, acc[r][e], xn2s[ri]);
+                if (c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + c0 + ri] = t - o;
+              }
+            continue;
+          }
+          bool any = false;
 #pragma unroll
-          for (int cb = 0; cb < 2; cb++)
+          for (int r = 0; r < 2; r++) {
+            float m = acc[r][0];
+#pragma unroll
+            for (int e = 1; e < 16; e++) m = fmaxf(m, acc[r][e]);
+            any |= fmaf(-2.0f, m, xmin[r]) <= cq;
+          }
+          if (!__ballot(mbit && any)) continue;
+          // rare: exact per-pair test and one append atomic per lane
+          uint32_t hits[2];
+#pragma unroll
+          for (int r = 0; r < 2; r++) {
+            uint32_t h = 0;
 #pragma unroll
             for (int e = 0; e < 16; e++) {
               const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-              const float t = fmaf(-2.0f, acc[r][cb][e], xn2s[ri]);
-              if (c0 + ri < a.N && qo[cb] >= 0) b.dump[(int64_t)qo[cb] * a.N + c0 + ri] = t - oq[cb];
+              h |= fmaf(-2.0f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
             }
-        continue;
+            hits[r] = h;
+          }
+          const uint32_t nh = mbit ? (uint32_t)(__popc(hits[0]) + __popc(hits[1])) : 0u;
+          if (nh) {
+            uint32_t slot = atomicAdd(b.ccnt + q, nh);
+            bool dropped = false;
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+              uint32_t h = hits[r];
+              while (h) {
+                const int e = __builtin_ctz(h);
+                h &= h - 1;
+                const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+                if (slot < (uint32_t)b.cap)
+                  b.cand[(int64_t)q * b.cap + slot] = (uint32_t)(c0 + ri);
+                else
+                  dropped = true;
+                slot++;
+              }
+            }
+            // a dropped candidate: the query is finished exhaustively
+            if (dropped && b.cevmin[q] != 0u) atomicMin(b.cevmin + q, 0u);
+          }
+        }
       }
-      uint32_t hits[2][2];
-#pragma unroll
-      for (int r = 0; r < 2; r++)
-#pragma unroll
-        for (int cb = 0; cb < 2; cb++) {
-          uint32_t h = 0;
-#pragma unroll
-          for (int e = 0; e < 16; e++) {
-            const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-            const float t = fmaf(-2.0f, acc[r][cb][e], xn2s[ri]);
-            h |= (t <= cq[cb]) ? (1u << e) : 0u;
-          }
-          hits[r][cb] = h;
-        }
-#pragma unroll
-      for (int r = 0; r < 2; r++)
-#pragma unroll
-        for (int cb = 0; cb < 2; cb++) {
-          uint32_t h = hits[r][cb];
-          while (h) {
-            const int e = __builtin_ctz(h);
-            h &= h - 1;
-            const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-            const int64_t row = c0 + ri;
-            const int q = qo[cb];
-            if (row < a.N && ((a.masks[blk * a.B + q] >> bit) & 1ull)) {
-              const uint32_t slot = atomicAdd(b.ccnt + q, 1u);
-              if (slot < (uint32_t)b.cap)
-                b.cand[(int64_t)q * b.cap + slot] = (uint32_t)row;
-              else
-                atomicMin(b.cevmin + q, 0u);  // a dropped candidate: finish exhaustively
-            }
-          }
-        }
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
@@ -357,8 +411,9 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
   unsigned long long st_refined = 0;
   for (uint32_t ch = z * 4 + wave; ch * 64 < cnt; ch += 4 * kCandSplit) {
     const uint32_t idx = ch * 64 + lane;
-    const bool valid = idx < cnt;
-    const uint32_t pos = valid ? b.cand[(int64_t)q * b.cap + idx] : 0u;
+    uint32_t pos = idx < cnt ? b.cand[(int64_t)q * b.cap + idx] : 0u;
+    const bool valid = idx < cnt && (int64_t)pos < a.N;
+    pos = valid ? pos : 0u;
     uint64_t bal = __ballot(valid);
     st_refined += (unsigned long long)__popcll(bal);
     const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
@@ -430,12 +485,21 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   const int B = a.B;
   k_qcount<<<nblk(B, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, b.qcount);
   k_qsort<<<nblk(B, 256), 256, 0, st>>>(b.qcount, B, b.perm);
-  k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, b.perm, b.G, b.gmask);
   const int Spad = b.G * kGroup;
+  k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
+  k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(b.smask, a.n_blocks, b.G, b.gmask);
   const int KS = a.n_pad / 16;
   k_qprep_bf16<<<nblk((int64_t)(Spad / 32) * KS * 64, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
                                                                            b.perm, b.qb);
   k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+static sofa_status launch_slotc(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+  const int Spad = b.G * kGroup;
+  const float gam = (float)(a.n_pad + 16) * 0x1p-23f;
+  k_slotc<<<nblk(Spad, 256), 256, 0, st>>>(b.qmeta, b.perm, a.B, Spad, a.U, a.lb_f, gam, b.slotc);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -448,12 +512,13 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   b.chunk_stride = 1;
   b.n_items = (a.N + 255) / 256;
   SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
+  SOFA_TRY(launch_slotc(a, b, st));
   unsigned grid = 256 * 2;
   if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
   switch (a.n_pad / 16) {
-    case 4: k_bf16_tiles<4><<<grid, 256, 0, st>>>(a, b); break;
-    case 8: k_bf16_tiles<8><<<grid, 256, 0, st>>>(a, b); break;
-    case 16: k_bf16_tiles<16><<<grid, 256, 0, st>>>(a, b); break;
+    case 4: k_bf16_tiles<4, true><<<grid, 256, 0, st>>>(a, b); break;
+    case 8: k_bf16_tiles<8, true><<<grid, 256, 0, st>>>(a, b); break;
+    case 16: k_bf16_tiles<16, true><<<grid, 256, 0, st>>>(a, b); break;
     default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
   }
   SOFA_HIP(hipGetLastError());
@@ -476,13 +541,15 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
   }
   SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
   SOFA_TRY(launch_fill_u32(b.ccnt, 0u, a.B, st));
+  // the bounds U of this pass (earlier passes tighten them)
+  SOFA_TRY(launch_slotc(a, b, st));
   unsigned grid = 256 * 2;
   if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
   if (ev) (void)hipEventRecord(ev[0], st);
   switch (a.n_pad / 16) {
-    case 4: k_bf16_tiles<4><<<grid, 256, 0, st>>>(a, b); break;
-    case 8: k_bf16_tiles<8><<<grid, 256, 0, st>>>(a, b); break;
-    case 16: k_bf16_tiles<16><<<grid, 256, 0, st>>>(a, b); break;
+    case 4: k_bf16_tiles<4, false><<<grid, 256, 0, st>>>(a, b); break;
+    case 8: k_bf16_tiles<8, false><<<grid, 256, 0, st>>>(a, b); break;
+    case 16: k_bf16_tiles<16, false><<<grid, 256, 0, st>>>(a, b); break;
     default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256 (padded %d)", a.n_pad);
   }
   if (ev) (void)hipEventRecord(ev[1], st);

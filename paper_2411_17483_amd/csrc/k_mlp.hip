@@ -72,6 +72,10 @@ __global__ void k_mlp_round(const float* __restrict__ p, float* __restrict__ wr,
 //  1: C = acc + bias[n] (pre-activation), H = g(C)
 //  2: C = acc * g'(Zin[m][n])
 constexpr int kTm = 64, kTn = 64, kTk = 16;
+constexpr int kSplitK = 8;  // batch slices of the weight-gradient products
+
+// With gridDim.z = S > 1 (epilogue 0 only), slice z sums k in
+// [z*ceil(K/S), (z+1)*ceil(K/S)) and writes C + z*M*ldc.
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A,
@@ -83,21 +87,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   __shared__ float Bs[kTk][kTn + 1];
   const int t = threadIdx.x, tm = t / 16, tn = t % 16;
   const int m0 = blockIdx.y * kTm, n0 = blockIdx.x * kTn;
+  const int per = (K + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int kb = (int)blockIdx.z * per, ke = kb + per < K ? kb + per : K;
+  C += (int64_t)blockIdx.z * M * ldc;
   float acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) acc[i][j] = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += kTk) {
+  for (int k0 = kb; k0 < ke; k0 += kTk) {
     for (int e = t; e < kTk * kTm; e += 256) {
       int kk = e / kTm, mm = e % kTm;
       int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
+      As[kk][mm] = (m < M && k < ke) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
     }
     for (int e = t; e < kTk * kTn; e += 256) {
       int kk = e / kTn, nn = e % kTn;
       int n = n0 + nn, k = k0 + kk;
-      Bs[kk][nn] = (n < N && k < K) ? Bm[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
+      Bs[kk][nn] = (n < N && k < ke) ? Bm[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -140,6 +147,24 @@ static void gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak, 
                  const float* Zin, hipStream_t st) {
   dim3 g((unsigned)((N + kTn - 1) / kTn), (unsigned)((M + kTm - 1) / kTm));
   k_gemm<EPI><<<g, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, Zin);
+}
+
+// split-K: partial products over K slices into P[s][M][N], then a fixed-order sum
+__global__ void k_sum_slices(const float* __restrict__ P, int S, int64_t MN, float* __restrict__ C) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  float s = 0.0f;
+  for (int j = 0; j < S; j++) s += P[(int64_t)j * MN + i];
+  C[i] = s;
+}
+
+// C[M][N] = sum over the batch (K) of A(m,k) B(k,n): S slices in one launch
+// into part[S][M][N], then their sum in slice order
+static void gemm_splitk(int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
+                        int64_t sbk, int64_t sbn, float* C, float* part, int S, hipStream_t st) {
+  dim3 g((unsigned)((N + kTn - 1) / kTn), (unsigned)((M + kTm - 1) / kTm), (unsigned)S);
+  k_gemm<0><<<g, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, part, N, nullptr, nullptr, nullptr);
+  k_sum_slices<<<nblk((int64_t)M * N, 256), 256, 0, st>>>(part, S, (int64_t)M * N, C);
 }
 
 // xs[b][d] = (x[b*ld + d] - mu[d]) / sd[d]
@@ -296,6 +321,10 @@ __global__ void k_radius(const float* __restrict__ y, int64_t B, float margin, f
 // host side
 static sofa_status ensure_act(sofa_radius* m, int64_t B) {
   const MlpDims& d = m->dims;
+  if (!m->part.p) {
+    const int64_t mn = std::max<int64_t>((int64_t)d.H2 * d.H1, (int64_t)d.H1 * d.D);
+    SOFA_TRY(m->part.alloc((size_t)kSplitK * mn * 4));
+  }
   if (B <= m->act_rows) return SOFA_OK;
   const size_t per = (size_t)d.D + 2 * d.H1 + 3 * d.H2 + 4;
   SOFA_TRY(m->act.alloc(per * (size_t)B * 4));
@@ -332,7 +361,7 @@ void mlp_forward(const sofa_radius* m, const float* feat, int64_t ld, int64_t B,
 }
 
 static void mlp_backward(const sofa_radius* m, const float* target, int64_t B, const MlpAct& a,
-                         float* grad, float* loss, hipStream_t st) {
+                         float* grad, float* loss, float* part, hipStream_t st) {
   const MlpDims& d = m->dims;
   const float* wr = m->wr.as<float>();
   k_loss<<<1, 256, 0, st>>>(a.y, target, B, a.dy, loss);
@@ -341,11 +370,11 @@ static void mlp_backward(const sofa_radius* m, const float* target, int64_t B, c
   k_sum<<<1, 64, 0, st>>>(a.dy, B, grad + d.ob3);
   // second layer: dz2, dW2 = dz2^T h1, db2
   k_dz2<<<nblk(B * d.H2, 256), 256, 0, st>>>(a.dy, wr + d.oW3, a.z2, B, d.H2, a.dz2);
-  gemm<0>(d.H2, d.H1, (int)B, a.dz2, 1, d.H2, a.h1, d.H1, 1, grad + d.oW2, d.H1, nullptr, nullptr, nullptr, st);
+  gemm_splitk(d.H2, d.H1, (int)B, a.dz2, 1, d.H2, a.h1, d.H1, 1, grad + d.oW2, part, kSplitK, st);
   k_colsum<<<nblk(d.H2, 256), 256, 0, st>>>(a.dz2, B, d.H2, nullptr, grad + d.ob2);
   // first layer: dz1 = (dz2 W2) * g'(z1) (written over h1), dW1 = dz1^T xs, db1
   gemm<2>((int)B, d.H1, d.H2, a.dz2, d.H2, 1, wr + d.oW2, d.H1, 1, a.h1, d.H1, nullptr, nullptr, a.z1, st);
-  gemm<0>(d.H1, d.D, (int)B, a.h1, 1, d.H1, a.xs, d.D, 1, grad + d.oW1, d.D, nullptr, nullptr, nullptr, st);
+  gemm_splitk(d.H1, d.D, (int)B, a.h1, 1, d.H1, a.xs, d.D, 1, grad + d.oW1, part, kSplitK, st);
   k_colsum<<<nblk(d.H1, 256), 256, 0, st>>>(a.h1, B, d.H1, nullptr, grad + d.ob1);
 }
 
@@ -451,7 +480,7 @@ static sofa_status grads_impl(sofa_radius* m, const float* feat, const float* ta
   SOFA_TRY(ensure_act(m, B));
   MlpAct a = act_views(m->act.as<float>(), m->dims, B);
   mlp_forward(m, feat, m->dims.D, B, a, st);
-  mlp_backward(m, target, B, a, grad, loss, st);
+  mlp_backward(m, target, B, a, grad, loss, m->part.as<float>(), st);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }

@@ -43,5 +43,6 @@ struct sofa_radius {
   int64_t step = 0;
   sofa::DevBuf p, wr, g, m1, m2, mu, sd, loss;  // master, rounded copy, gradient, Adam moments
   sofa::DevBuf act;                             // activations of the largest training batch
+  sofa::DevBuf part;                            // split-K partial weight gradients
   int64_t act_rows = 0;
 };

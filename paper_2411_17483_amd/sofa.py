@@ -52,7 +52,7 @@ class IndexInfo(ctypes.Structure):
 
 class KnnParams(ctypes.Structure):
     _fields_ = [("prune", _i32), ("d_radius", _vp), ("radius_model", _vp), ("no_seed_leaf", _i32),
-                ("ws", _vp), ("candidate_capacity", _i32)]
+                ("ws", _vp), ("candidate_capacity", _i32), ("sampling", _i32)]
 
 
 class RadiusParams(ctypes.Structure):
@@ -261,7 +261,7 @@ class Index:
         return W, ids, env, keys
 
     def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0,
-            model=None):
+            model=None, sampling=0):
         """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors."""
         import torch
         B = Q.shape[0]
@@ -269,7 +269,7 @@ class Index:
         d = torch.empty((B, k), dtype=torch.float32, device=Q.device)
         p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
                       None if model is None else model._h, 1 if no_seed_leaf else 0,
-                      None if ws is None else ws._h, int(candidate_capacity))
+                      None if ws is None else ws._h, int(candidate_capacity), int(sampling))
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
         return ids, d
