@@ -27,6 +27,7 @@ namespace sofa {
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));  // plain 16-byte vector (no struct copies)
 
 static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
 
@@ -125,26 +126,46 @@ __global__ __launch_bounds__(256) void k_bf16_leafmeta(const float4* __restrict_
 // ----------------------------------------------------------------------------
 // query side
 // surviving leaves per query
+// surviving leaves per query; grid (query blocks, slices of the leaf blocks),
+// cnt cleared beforehand
 __global__ void k_qcount(const uint64_t* __restrict__ masks, int64_t n_blocks, int B,
                          uint32_t* __restrict__ cnt) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= B) return;
   uint32_t c = 0;
-  for (int64_t b = 0; b < n_blocks; b++) c += __popcll(masks[b * B + q]);
-  cnt[q] = c;
+  for (int64_t b = blockIdx.y; b < n_blocks; b += gridDim.y) c += __popcll(masks[b * B + q]);
+  if (c) atomicAdd(cnt + q, c);
 }
 
-// order: more surviving leaves first, then lower query index
-__global__ void k_qsort(const uint32_t* __restrict__ cnt, int B, int32_t* __restrict__ perm) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= B) return;
-  uint32_t c = cnt[q];
-  int rank = 0;
-  for (int o = 0; o < B; o++) {
-    uint32_t d = cnt[o];
-    rank += (d > c || (d == c && o < q)) ? 1 : 0;
+// Query order for the groups: density class first (0 when at least half of
+// the leaves survive, c when the surviving fraction is in [2^-(c+1), 2^-c),
+// at most 7), then the query's best leaf, so that a group gathers queries
+// whose surviving leaves overlap; ties by query index.
+__device__ __forceinline__ uint64_t qorder_key(uint32_t cnt, uint64_t best, int64_t n_leaves) {
+  int cls = 7;
+  if (cnt > 0) {
+    cls = 0;
+    while (cls < 7 && ((uint64_t)cnt << (cls + 1)) < (uint64_t)n_leaves) cls++;
   }
-  perm[rank] = q;
+  const uint64_t leaf = best == kEmpty ? 0xFFFFFFFFFFFFull : (uint64_t)(uint32_t)best;
+  return ((uint64_t)cls << 48) | leaf;
+}
+
+// rank sort, one wave per query (best may be null: order by density only)
+__global__ __launch_bounds__(256) void k_qsort(const uint32_t* __restrict__ cnt,
+                                               const uint64_t* __restrict__ best, int B,
+                                               int64_t n_leaves, int32_t* __restrict__ perm) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= B) return;
+  const uint64_t kq = qorder_key(cnt[q], best ? best[q] : kEmpty, n_leaves);
+  int rank = 0;
+  for (int o = lane; o < B; o += 64) {
+    const uint64_t ko = qorder_key(cnt[o], best ? best[o] : kEmpty, n_leaves);
+    rank += (ko < kq || (ko == kq && o < q)) ? 1 : 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) rank += __shfl_xor(rank, off);
+  if (lane == 0) perm[rank] = q;
 }
 
 // smask[blk][s]: the survivor mask of the query in sorted slot s (0 past B)
@@ -233,20 +254,171 @@ __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp
 // tiles: one 256-row chunk per work item
 //
 // Per group, the two 32-query column blocks are taken one after the other
-// (32 accumulators live instead of 64; each BF16 query fragment is still read
-// from LDS once).  The usual fragment has no hit, so the epilogue first tests
-// a superset: for the 16 rows e of a lane's fragment,
+// (32 accumulators live instead of 64; each BF16 query fragment is read from
+// LDS once).  The usual fragment has no hit, so the epilogue first tests a
+// superset: for the 16 rows e of a lane's fragment,
 //   min_e fl(|x_e|^2 - 2 P_e) >= fl(min_e |x_e|^2 - 2 max_e P_e)
 // (rounding is monotone), and only when that value passes the per-query
 // threshold for some lane of the wave are the 16 pairs tested one by one.
+//
+// The groups of a chunk alternate between two LDS buffers: while the matrix
+// cores read one, the next group's fragments stream into the other by LDS
+// DMA (global_load_lds_dwordx4, no registers), and the next group's
+// per-column terms are loaded into registers.  The two buffers are separate
+// arrays so that reads of one never wait on the DMA into the other.
+
+// per-column terms of a group's two 32-query blocks (query slot order)
+struct ColTerms {
+  float4 c0, c1;    // bound terms (a, b, c) and query id
+  uint64_t m0, m1;  // survivor masks of the chunk's leaf block
+};
+
+__device__ __forceinline__ void load_cols(const Bf16Args& b, int64_t blk, int g, int lane,
+                                          ColTerms& t) {
+  const int s = g * kGroup + (lane & 31);
+  t.c0 = b.slotc[s];
+  t.c1 = b.slotc[s + 32];
+  t.m0 = b.smask[blk * (int64_t)b.G * kGroup + s];
+  t.m1 = b.smask[blk * (int64_t)b.G * kGroup + s + 32];
+}
+
+// DMA of group g's 2 KS wave-sized (1 KB) fragment pieces into dst, KS/2 per wave
+template <int KS>
+__device__ __forceinline__ void stage_group(const Bf16Args& b, int g, int wave, int lane, u4v* dst) {
+  const u4v* src = reinterpret_cast<const u4v*>(b.qb) + (int64_t)(2 * g) * KS * 64;
+#pragma unroll
+  for (int i = 0; i < KS / 2; i++) {
+    const int piece = wave + 4 * i;
+    __builtin_amdgcn_global_load_lds((const void*)(src + piece * 64 + lane),
+                                     (__attribute__((address_space(3))) void*)(dst + piece * 64),
+                                     16, 0, 0);
+  }
+}
+
+// chunk-level state shared by the group steps
+struct ChunkState {
+  int64_t c0, blk;
+  int bit, wave, lane;
+  float4 lmx;
+  float lead, gam;
+  float xmin[2];
+};
+
+// one group: thresholds from the terms loaded one group ahead, prefetch of
+// the next group (gn; the current one again when gn < 0, unused), the two
+// column blocks, and the barrier that publishes the next buffer
+template <int KS, bool DUMP>
+__device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& b,
+                                           const ChunkState& cs, const bf8v (&av)[2][KS],
+                                           const float* xn2s, int g, int gn, ColTerms& cols,
+                                           const u4v* cur, u4v* nxt,
+                                           unsigned long long& st_pairs) {
+  const int wave = cs.wave, lane = cs.lane;
+  const int q0 = __float_as_int(cols.c0.w), q1 = __float_as_int(cols.c1.w);
+  const float cq0 = cols.c0.x + cols.c0.y * cs.lmx.x + cols.c0.z * cs.lmx.y + cs.lead;
+  const float cq1 = cols.c1.x + cols.c1.y * cs.lmx.x + cols.c1.z * cs.lmx.y + cs.lead;
+  const bool mb0 = q0 >= 0 && ((cols.m0 >> cs.bit) & 1ull);
+  const bool mb1 = q1 >= 0 && ((cols.m1 >> cs.bit) & 1ull);
+  const int gp = gn >= 0 ? gn : g;
+  stage_group<KS>(b, gp, wave, lane, nxt);
+  load_cols(b, cs.blk, gp, lane, cols);
+#pragma unroll
+  for (int cb = 0; cb < 2; cb++) {
+    // this lane's query column: threshold cq on t = |x|^2 - 2P
+    const int q = cb ? q1 : q0;
+    const float cq = cb ? cq1 : cq0;
+    const bool mbit = cb ? mb1 : mb0;
+    // a 32-query block with no surviving (query, leaf) pair is skipped
+    if (!DUMP && !__ballot(mbit)) continue;
+    st_pairs += 64 * 32;
+    f16v acc[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+      const u4v u = cur[(cb * KS + ks) * 64 + lane];
+      const bf8v bq = __builtin_bit_cast(bf8v, u);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], bq, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], bq, acc[1], 0, 0, 0);
+    }
+    // D[i][j]: j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row)
+    if (DUMP) {
+      // inspection: the lower bound t - o of every pair
+      const float4 qm = b.qmeta[g * kGroup + cb * 32 + (lane & 31)];
+      const float o = -qm.x + 2.0f * (cs.gam * qm.z + qm.y) * cs.lmx.x + 2.0f * qm.w * cs.lmx.y +
+                      (qm.x + cs.lmx.z) * 0x1p-20f;
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+          const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+          const float t = fmaf(-2.0f, acc[r][e], xn2s[ri]);
+          if (cs.c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + cs.c0 + ri] = t - o;
+        }
+      continue;
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      float m = acc[r][0];
+#pragma unroll
+      for (int e = 1; e < 16; e++) m = fmaxf(m, acc[r][e]);
+      any |= fmaf(-2.0f, m, cs.xmin[r]) <= cq;
+    }
+    if (!__ballot(mbit && any)) continue;
+    // rare: exact per-pair test and one append atomic per lane
+    uint32_t hits[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      uint32_t h = 0;
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+        h |= fmaf(-2.0f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
+      }
+      hits[r] = h;
+    }
+    const uint32_t nh = mbit ? (uint32_t)(__popc(hits[0]) + __popc(hits[1])) : 0u;
+    if (nh) {
+      uint32_t slot = atomicAdd(b.ccnt + q, nh);
+      bool dropped = false;
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        uint32_t h = hits[r];
+        while (h) {
+          const int e = __builtin_ctz(h);
+          h &= h - 1;
+          const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+          if (slot < (uint32_t)b.cap)
+            b.cand[(int64_t)q * b.cap + slot] = (uint32_t)(cs.c0 + ri);
+          else
+            dropped = true;
+          slot++;
+        }
+      }
+      // a dropped candidate: the query is finished exhaustively
+      if (dropped && b.cevmin[q] != 0u) atomicMin(b.cevmin + q, 0u);
+    }
+  }
+  // the next group's fragments have landed; every wave is done with cur
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+}
+
 template <int KS, bool DUMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_bf16_tiles(SearchArgs a, Bf16Args b) {
-  __shared__ __attribute__((aligned(16))) uint4 Bs[2 * KS * 64];
+  __shared__ __attribute__((aligned(16))) u4v Bs0[2 * KS * 64];
+  __shared__ __attribute__((aligned(16))) u4v Bs1[2 * KS * 64];
   __shared__ float xn2s[256];
   __shared__ uint32_t item_sh;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const float gam = (float)(KS * 16 + 16) * 0x1p-23f;
+  ChunkState cs;
+  cs.wave = threadIdx.x >> 6;
+  cs.lane = threadIdx.x & 63;
+  cs.gam = (float)(KS * 16 + 16) * 0x1p-23f;
+  const int wave = cs.wave, lane = cs.lane;
   unsigned long long st_pairs = 0;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
@@ -258,30 +430,49 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     const int64_t chunk =
         b.chunk_mult * (b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
                                    : (int64_t)it * b.chunk_stride + b.chunk_first);
-    const int64_t c0 = chunk * 256;
-    const int64_t leaf = c0 / a.L;
-    const int64_t blk = leaf / kLeavesPerItem;
-    const int bit = (int)(leaf % kLeavesPerItem);
+    cs.c0 = chunk * 256;
+    const int64_t leaf = cs.c0 / a.L;
+    cs.blk = leaf / kLeavesPerItem;
+    cs.bit = (int)(leaf % kLeavesPerItem);
+    // the chunk's groups with work, 64 at a time: one load per lane and a ballot
+    int w0 = 0;
+    uint64_t glist = __ballot(lane < b.G && ((b.gmask[cs.blk * b.G + lane] >> cs.bit) & 1ull));
+    auto next_group = [&]() -> int {
+      while (!glist) {
+        w0 += 64;
+        if (w0 >= b.G) return -1;
+        glist = __ballot(w0 + lane < b.G && ((b.gmask[cs.blk * b.G + w0 + lane] >> cs.bit) & 1ull));
+      }
+      const int g = w0 + __builtin_ctzll(glist);
+      glist &= glist - 1;
+      return g;
+    };
+    int g = next_group();
+    ColTerms cols;
+    if (g >= 0) {
+      stage_group<KS>(b, g, wave, lane, Bs0);
+      load_cols(b, cs.blk, g, lane, cols);
+    }
     // A operand: this wave's 64 rows, all K steps, in registers
-    const int64_t rb0 = (c0 + 64 * wave) / 32;
+    const int64_t rb0 = (cs.c0 + 64 * wave) / 32;
     bf8v av[2][KS];
 #pragma unroll
     for (int r = 0; r < 2; r++)
 #pragma unroll
       for (int ks = 0; ks < KS; ks++) {
-        uint4 v = b.xb[((rb0 + r) * KS + ks) * 64 + lane];
-        av[r][ks] = *reinterpret_cast<bf8v*>(&v);
+        const u4v v = reinterpret_cast<const u4v*>(b.xb)[((rb0 + r) * KS + ks) * 64 + lane];
+        av[r][ks] = __builtin_bit_cast(bf8v, v);
       }
     {
       // rows past N (zero in the copy) get a NaN |x|^2: no compare passes
-      const int64_t row = c0 + threadIdx.x;
+      const int64_t row = cs.c0 + threadIdx.x;
       xn2s[threadIdx.x] = row < a.N ? b.meta[row].x : __builtin_nanf("");
     }
-    const float4 lmx = b.leafmeta[leaf];
-    const float lead = lmx.z * 0x1p-20f;
+    cs.lmx = b.leafmeta[leaf];
+    cs.lead = cs.lmx.z * 0x1p-20f;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first group's fragments
     __syncthreads();
     // smallest |x|^2 over the 16 rows of this lane's fragment, per row block
-    float xmin[2];
 #pragma unroll
     for (int r = 0; r < 2; r++) {
       float m = INFINITY;  // NaN rows are skipped; all-NaN leaves +inf (a superset)
@@ -290,100 +481,17 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
         const float v = xn2s[64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4)];
         m = v < m ? v : m;
       }
-      xmin[r] = m;
+      cs.xmin[r] = m;
     }
-    // the chunk's groups with work: one load per lane and a ballot per 64 groups
-    for (int w0 = 0; w0 < b.G; w0 += 64) {
-      const bool has = w0 + lane < b.G && ((b.gmask[blk * b.G + w0 + lane] >> bit) & 1ull);
-      uint64_t glist = __ballot(has);
-      while (glist) {
-        const int g = w0 + __builtin_ctzll(glist);
-        glist &= glist - 1;
-        __syncthreads();
-        const uint4* src = b.qb + (int64_t)(2 * g) * KS * 64;
-        for (int i = threadIdx.x; i < 2 * KS * 64; i += 256) Bs[i] = src[i];
-        __syncthreads();
-        st_pairs += 64 * 64;
-#pragma nounroll
-        for (int cb = 0; cb < 2; cb++) {
-          // this lane's query column: threshold cq on t = |x|^2 - 2P
-          const int s = g * kGroup + cb * 32 + (lane & 31);
-          const float4 c = b.slotc[s];
-          const int q = __float_as_int(c.w);
-          const float cq = c.x + c.y * lmx.x + c.z * lmx.y + lead;
-          const bool mbit = q >= 0 && ((b.smask[blk * (int64_t)b.G * kGroup + s] >> bit) & 1ull);
-          f16v acc[2];
-#pragma unroll
-          for (int r = 0; r < 2; r++)
-#pragma unroll
-            for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
-#pragma unroll
-          for (int ks = 0; ks < KS; ks++) {
-            uint4 u = Bs[(cb * KS + ks) * 64 + lane];
-            bf8v bq = *reinterpret_cast<bf8v*>(&u);
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], bq, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], bq, acc[1], 0, 0, 0);
-          }
-          // D[i][j]: j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row)
-          if (DUMP) {
-            // inspection: the lower bound t - o of every pair
-            const float4 qm = b.qmeta[s];
-            const float o = -qm.x + 2.0f * (gam * qm.z + qm.y) * lmx.x + 2.0f * qm.w * lmx.y +
-                            (qm.x + lmx.z) * 0x1p-20f;
-#pragma unroll
-            for (int r = 0; r < 2; r++)
-#pragma unroll
-              for (int e = 0; e < 16; e++) {
-                const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-                const float t = fmaf(-2.0f, acc[r][e], xn2s[ri]);
-                if (c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + c0 + ri] = t - o;
-              }
-            continue;
-          }
-          bool any = false;
-#pragma unroll
-          for (int r = 0; r < 2; r++) {
-            float m = acc[r][0];
-#pragma unroll
-            for (int e = 1; e < 16; e++) m = fmaxf(m, acc[r][e]);
-            any |= fmaf(-2.0f, m, xmin[r]) <= cq;
-          }
-          if (!__ballot(mbit && any)) continue;
-          // rare: exact per-pair test and one append atomic per lane
-          uint32_t hits[2];
-#pragma unroll
-          for (int r = 0; r < 2; r++) {
-            uint32_t h = 0;
-#pragma unroll
-            for (int e = 0; e < 16; e++) {
-              const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-              h |= fmaf(-2.0f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
-            }
-            hits[r] = h;
-          }
-          const uint32_t nh = mbit ? (uint32_t)(__popc(hits[0]) + __popc(hits[1])) : 0u;
-          if (nh) {
-            uint32_t slot = atomicAdd(b.ccnt + q, nh);
-            bool dropped = false;
-#pragma unroll
-            for (int r = 0; r < 2; r++) {
-              uint32_t h = hits[r];
-              while (h) {
-                const int e = __builtin_ctz(h);
-                h &= h - 1;
-                const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-                if (slot < (uint32_t)b.cap)
-                  b.cand[(int64_t)q * b.cap + slot] = (uint32_t)(c0 + ri);
-                else
-                  dropped = true;
-                slot++;
-              }
-            }
-            // a dropped candidate: the query is finished exhaustively
-            if (dropped && b.cevmin[q] != 0u) atomicMin(b.cevmin + q, 0u);
-          }
-        }
-      }
+    // groups alternate between the two buffers
+    while (g >= 0) {
+      int gn = next_group();
+      group_step<KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
+      g = gn;
+      if (g < 0) break;
+      gn = next_group();
+      group_step<KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
+      g = gn;
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
@@ -483,8 +591,13 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
 
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st) {
   const int B = a.B;
-  k_qcount<<<nblk(B, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, b.qcount);
-  k_qsort<<<nblk(B, 256), 256, 0, st>>>(b.qcount, B, b.perm);
+  SOFA_TRY(launch_fill_u32(b.qcount, 0u, B, st));
+  {
+    const int64_t sl = a.n_blocks < 64 ? a.n_blocks : 64;
+    dim3 grid(nblk(B, 256), (unsigned)(sl > 0 ? sl : 1));
+    k_qcount<<<grid, 256, 0, st>>>(a.masks, a.n_blocks, B, b.qcount);
+  }
+  k_qsort<<<nblk(B, 4), 256, 0, st>>>(b.qcount, a.best, B, a.n_leaves, b.perm);
   const int Spad = b.G * kGroup;
   k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
   k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(b.smask, a.n_blocks, b.G, b.gmask);

@@ -212,20 +212,43 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
 }
 
 // column sums over the batch: out[i] = sum_b scale_b * X[b][i]  (scale nullable)
-__global__ void k_colsum(const float* __restrict__ X, int64_t B, int W, const float* __restrict__ scale,
-                         float* __restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// column sums over the batch, sum_b scale[b] X[b][i] (scale may be null):
+// part[s][i] over the rows b = 4s + r (mod 4 kColSlices), r = wave, the four
+// waves added in order, then the kColSlices partials added in slice order
+constexpr int kColSlices = 16;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ X, int64_t B, int W,
+                                                    const float* __restrict__ scale,
+                                                    float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r = threadIdx.x >> 6;
+  float acc = 0.0f;
+  if (c < W)
+    for (int64_t b = (int64_t)blockIdx.y * 4 + r; b < B; b += 4 * kColSlices)
+      acc = fmaf(scale ? scale[b] : 1.0f, X[b * W + c], acc);
+  red[r][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (r == 0 && c < W) {
+    const int j = threadIdx.x & 63;
+    part[(int64_t)blockIdx.y * W + c] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+  }
+}
+
+__global__ void k_colsum_fin(const float* __restrict__ part, int W, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W) return;
   float s = 0.0f;
-  for (int64_t b = 0; b < B; b++) s = fmaf(scale ? scale[b] : 1.0f, X[b * W + i], s);
+  for (int j = 0; j < kColSlices; j++) s += part[(int64_t)j * W + i];
   out[i] = s;
 }
 
-__global__ void k_sum(const float* __restrict__ x, int64_t B, float* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  float s = 0.0f;
-  for (int64_t b = 0; b < B; b++) s += x[b];
-  out[0] = s;
+// part holds at least kColSlices * W floats
+static void colsum(const float* X, int64_t B, int W, const float* scale, float* part, float* out,
+                   hipStream_t st) {
+  dim3 g(nblk(W, 64), kColSlices);
+  k_colsum_part<<<g, 256, 0, st>>>(X, B, W, scale, part);
+  k_colsum_fin<<<nblk(W, 256), 256, 0, st>>>(part, W, out);
 }
 
 // dz2[b][i] = dy[b] * w3[i] * g'(z2[b][i])
@@ -323,7 +346,10 @@ static sofa_status ensure_act(sofa_radius* m, int64_t B) {
   const MlpDims& d = m->dims;
   if (!m->part.p) {
     const int64_t mn = std::max<int64_t>((int64_t)d.H2 * d.H1, (int64_t)d.H1 * d.D);
-    SOFA_TRY(m->part.alloc((size_t)kSplitK * mn * 4));
+    // split-K partials, and the column-sum partials (kColSlices per column)
+    const int64_t need = std::max<int64_t>((int64_t)kSplitK * mn,
+                                           (int64_t)kColSlices * std::max(d.H1, d.H2));
+    SOFA_TRY(m->part.alloc((size_t)need * 4));
   }
   if (B <= m->act_rows) return SOFA_OK;
   const size_t per = (size_t)d.D + 2 * d.H1 + 3 * d.H2 + 4;
@@ -366,16 +392,16 @@ static void mlp_backward(const sofa_radius* m, const float* target, int64_t B, c
   const float* wr = m->wr.as<float>();
   k_loss<<<1, 256, 0, st>>>(a.y, target, B, a.dy, loss);
   // output layer
-  k_colsum<<<nblk(d.H2, 256), 256, 0, st>>>(a.h2, B, d.H2, a.dy, grad + d.oW3);
-  k_sum<<<1, 64, 0, st>>>(a.dy, B, grad + d.ob3);
+  colsum(a.h2, B, d.H2, a.dy, part, grad + d.oW3, st);
+  colsum(a.dy, B, 1, nullptr, part, grad + d.ob3, st);
   // second layer: dz2, dW2 = dz2^T h1, db2
   k_dz2<<<nblk(B * d.H2, 256), 256, 0, st>>>(a.dy, wr + d.oW3, a.z2, B, d.H2, a.dz2);
   gemm_splitk(d.H2, d.H1, (int)B, a.dz2, 1, d.H2, a.h1, d.H1, 1, grad + d.oW2, part, kSplitK, st);
-  k_colsum<<<nblk(d.H2, 256), 256, 0, st>>>(a.dz2, B, d.H2, nullptr, grad + d.ob2);
+  colsum(a.dz2, B, d.H2, nullptr, part, grad + d.ob2, st);
   // first layer: dz1 = (dz2 W2) * g'(z1) (written over h1), dW1 = dz1^T xs, db1
   gemm<2>((int)B, d.H1, d.H2, a.dz2, d.H2, 1, wr + d.oW2, d.H1, 1, a.h1, d.H1, nullptr, nullptr, a.z1, st);
   gemm_splitk(d.H1, d.D, (int)B, a.h1, 1, d.H1, a.xs, d.D, 1, grad + d.oW1, part, kSplitK, st);
-  k_colsum<<<nblk(d.H1, 256), 256, 0, st>>>(a.h1, B, d.H1, nullptr, grad + d.ob1);
+  colsum(a.h1, B, d.H1, nullptr, part, grad + d.ob1, st);
 }
 
 }  // namespace sofa
