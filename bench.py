@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published FP32 vector peak
 PEAK_BF16_MFMA = 2.5e15       # FLOP/s, MI355X published dense BF16 matrix peak
+PEAK_FP8_MFMA = 5.0e15        # FLOP/s, MI355X published dense FP8 matrix peak
 
 
 def log(*a):
@@ -56,6 +57,8 @@ def main():
                     help="noisy-copy training queries for the radius network")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--quantile", type=float, default=0.999)
+    ap.add_argument("--headline", default="learned_bf16",
+                    help="path whose k-NN rate is the reported value")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -80,7 +83,7 @@ def main():
     bins = sofa.Bins.learn(Xd, max(1, N // 100))
     t_bins = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ix = sofa.Index(bins, Xd, leaf_size=args.leaf, precision=1)
+    ix = sofa.Index(bins, Xd, leaf_size=args.leaf, precision=3)  # BF16 and FP8 copies
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del Xd
@@ -103,6 +106,8 @@ def main():
         for i in range(0, ntr, 4096):
             _, dd = ix.knn(Qtr_d[i:i + 4096].contiguous(), kk, prune=1)
             lab.append(torch.log(dd[:, -1]))
+            if (i // 4096) % 64 == 63:
+                log(f"labels k={kk}: {i + 4096}/{ntr}")
         target = torch.cat(lab).contiguous()
         m = sofa.RadiusModel(k=kk, seed=11 + kk)
         m.standardize(feat[:n_fit].contiguous())
@@ -121,10 +126,13 @@ def main():
     del Qtr_d, feat
     log(f"radius training {t_train:.1f}s")
 
-    paths = {"plain": dict(prune=0), "bf16": dict(prune=1),
+    paths = {"plain": dict(prune=0), "bf16": dict(prune=1), "fp8": dict(prune=2),
              "learned_bf16": dict(prune=1, model="learned", sampling=1),
-             "learned_bf16_1pass": dict(prune=1, model="learned", sampling=2)}
-    headline = "learned_bf16"
+             "learned_bf16_1pass": dict(prune=1, model="learned", sampling=2),
+             "learned_fp8": dict(prune=2, model="learned", sampling=1)}
+    headline = args.headline
+    if headline not in paths:
+        raise SystemExit(f"unknown headline path {headline}")
 
     def run_steps(kk, kw, steps, warmup):
         kw = dict(kw)
@@ -158,6 +166,16 @@ def main():
                                                  "series_refined", "series_bf16_checked",
                                                  "radius_fallbacks", "overflow_fallbacks")},
             }
+            if kw.get("prune", 0):
+                # MFMA rate of the tile kernel on the pairs whose leaf survived
+                pairs = st["leaves_visited"] * args.leaf
+                tms = res[f"k{kk}"]["stages_ms"]["ms_bf16_tiles"]
+                peak = PEAK_FP8_MFMA if kw["prune"] == 2 else PEAK_BF16_MFMA
+                if tms > 0:
+                    res[f"k{kk}"]["tiles_tflops_needed"] = 2.0 * n * pairs / (tms * 1e-3) / 1e12
+                    res[f"k{kk}"]["tiles_tflops_executed"] = (2.0 * n * st["series_bf16_checked"] /
+                                                              (tms * 1e-3) / 1e12)
+                    res[f"k{kk}"]["tiles_peak_tflops"] = peak / 1e12
             if kk == k:
                 ids_by_path[name] = ids.cpu().numpy()
             log(f"{name} k={kk}: {sec * 1e3:.2f} ms/step ({B / sec:.0f} q/s)")
@@ -196,8 +214,9 @@ def main():
         flops = 2.0 * n * pairs
         ms = stg["ms_bf16_tiles"]
         ach = flops / (ms * 1e-3)
-        roofline = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
-                    "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA, "traffic": None,
+        peak = PEAK_FP8_MFMA if paths[headline]["prune"] == 2 else PEAK_BF16_MFMA
+        roofline = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                     "kernel": "k_bf16_tiles", "ms_per_launch": ms,
                     "work_per_launch": {"flop": flops, "pairs_needed": pairs,
                                         "pairs_computed": cnt["series_bf16_checked"]}}
@@ -222,7 +241,7 @@ def main():
         "metric": "exact k-NN queries/s @10M x 256: learned-radius + BF16 vs plain GPU; p99 ms",
         "value": h["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": ("fp8" if paths[headline].get("prune") == 2 else "bf16") + "+f32+f64", "data": "synthetic",
         "config": {"workload": f"{N} x {n} FP32 mix (even rows random walk, odd rows 8-sinusoid "
                                f"high-frequency), {B} noisy-copy queries (sigma 0.1), k={k}, "
                                f"l=16 alpha=256 equi-depth, 1% sample, leaf {args.leaf}",

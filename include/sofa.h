@@ -117,7 +117,11 @@ double sofa_bins_eta_per_norm(const sofa_bins* bins);
  * the call returns. */
 typedef struct {
   int32_t leaf_size; /* rows per leaf, a multiple of 64 in [64, 4096] (default 256) */
-  int32_t precision; /* bit 0: keep a BF16 copy for the batched-distance prune */
+  /* bit 0: keep a BF16 copy for the batched-distance prune (n <= 256);
+   * bit 1: keep an FP8 (OCP e4m3) copy (n <= 512), scaled by a power of two
+   * per 256-row chunk so that every value fits the e4m3 range.  Both need
+   * leaf_size to be a multiple of 256. */
+  int32_t precision;
   /* sort key: 0 (default) spends 8/8/8/8, 4/4/4/4, 2 x 8 key bits on word
    * positions 0-3, 4-7, 8-15 (positions are in decreasing-variance order),
    * interleaved most significant first; 1 spends 4 bits on every position */
@@ -137,6 +141,7 @@ typedef struct {
   int64_t device_bytes; /* device memory held by the index */
   double eta_x;         /* projection error bound used for the data words */
   int32_t has_bf16;
+  int32_t has_fp8;
 } sofa_index_info;
 
 sofa_status sofa_index_get_info(const sofa_index* index, sofa_index_info* info);
@@ -174,7 +179,10 @@ void sofa_workspace_free(sofa_workspace* ws);
 
 typedef struct {
   /* Batched-distance prune before the FP32 refinement: 0 off, 1 BF16 MFMA
-   * (needs an index built with precision bit 0). */
+   * (needs an index built with precision bit 0), 2 FP8 e4m3 MFMA (needs
+   * precision bit 1).  The prune discards a row only when a rigorous lower
+   * bound of its distance exceeds the query's bound, so results are the same
+   * for every setting. */
   int32_t prune;
   /* Nullable device array of B radii (distance units, not squared).  A
    * finite radius seeds the best-so-far bound with radius^2 so the first
@@ -194,14 +202,14 @@ typedef struct {
    * smaller value only costs time: when in-band candidates are dropped the
    * query is finished by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
-  /* BF16 prune only: 0 (default) runs chunk samples of stride 1024 and 32
+  /* BF16/FP8 prune only: 0 (default) runs chunk samples of stride 1024 and 32
    * before the remaining chunks when no radius is given (each pass prunes
    * with the bound the earlier ones established) and one pass with a radius;
    * 1 always runs the sampled passes; 2 always runs one pass. */
   int32_t sampling;
 } sofa_knn_params;
 
-/* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 128).
+/* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 100).
  * Non-finite query values give SOFA_EINVAL.  Synchronises `stream` before
  * returning (it reads per-query status flags to run fall-backs). */
 sofa_status sofa_knn(const sofa_index* index, const float* d_queries, int64_t B, int32_t k,
@@ -227,11 +235,16 @@ typedef struct {
   /* with the BF16 prune, the refinement stage splits into the MFMA tile
    * kernel(s) and the exact refinement of their candidates */
   double ms_bf16_tiles, ms_bf16_refine;
-  /* why queries took the exhaustive pass: a candidate inside the final band
-   * was evicted or dropped; a BF16 candidate was dropped; the final band
-   * held more rows than the ranking buffer.  max_candidates: the largest
-   * BF16 candidate count of one query in one pass. */
+  /* queries whose batched-distance candidates overflowed, by cause: a
+   * candidate inside the final band was evicted or dropped; a BF16/FP8
+   * candidate was dropped; the final band held more rows than the ranking
+   * buffer.  max_candidates: the largest BF16/FP8 candidate count of one
+   * query in one pass. */
   int64_t overflow_evicted, overflow_bf16_drop, overflow_band, max_candidates;
+  /* queries whose BF16/FP8 candidates overflowed and that were searched once
+   * more with their tightened bound as the radius (on the BF16 tier when the
+   * index has it) before any exhaustive pass */
+  int64_t overflow_retries;
 } sofa_knn_stats;
 
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,
@@ -323,6 +336,15 @@ sofa_status sofa_radius_predict(const sofa_radius* model, const float* d_feat, i
  * products, qh/xh the BF16 copies, r = |x - xh|).  d_lb: B x N FP32. */
 sofa_status sofa_bf16_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
                                    float* d_lb, void* stream);
+
+/* The same for the FP8 tier (index built with precision bit 1): xh =
+ * s_c e4m3(x / s_c) with s_c the power-of-two scale of the row's 256-row
+ * chunk, qh = s_q e4m3(q / s_q), P the FP32 accumulation of the e4m3
+ * products (exact in FP32), and the bound
+ *   |q|^2 + |x|^2 - 2 (s_q s_c P + g|qh||xh| + |q| r_x + r_q |xh|)
+ * with g = (n_pad + 64) 2^-23.  d_lb: B x N FP32. */
+sofa_status sofa_fp8_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
+                                  float* d_lb, void* stream);
 
 #ifdef __cplusplus
 }

@@ -213,7 +213,8 @@ extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int6
 // ============================================================================
 int64_t sofa_index::device_bytes() const {
   return (int64_t)(X.bytes + words.bytes + ids.bytes + keys.bytes + env.bytes + norm2.bytes +
-                   xb.bytes + xb_meta.bytes + xb_leafmeta.bytes);
+                   xb.bytes + xb_meta.bytes + xb_leafmeta.bytes + xf.bytes + xf_cscale.bytes +
+                   xf_meta.bytes + xf_leafmeta.bytes);
 }
 
 static sofa_status clone_bins(const sofa_bins* src, sofa_bins* dst) {
@@ -292,6 +293,26 @@ extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, 
         if (s == SOFA_OK) ix->has_bf16 = 1;
       }
     }
+    if (s == SOFA_OK && params && (params->precision & 2)) {
+      if (ix->n_pad > 512)
+        s = set_error(SOFA_EINVAL, "the FP8 copy supports n <= 512 (padded length %d)", ix->n_pad);
+      else if (ix->L % 256)
+        s = set_error(SOFA_EINVAL, "the FP8 copy needs leaf_size to be a multiple of 256");
+      else {
+        const int64_t n_chunks = (N + 255) / 256;
+        if (s == SOFA_OK) s = ix->xf.alloc((size_t)n_chunks * 256 * ix->n_pad);
+        if (s == SOFA_OK) s = ix->xf_cscale.alloc((size_t)n_chunks * 4);
+        if (s == SOFA_OK) s = ix->xf_meta.alloc((size_t)N * 16);
+        if (s == SOFA_OK) s = ix->xf_leafmeta.alloc((size_t)ix->n_leaves * 16);
+        if (s == SOFA_OK)
+          s = launch_fp8_build(ix->X.as<float>(), N, ix->n_pad, ix->L, ix->n_leaves, ix->xf.as<uint4>(),
+                               ix->xf_cscale.as<float>(), ix->xf_meta.as<float4>(),
+                               ix->xf_leafmeta.as<float4>(), st);
+        if (s == SOFA_OK && hipStreamSynchronize(st) != hipSuccess)
+          s = set_error(SOFA_EDEVICE, "FP8 copy failed: %s", hipGetErrorString(hipGetLastError()));
+        if (s == SOFA_OK) ix->has_fp8 = 1;
+      }
+    }
   }
   if (s != SOFA_OK) {
     delete ix;
@@ -313,6 +334,7 @@ extern "C" sofa_status sofa_index_get_info(const sofa_index* ix, sofa_index_info
   info->device_bytes = ix->device_bytes();
   info->eta_x = ix->eta_x;
   info->has_bf16 = ix->has_bf16;
+  info->has_fp8 = ix->has_fp8;
   return SOFA_OK;
 }
 
@@ -379,8 +401,8 @@ int cap_for(int k, const sofa_knn_params* p) {
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
   W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
-  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_BCTR, W_MLP,
-  W_END
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
+  W_MLP, W_END
 };
 
 struct Layout {
@@ -398,7 +420,7 @@ constexpr int kSample0 = 1024, kSample1 = 32;
 
 Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
   size_t sz[W_END];
-  const bool bf = p && p->prune == 1;
+  const bool bf = p && (p->prune == 1 || p->prune == 2);
   const int64_t G = (B + kGroup - 1) / kGroup;
   sz[W_QP] = (size_t)B * ix->n_pad * 4;
   sz[W_POOL] = (size_t)B * ix->bins.ncol_pool * 4;
@@ -428,6 +450,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_SLOTC] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
   sz[W_QMETA] = bf ? (size_t)G * kGroup * 16 : 0;
+  sz[W_QSCALE] = bf ? (size_t)G * kGroup * 4 : 0;
   sz[W_BCTR] = bf ? 64 : 0;
   sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
   Layout L;
@@ -454,7 +477,7 @@ extern "C" sofa_status sofa_workspace_bytes_for(const sofa_index* ix, int64_t B,
 
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
-                            sofa_workspace* ws, sofa_knn_stats& stats);
+                            sofa_workspace* ws, sofa_knn_stats& stats, int depth = 0);
 
 extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
                                 const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
@@ -473,9 +496,11 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
                        m->dims.D, 2 * ix->bins.pool);
   }
   if (params && params->prune != 0) {
-    if (params->prune != 1) return set_error(SOFA_EINVAL, "prune must be 0 (off) or 1 (BF16)");
+    if (params->prune != 1 && params->prune != 2)
+      return set_error(SOFA_EINVAL, "prune must be 0 (off), 1 (BF16) or 2 (FP8)");
     if (params->sampling < 0 || params->sampling > 2) return set_error(SOFA_EINVAL, "sampling must be 0, 1 or 2");
-    if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+    if (params->prune == 1 && !ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+    if (params->prune == 2 && !ix->has_fp8) return set_error(SOFA_EINVAL, "the index was built without the FP8 copy");
   }
   sofa_workspace* ws = params ? params->ws : nullptr;
   if (!ws) {
@@ -505,7 +530,7 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
 
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
-                            sofa_workspace* ws, sofa_knn_stats& stats) {
+                            sofa_workspace* ws, sofa_knn_stats& stats, int depth) {
   const Layout lay = layout_for(ix, B, k, p);
   if (ws->max_bytes > 0 && (int64_t)lay.total > ws->max_bytes)
     return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay.total,
@@ -564,7 +589,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_model_radius(p->radius_model, (const float*)at(W_POOL), ix->bins.ncol_pool, B,
                                  (float*)at(W_MLP), a.U0, st));
   const bool has_radius = p && (p->d_radius || use_model);
-  const bool bf = p && p->prune == 1;
+  const bool bf = p && (p->prune == 1 || p->prune == 2);
   int bf_passes = 0;
   if (!bf) {
     SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
@@ -574,11 +599,20 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_fill_u32(cev, 0xFFFFFFFFu, B, st));
     SOFA_TRY(launch_front(a, st, ev));
     Bf16Args b{};
-    b.xb = ix->xb.as<uint4>();
-    b.meta = ix->xb_meta.as<float4>();
-    b.leafmeta = ix->xb_leafmeta.as<float4>();
+    b.prec = p->prune;
+    if (b.prec == 2) {
+      b.xb = ix->xf.as<uint4>();
+      b.meta = ix->xf_meta.as<float4>();
+      b.leafmeta = ix->xf_leafmeta.as<float4>();
+      b.cscale = ix->xf_cscale.as<float>();
+    } else {
+      b.xb = ix->xb.as<uint4>();
+      b.meta = ix->xb_meta.as<float4>();
+      b.leafmeta = ix->xb_leafmeta.as<float4>();
+    }
     b.qb = (uint4*)at(W_QB);
     b.qmeta = (float4*)at(W_QMETA);
+    b.qscale = (float*)at(W_QSCALE);
     b.perm = (int32_t*)at(W_PERM);
     b.qcount = (uint32_t*)at(W_QCNT);
     b.gmask = (uint64_t*)at(W_GMASK);
@@ -610,10 +644,12 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   }
   std::vector<int32_t> hst(B);
   std::vector<float> hu0(B);
+  std::vector<uint32_t> hu(B);
   unsigned hbad = 0;
   unsigned long long hstats[8];
   SOFA_HIP(hipMemcpyAsync(hst.data(), status, 4 * B, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipMemcpyAsync(hu0.data(), a.U0, 4 * B, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipMemcpyAsync(hu.data(), a.U, 4 * B, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipMemcpyAsync(hstats, a.stats, 64, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipStreamSynchronize(st));
@@ -647,11 +683,21 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     if (hst[q] == 4) stats.overflow_bf16_drop++;
     if (hst[q] == 5) stats.overflow_band++;
   }
-  std::vector<int64_t> redo;
+  std::vector<int64_t> redo, tighten;
+  std::vector<float> tighten_r;
   for (int64_t q = 0; q < B; q++) {
     int st_q = hst[q];
     bool has_radius = std::isfinite(hu0[q]);
-    if (st_q == 1 || (st_q >= 2 && has_radius)) {
+    float uq = 0.0f;
+    memcpy(&uq, &hu[q], 4);
+    if (st_q == 4 && bf && depth == 0 && std::isfinite(uq) && uq >= 0.0f) {
+      // the prune tier dropped candidates: U is still a valid bound on the
+      // k-th distance (k rows were refined), so search once more with it as
+      // the radius, on the BF16 tier when the index has it (its bound is
+      // tighter than FP8's); that search falls back like any radius search
+      tighten.push_back(q);
+      tighten_r.push_back((float)(std::sqrt((double)uq) * (1.0 + 1e-6)));
+    } else if (st_q == 1 || (st_q >= 2 && has_radius)) {
       redo.push_back(q);
     } else if (st_q >= 2) {
       // exhaustive pass with the query's valid bound
@@ -666,33 +712,37 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       stats.overflow_fallbacks++;
     }
   }
-  if (!redo.empty()) {
-    // search these queries again without their radius (exactness does not
-    // depend on the radius)
-    const int64_t R = (int64_t)redo.size();
-    DevBuf qb, ib, db;
+  // search a subset of the queries again (exactness does not depend on the
+  // radius or the prune setting) and scatter the results back
+  auto research = [&](const std::vector<int64_t>& list, const float* radii, int prune,
+                      int sampling) -> sofa_status {
+    const int64_t R = (int64_t)list.size();
+    DevBuf qb, ib, db, rb;
     SOFA_TRY(qb.alloc((size_t)R * ix->n * 4));
     SOFA_TRY(ib.alloc((size_t)R * k * 8));
     SOFA_TRY(db.alloc((size_t)R * k * 4));
     for (int64_t i = 0; i < R; i++)
-      SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + redo[i] * ix->n, (size_t)ix->n * 4,
+      SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + list[i] * ix->n, (size_t)ix->n * 4,
                               hipMemcpyDeviceToDevice, st));
     sofa_knn_params p2{};
-    if (p) {
-      p2.candidate_capacity = p->candidate_capacity;
-      p2.prune = p->prune;
-      p2.sampling = p->sampling == 2 ? 0 : p->sampling;  // without a radius, sample first
+    if (p) p2.candidate_capacity = p->candidate_capacity;
+    p2.prune = prune;
+    p2.sampling = sampling;
+    if (radii) {
+      SOFA_TRY(rb.alloc((size_t)R * 4));
+      SOFA_HIP(hipMemcpyAsync(rb.p, radii, (size_t)R * 4, hipMemcpyHostToDevice, st));
+      p2.d_radius = rb.as<float>();
     }
     sofa_knn_stats s2{};
-    SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2));
+    SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2,
+                      depth + 1));
     for (int64_t i = 0; i < R; i++) {
-      SOFA_HIP(hipMemcpyAsync(d_ids + redo[i] * k, ib.as<int64_t>() + i * k, (size_t)k * 8,
+      SOFA_HIP(hipMemcpyAsync(d_ids + list[i] * k, ib.as<int64_t>() + i * k, (size_t)k * 8,
                               hipMemcpyDeviceToDevice, st));
-      SOFA_HIP(hipMemcpyAsync(d_d + redo[i] * k, db.as<float>() + i * k, (size_t)k * 4,
+      SOFA_HIP(hipMemcpyAsync(d_d + list[i] * k, db.as<float>() + i * k, (size_t)k * 4,
                               hipMemcpyDeviceToDevice, st));
     }
     SOFA_HIP(hipStreamSynchronize(st));
-    stats.radius_fallbacks += R;
     stats.leaves_visited += s2.leaves_visited;
     stats.series_lb_checked += s2.series_lb_checked;
     stats.series_refined += s2.series_refined;
@@ -701,6 +751,20 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.overflow_evicted += s2.overflow_evicted;
     stats.overflow_bf16_drop += s2.overflow_bf16_drop;
     stats.overflow_band += s2.overflow_band;
+    stats.radius_fallbacks += s2.radius_fallbacks;
+    stats.overflow_retries += s2.overflow_retries;
+    return SOFA_OK;
+  };
+  if (!tighten.empty()) {
+    SOFA_TRY(research(tighten, tighten_r.data(), ix->has_bf16 ? 1 : p->prune, 2));
+    stats.overflow_retries += (int64_t)tighten.size();
+  }
+  if (!redo.empty()) {
+    // without their radius; without a radius the prune samples first
+    const int prune = p ? p->prune : 0;
+    const int sampling = p ? (p->sampling == 2 ? 0 : p->sampling) : 0;
+    SOFA_TRY(research(redo, nullptr, prune, sampling));
+    stats.radius_fallbacks += (int64_t)redo.size();
   }
   return SOFA_OK;
 }
@@ -755,15 +819,17 @@ extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_qu
   return SOFA_OK;
 }
 
-extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
-                                              float* d_lb, void* stream) {
+// the prune tier's lower bound of every (query, row) pair, no pruning
+static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B, int prec,
+                                      float* d_lb, void* stream) {
   if (!ix || B < 0 || (B > 0 && (!d_queries || !d_lb))) return set_error(SOFA_EINVAL, "bad arguments");
-  if (!ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+  if (prec == 1 && !ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
+  if (prec == 2 && !ix->has_fp8) return set_error(SOFA_EINVAL, "the index was built without the FP8 copy");
   if (B == 0) return SOFA_OK;
   if (B > 65535) return set_error(SOFA_EINVAL, "B too large");
   hipStream_t st = S(stream);
   const int64_t G = (B + kGroup - 1) / kGroup;
-  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, sm, sc, perm, qb, qmeta, ctr, U, stats;
+  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, sm, sc, perm, qb, qmeta, qscale, ctr, U, stats;
   SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
   SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
   SOFA_TRY(qn.alloc((size_t)B * 8));
@@ -779,6 +845,7 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   SOFA_TRY(perm.alloc((size_t)B * 4));
   SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2));
   SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16));
+  SOFA_TRY(qscale.alloc((size_t)G * kGroup * 4));
   SOFA_TRY(ctr.alloc(64));
   SOFA_TRY(stats.alloc(64));
   SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
@@ -806,11 +873,20 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   SOFA_TRY(launch_fill_u32((uint32_t*)masks.p, 0xFFFFFFFFu, ix->n_blocks * B * 2, st));
   SOFA_TRY(launch_fill_u32(U.as<uint32_t>(), 0x7F800000u, B, st));
   Bf16Args b{};
-  b.xb = ix->xb.as<uint4>();
-  b.meta = ix->xb_meta.as<float4>();
-  b.leafmeta = ix->xb_leafmeta.as<float4>();
+  b.prec = prec;
+  if (prec == 2) {
+    b.xb = ix->xf.as<uint4>();
+    b.meta = ix->xf_meta.as<float4>();
+    b.leafmeta = ix->xf_leafmeta.as<float4>();
+    b.cscale = ix->xf_cscale.as<float>();
+  } else {
+    b.xb = ix->xb.as<uint4>();
+    b.meta = ix->xb_meta.as<float4>();
+    b.leafmeta = ix->xb_leafmeta.as<float4>();
+  }
   b.qb = qb.as<uint4>();
   b.qmeta = qmeta.as<float4>();
+  b.qscale = qscale.as<float>();
   b.perm = perm.as<int32_t>();
   b.qcount = u0.as<uint32_t>();  // scratch for the density sort
   b.gmask = gm.as<uint64_t>();
@@ -822,4 +898,14 @@ extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float*
   SOFA_TRY(launch_bf16_dump(a, b, d_lb, st));
   SOFA_HIP(hipStreamSynchronize(st));
   return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_bf16_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
+                                              float* d_lb, void* stream) {
+  return prune_lower_bounds(ix, d_queries, B, 1, d_lb, stream);
+}
+
+extern "C" sofa_status sofa_fp8_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
+                                             float* d_lb, void* stream) {
+  return prune_lower_bounds(ix, d_queries, B, 2, d_lb, stream);
 }

@@ -1,4 +1,4 @@
-// bf16.h -- arguments of the BF16 batched-distance prune (internal).
+// bf16.h -- arguments of the BF16 / FP8 batched-distance prune (internal).
 #pragma once
 
 #include "search_dev.h"
@@ -8,10 +8,13 @@ namespace sofa {
 constexpr int kGroup = 64;  // queries per MFMA query group
 
 struct Bf16Args {
-  const uint4* xb;          // BF16 rows in MFMA A-operand order
+  int prec;                 // 1: BF16 copy, 2: FP8 (e4m3) copy
+  const uint4* xb;          // BF16 or FP8 rows in MFMA A-operand order
   const float4* meta;       // per row: |x|^2 (down), r_x (up), |xh| (up)
   const float4* leafmeta;   // per leaf: max |xh|, max r_x, max |x|^2
-  uint4* qb;                // BF16 query fragments per sorted slot
+  const float* cscale;      // FP8: power-of-two scale per 256-row chunk
+  uint4* qb;                // BF16 or FP8 query fragments per sorted slot
+  float* qscale;            // FP8: power-of-two scale per sorted slot
   float4* qmeta;            // per slot: |q|^2 (down), r_q (up), |qh| (up), |q| (up)
   int32_t* perm;            // sorted slot -> query
   uint32_t* qcount;         // surviving leaves per query
@@ -32,6 +35,10 @@ struct Bf16Args {
 
 sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                               uint4* xb, float4* meta, float4* leafmeta, hipStream_t st);
+// FP8 copy: xf in 32x32x64 operand order (two 16-byte halves per lane
+// fragment), cscale per 256-row chunk, per-row meta and per-leaf maxima
+sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
+                             uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st);
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
 // ev (nullable): events recorded before the tile kernel, between it and the

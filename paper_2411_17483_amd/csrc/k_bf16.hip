@@ -38,6 +38,54 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_val(uint32_t h) { return __uint_as_float(h << 16); }
 
+// FP32 -> OCP e4m3 (no infinities, largest finite 448), round to nearest
+// even; |v| <= 448 (the power-of-two scales guarantee it), so the NaN code
+// 0x7F never appears
+__device__ __forceinline__ uint32_t e4m3_code(float v) {
+  const uint32_t sgn = (__float_as_uint(v) >> 31) << 7;
+  const float a = fabsf(v);
+  uint32_t code;
+  if (a < 0x1p-6f) {
+    code = (uint32_t)rintf(a * 0x1p9f);  // subnormal step 2^-9; 8 is the smallest normal
+  } else {
+    int ex;
+    (void)frexpf(a, &ex);  // a = f 2^ex, f in [0.5, 1)
+    int e = ex - 1;        // a in [2^e, 2^(e+1))
+    uint32_t m = (uint32_t)rintf(ldexpf(a, 3 - e));  // 8..16
+    if (m == 16) {
+      m = 8;
+      e++;
+    }
+    code = ((uint32_t)(e + 7) << 3) | (m - 8);
+  }
+  return sgn | code;
+}
+__device__ __forceinline__ float e4m3_val(uint32_t c) {
+  const int ef = (int)((c >> 3) & 15u);
+  const float m = (float)(c & 7u);
+  const float mag = ef == 0 ? ldexpf(m, -9) : ldexpf(8.0f + m, ef - 10);
+  return (c & 0x80u) ? -mag : mag;
+}
+// smallest power of two s with 448 s >= maxabs (1 for an all-zero block)
+__device__ __forceinline__ float fp8_scale_for(float maxabs) {
+  if (!(maxabs > 0.0f)) return 1.0f;
+  int e = ilogbf(maxabs) - 8;
+  while (ldexp(448.0, e) < (double)maxabs) e++;
+  while (ldexp(448.0, e - 1) >= (double)maxabs) e--;
+  return ldexpf(1.0f, e);
+}
+// 16 consecutive FP32 values scaled by inv (a power of two) -> 16 e4m3 codes
+__device__ __forceinline__ uint4 fp8_pack16(const float* __restrict__ p, float inv) {
+  uint32_t w[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const float4 v = *reinterpret_cast<const float4*>(p + 4 * j);
+    w[j] = e4m3_code(v.x * inv) | (e4m3_code(v.y * inv) << 8) | (e4m3_code(v.z * inv) << 16) |
+           (e4m3_code(v.w * inv) << 24);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // ----------------------------------------------------------------------------
 // build: swizzled BF16 copy.  Thread i writes the 8 values of fragment slot
 // i = ((rb*KS + ks)*64 + lane): rows rb*32 + lane%32, columns ks*16 + 8*(lane/32) + e.
@@ -89,6 +137,32 @@ __device__ __forceinline__ void norms_of(const float* __restrict__ row, int n_pa
                     __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
 }
 
+// the same for the FP8 copy: xh = sc * e4m3(x / sc)
+__device__ __forceinline__ void norms_of_fp8(const float* __restrict__ row, int n_pad, int lane,
+                                             float sc, float4& out) {
+  const float inv = 1.0f / sc;  // exact: sc is a power of two
+  double s2 = 0.0, r2 = 0.0, h2 = 0.0;
+  for (int c = lane * 4; c < n_pad; c += 256) {
+    float4 v = *reinterpret_cast<const float4*>(row + c);
+    float xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      double x = xs[e], h = (double)sc * (double)e4m3_val(e4m3_code(xs[e] * inv));
+      s2 += x * x;
+      r2 += (x - h) * (x - h);
+      h2 += h * h;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s2 += __shfl_xor(s2, o);
+    r2 += __shfl_xor(r2, o);
+    h2 += __shfl_xor(h2, o);
+  }
+  out = make_float4(__double2float_rd(s2 * (1.0 - 1e-12)), __double2float_ru(sqrt(r2) * (1.0 + 1e-12)),
+                    __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
+}
+
 __global__ __launch_bounds__(256) void k_bf16_meta(const float* __restrict__ X, int64_t N, int n_pad,
                                                    float4* __restrict__ meta) {
   const int lane = threadIdx.x & 63;
@@ -121,6 +195,57 @@ __global__ __launch_bounds__(256) void k_bf16_leafmeta(const float4* __restrict_
   }
   // |x|^2 was rounded down: the margin below uses a value rounded up
   if (lane == 0) lm[leaf] = make_float4(xh, rx, xn * (1.0f + 0x1p-20f), 0.0f);
+}
+
+// ----------------------------------------------------------------------------
+// build: FP8 copy.  Scale per 256-row chunk (one workgroup per chunk).
+__global__ __launch_bounds__(256) void k_fp8_chunk_scale(const float* __restrict__ X, int64_t N,
+                                                         int n_pad, float* __restrict__ cscale) {
+  __shared__ float red[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)blockIdx.x * 256;
+  float m = 0.0f;
+  for (int r = wave; r < 256 && c0 + r < N; r += 4)
+    for (int c = lane * 4; c < n_pad; c += 256) {
+      const float4 v = *reinterpret_cast<const float4*>(X + (c0 + r) * n_pad + c);
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    cscale[blockIdx.x] = fp8_scale_for(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
+
+// Thread i writes the 16-byte half h of fragment slot ((rb*KS + ks)*2 + h)*64 + lane:
+// row rb*32 + lane%32, columns 64 ks + 32 (lane/32) + 16 h + (0..15).
+__global__ void k_fp8_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
+                           const float* __restrict__ cscale, uint4* __restrict__ xf) {
+  const int KS = n_pad / 64;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrb * KS * 128) return;
+  const int lane = (int)(i % 64);
+  const int h = (int)((i / 64) % 2);
+  const int64_t t = i / 128;
+  const int ks = (int)(t % KS);
+  const int64_t rb = t / KS;
+  const int64_t row = rb * 32 + lane % 32;
+  const int k0 = ks * 64 + 32 * (lane / 32) + 16 * h;
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+  if (row < N) w = fp8_pack16(X + row * n_pad + k0, 1.0f / cscale[row / 256]);
+  xf[i] = w;
+}
+
+__global__ __launch_bounds__(256) void k_fp8_meta(const float* __restrict__ X, int64_t N, int n_pad,
+                                                  const float* __restrict__ cscale,
+                                                  float4* __restrict__ meta) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  float4 m;
+  norms_of_fp8(X + row * n_pad, n_pad, lane, cscale[row / 256], m);
+  if (lane == 0) meta[row] = m;
 }
 
 // ----------------------------------------------------------------------------
@@ -250,14 +375,69 @@ __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp
   }
 }
 
+// FP8 query side: a power-of-two scale per slot, fragments in 32x32x64
+// operand order (two 16-byte halves per lane), the same bound terms
+__global__ __launch_bounds__(256) void k_qscale_fp8(const float* __restrict__ Qp, int B, int n_pad,
+                                                    const int32_t* __restrict__ perm, int Spad,
+                                                    float* __restrict__ qscale) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= Spad) return;
+  float m = 0.0f;
+  if (s < B) {
+    const float* qr = Qp + (int64_t)perm[s] * n_pad;
+    for (int c = lane * 4; c < n_pad; c += 256) {
+      const float4 v = *reinterpret_cast<const float4*>(qr + c);
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) qscale[s] = fp8_scale_for(m);
+}
+
+__global__ void k_qprep_fp8(const float* __restrict__ Qp, int B, int n_pad, int Spad,
+                            const int32_t* __restrict__ perm, const float* __restrict__ qscale,
+                            uint4* __restrict__ qb) {
+  const int KS = n_pad / 64;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)(Spad / 32) * KS * 128) return;
+  const int lane = (int)(i % 64);
+  const int h = (int)((i / 64) % 2);
+  const int64_t t = i / 128;
+  const int ks = (int)(t % KS);
+  const int cb = (int)(t / KS);
+  const int s = cb * 32 + lane % 32;
+  const int k0 = ks * 64 + 32 * (lane / 32) + 16 * h;
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+  if (s < B) w = fp8_pack16(Qp + (int64_t)perm[s] * n_pad + k0, 1.0f / qscale[s]);
+  qb[i] = w;
+}
+
+__global__ __launch_bounds__(256) void k_qmeta_fp8(const float* __restrict__ Qp, int B, int n_pad,
+                                                   const int32_t* __restrict__ perm, int Spad,
+                                                   const float* __restrict__ qscale,
+                                                   float4* __restrict__ qmeta) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= Spad) return;
+  float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (s < B) norms_of_fp8(Qp + (int64_t)perm[s] * n_pad, n_pad, lane, qscale[s], m);
+  if (lane == 0) {
+    m.w = __double2float_ru(sqrt((double)m.x) * (1.0 + 1e-7) + 1e-30);
+    qmeta[s] = m;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // tiles: one 256-row chunk per work item
 //
 // Per group, the two 32-query column blocks are taken one after the other
-// (32 accumulators live instead of 64; each BF16 query fragment is read from
-// LDS once).  The usual fragment has no hit, so the epilogue first tests a
-// superset: for the 16 rows e of a lane's fragment,
-//   min_e fl(|x_e|^2 - 2 P_e) >= fl(min_e |x_e|^2 - 2 max_e P_e)
+// (32 accumulators live instead of 64; each query fragment is read from LDS
+// once).  With f = 2 (BF16) or f = 2 s_q s_c (FP8; exact, both scales are
+// powers of two), t = |x|^2 - f P.  The usual fragment has no hit, so the
+// epilogue first tests a superset: for the 16 rows e of a lane's fragment,
+//   min_e fl(|x_e|^2 - f P_e) >= fl(min_e |x_e|^2 - f max_e P_e)
 // (rounding is monotone), and only when that value passes the per-query
 // threshold for some lane of the wave are the 16 pairs tested one by one.
 //
@@ -266,13 +446,52 @@ __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp
 // DMA (global_load_lds_dwordx4, no registers), and the next group's
 // per-column terms are loaded into registers.  The two buffers are separate
 // arrays so that reads of one never wait on the DMA into the other.
+//
+// PREC 1: BF16, v_mfma_f32_32x32x16_bf16, fragment = 8 values (16 bytes) per
+// lane, K step 16.  PREC 2: FP8 e4m3, v_mfma_f32_32x32x64_f8f6f4, fragment =
+// 32 values per lane stored as two 16-byte halves, K step 64.  KS = n_pad /
+// (K step).  Rows and queries use the same fragment order, so the products
+// pair up whatever order the instruction takes within a fragment.
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct TileTraits;
+template <> struct TileTraits<1> {
+  typedef bf8v frag;
+  static constexpr int kHalves = 1, kStep = 16;
+};
+template <> struct TileTraits<2> {
+  typedef v8i frag;
+  static constexpr int kHalves = 2, kStep = 64;
+};
+
+template <int PREC>
+__device__ __forceinline__ typename TileTraits<PREC>::frag load_frag(const u4v* p) {
+  if constexpr (PREC == 1) {
+    return __builtin_bit_cast(bf8v, p[0]);
+  } else {
+    const u4v lo = p[0], hi = p[64];
+    return __builtin_bit_cast(v8i, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f16v mma(typename TileTraits<PREC>::frag a, typename TileTraits<PREC>::frag b,
+                                    f16v c) {
+  if constexpr (PREC == 1)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  else  // A and B formats 0 = FP8 e4m3; no block scales
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
 
 // per-column terms of a group's two 32-query blocks (query slot order)
 struct ColTerms {
   float4 c0, c1;    // bound terms (a, b, c) and query id
   uint64_t m0, m1;  // survivor masks of the chunk's leaf block
+  float s0, s1;     // FP8 query scales
 };
 
+template <int PREC>
 __device__ __forceinline__ void load_cols(const Bf16Args& b, int64_t blk, int g, int lane,
                                           ColTerms& t) {
   const int s = g * kGroup + (lane & 31);
@@ -280,14 +499,26 @@ __device__ __forceinline__ void load_cols(const Bf16Args& b, int64_t blk, int g,
   t.c1 = b.slotc[s + 32];
   t.m0 = b.smask[blk * (int64_t)b.G * kGroup + s];
   t.m1 = b.smask[blk * (int64_t)b.G * kGroup + s + 32];
+  if constexpr (PREC == 2) {
+    t.s0 = b.qscale[s];
+    t.s1 = b.qscale[s + 32];
+  } else {
+    t.s0 = t.s1 = 1.0f;
+  }
 }
 
-// DMA of group g's 2 KS wave-sized (1 KB) fragment pieces into dst, KS/2 per wave
-template <int KS>
+// u4v (16-byte) units of one group's fragments
+template <int PREC, int KS>
+constexpr int group_units() { return 2 * KS * 64 * TileTraits<PREC>::kHalves; }
+
+// DMA of group g's fragments (1 KB pieces, a quarter of them per wave) into dst
+template <int PREC, int KS>
 __device__ __forceinline__ void stage_group(const Bf16Args& b, int g, int wave, int lane, u4v* dst) {
-  const u4v* src = reinterpret_cast<const u4v*>(b.qb) + (int64_t)(2 * g) * KS * 64;
+  constexpr int kPieces = group_units<PREC, KS>() / 64;
+  static_assert(kPieces % 4 == 0, "whole pieces per wave");
+  const u4v* src = reinterpret_cast<const u4v*>(b.qb) + (int64_t)g * group_units<PREC, KS>();
 #pragma unroll
-  for (int i = 0; i < KS / 2; i++) {
+  for (int i = 0; i < kPieces / 4; i++) {
     const int piece = wave + 4 * i;
     __builtin_amdgcn_global_load_lds((const void*)(src + piece * 64 + lane),
                                      (__attribute__((address_space(3))) void*)(dst + piece * 64),
@@ -300,34 +531,38 @@ struct ChunkState {
   int64_t c0, blk;
   int bit, wave, lane;
   float4 lmx;
-  float lead, gam;
+  float lead, gam, sc;
   float xmin[2];
 };
 
 // one group: thresholds from the terms loaded one group ahead, prefetch of
 // the next group (gn; the current one again when gn < 0, unused), the two
 // column blocks, and the barrier that publishes the next buffer
-template <int KS, bool DUMP>
+template <int PREC, int KS, bool DUMP>
 __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& b,
-                                           const ChunkState& cs, const bf8v (&av)[2][KS],
+                                           const ChunkState& cs,
+                                           const typename TileTraits<PREC>::frag (&av)[2][KS],
                                            const float* xn2s, int g, int gn, ColTerms& cols,
-                                           const u4v* cur, u4v* nxt,
-                                           unsigned long long& st_pairs) {
+                                           const u4v* cur, u4v* nxt, unsigned long long& st_pairs) {
+  constexpr int H = TileTraits<PREC>::kHalves;
   const int wave = cs.wave, lane = cs.lane;
   const int q0 = __float_as_int(cols.c0.w), q1 = __float_as_int(cols.c1.w);
   const float cq0 = cols.c0.x + cols.c0.y * cs.lmx.x + cols.c0.z * cs.lmx.y + cs.lead;
   const float cq1 = cols.c1.x + cols.c1.y * cs.lmx.x + cols.c1.z * cs.lmx.y + cs.lead;
   const bool mb0 = q0 >= 0 && ((cols.m0 >> cs.bit) & 1ull);
   const bool mb1 = q1 >= 0 && ((cols.m1 >> cs.bit) & 1ull);
+  const float f0 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s0;
+  const float f1 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s1;
   const int gp = gn >= 0 ? gn : g;
-  stage_group<KS>(b, gp, wave, lane, nxt);
-  load_cols(b, cs.blk, gp, lane, cols);
+  stage_group<PREC, KS>(b, gp, wave, lane, nxt);
+  load_cols<PREC>(b, cs.blk, gp, lane, cols);
 #pragma unroll
   for (int cb = 0; cb < 2; cb++) {
-    // this lane's query column: threshold cq on t = |x|^2 - 2P
+    // this lane's query column: threshold cq on t = |x|^2 - f P
     const int q = cb ? q1 : q0;
     const float cq = cb ? cq1 : cq0;
     const bool mbit = cb ? mb1 : mb0;
+    const float f = cb ? f1 : f0;
     // a 32-query block with no surviving (query, leaf) pair is skipped
     if (!DUMP && !__ballot(mbit)) continue;
     st_pairs += 64 * 32;
@@ -338,10 +573,9 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
       for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      const u4v u = cur[(cb * KS + ks) * 64 + lane];
-      const bf8v bq = __builtin_bit_cast(bf8v, u);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][ks], bq, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][ks], bq, acc[1], 0, 0, 0);
+      const auto bq = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
+      acc[0] = mma<PREC>(av[0][ks], bq, acc[0]);
+      acc[1] = mma<PREC>(av[1][ks], bq, acc[1]);
     }
     // D[i][j]: j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row)
     if (DUMP) {
@@ -354,7 +588,7 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
 #pragma unroll
         for (int e = 0; e < 16; e++) {
           const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-          const float t = fmaf(-2.0f, acc[r][e], xn2s[ri]);
+          const float t = fmaf(-f, acc[r][e], xn2s[ri]);
           if (cs.c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + cs.c0 + ri] = t - o;
         }
       continue;
@@ -365,7 +599,7 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
       float m = acc[r][0];
 #pragma unroll
       for (int e = 1; e < 16; e++) m = fmaxf(m, acc[r][e]);
-      any |= fmaf(-2.0f, m, cs.xmin[r]) <= cq;
+      any |= fmaf(-f, m, cs.xmin[r]) <= cq;
     }
     if (!__ballot(mbit && any)) continue;
     // rare: exact per-pair test and one append atomic per lane
@@ -376,7 +610,7 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
 #pragma unroll
       for (int e = 0; e < 16; e++) {
         const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-        h |= fmaf(-2.0f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
+        h |= fmaf(-f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
       }
       hits[r] = h;
     }
@@ -407,18 +641,21 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
   __syncthreads();
 }
 
-template <int KS, bool DUMP>
+template <int PREC, int KS, bool DUMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_bf16_tiles(SearchArgs a, Bf16Args b) {
-  __shared__ __attribute__((aligned(16))) u4v Bs0[2 * KS * 64];
-  __shared__ __attribute__((aligned(16))) u4v Bs1[2 * KS * 64];
+  typedef typename TileTraits<PREC>::frag frag;
+  constexpr int H = TileTraits<PREC>::kHalves;
+  __shared__ __attribute__((aligned(16))) u4v Bs0[group_units<PREC, KS>()];
+  __shared__ __attribute__((aligned(16))) u4v Bs1[group_units<PREC, KS>()];
   __shared__ float xn2s[256];
   __shared__ uint32_t item_sh;
   ChunkState cs;
   cs.wave = threadIdx.x >> 6;
   cs.lane = threadIdx.x & 63;
-  cs.gam = (float)(KS * 16 + 16) * 0x1p-23f;
+  cs.gam = (float)(KS * TileTraits<PREC>::kStep + TileTraits<PREC>::kStep) * 0x1p-23f;
   const int wave = cs.wave, lane = cs.lane;
+  const u4v* xv = reinterpret_cast<const u4v*>(b.xb);
   unsigned long long st_pairs = 0;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
@@ -450,19 +687,16 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     int g = next_group();
     ColTerms cols;
     if (g >= 0) {
-      stage_group<KS>(b, g, wave, lane, Bs0);
-      load_cols(b, cs.blk, g, lane, cols);
+      stage_group<PREC, KS>(b, g, wave, lane, Bs0);
+      load_cols<PREC>(b, cs.blk, g, lane, cols);
     }
     // A operand: this wave's 64 rows, all K steps, in registers
     const int64_t rb0 = (cs.c0 + 64 * wave) / 32;
-    bf8v av[2][KS];
+    frag av[2][KS];
 #pragma unroll
     for (int r = 0; r < 2; r++)
 #pragma unroll
-      for (int ks = 0; ks < KS; ks++) {
-        const u4v v = reinterpret_cast<const u4v*>(b.xb)[((rb0 + r) * KS + ks) * 64 + lane];
-        av[r][ks] = __builtin_bit_cast(bf8v, v);
-      }
+      for (int ks = 0; ks < KS; ks++) av[r][ks] = load_frag<PREC>(xv + ((rb0 + r) * KS + ks) * 64 * H + lane);
     {
       // rows past N (zero in the copy) get a NaN |x|^2: no compare passes
       const int64_t row = cs.c0 + threadIdx.x;
@@ -470,6 +704,7 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     }
     cs.lmx = b.leafmeta[leaf];
     cs.lead = cs.lmx.z * 0x1p-20f;
+    cs.sc = PREC == 2 ? b.cscale[chunk] : 1.0f;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first group's fragments
     __syncthreads();
     // smallest |x|^2 over the 16 rows of this lane's fragment, per row block
@@ -486,15 +721,42 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     // groups alternate between the two buffers
     while (g >= 0) {
       int gn = next_group();
-      group_step<KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
+      group_step<PREC, KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
       g = gn;
       if (g < 0) break;
       gn = next_group();
-      group_step<KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
+      group_step<PREC, KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
       g = gn;
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
+}
+
+// launch over the supported (precision, K steps) pairs
+template <bool DUMP>
+static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, hipStream_t st) {
+#define SOFA_TILE(P, K) k_bf16_tiles<P, K, DUMP><<<grid, 256, 0, st>>>(a, b)
+  if (b.prec == 1) {
+    switch (a.n_pad / 16) {
+      case 4: SOFA_TILE(1, 4); break;
+      case 8: SOFA_TILE(1, 8); break;
+      case 16: SOFA_TILE(1, 16); break;
+      default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256 (padded %d)", a.n_pad);
+    }
+  } else if (b.prec == 2) {
+    switch (a.n_pad / 64) {
+      case 1: SOFA_TILE(2, 1); break;
+      case 2: SOFA_TILE(2, 2); break;
+      case 4: SOFA_TILE(2, 4); break;
+      case 8: SOFA_TILE(2, 8); break;
+      default: return set_error(SOFA_EINVAL, "the FP8 prune supports n <= 512 (padded %d)", a.n_pad);
+    }
+  } else {
+    return set_error(SOFA_EINVAL, "unknown prune precision %d", b.prec);
+  }
+#undef SOFA_TILE
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -589,6 +851,19 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
   return SOFA_OK;
 }
 
+sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
+                             uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st) {
+  const int64_t n_chunks = (N + 255) / 256;
+  const int64_t nrb = n_chunks * 8;  // 32-row blocks, padded to whole 256-row chunks
+  const int KS = n_pad / 64;
+  k_fp8_chunk_scale<<<(unsigned)n_chunks, 256, 0, st>>>(X, N, n_pad, cscale);
+  k_fp8_copy<<<nblk(nrb * KS * 128, 256), 256, 0, st>>>(X, N, n_pad, nrb, cscale, xf);
+  k_fp8_meta<<<nblk(N, 4), 256, 0, st>>>(X, N, n_pad, cscale, meta);
+  k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st) {
   const int B = a.B;
   SOFA_TRY(launch_fill_u32(b.qcount, 0u, B, st));
@@ -601,18 +876,32 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   const int Spad = b.G * kGroup;
   k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
   k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(b.smask, a.n_blocks, b.G, b.gmask);
-  const int KS = a.n_pad / 16;
-  k_qprep_bf16<<<nblk((int64_t)(Spad / 32) * KS * 64, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
-                                                                           b.perm, b.qb);
-  k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
+  if (b.prec == 2) {
+    const int KS = a.n_pad / 64;
+    k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
+    k_qprep_fp8<<<nblk((int64_t)(Spad / 32) * KS * 128, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
+                                                                            b.perm, b.qscale, b.qb);
+    k_qmeta_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale, b.qmeta);
+  } else {
+    const int KS = a.n_pad / 16;
+    k_qprep_bf16<<<nblk((int64_t)(Spad / 32) * KS * 64, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
+                                                                             b.perm, b.qb);
+    k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
+  }
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
 
+// accumulation bound g = (K + K step) 2^-23 of the FP32 MFMA sums
+static float prune_gamma(const SearchArgs& a, const Bf16Args& b) {
+  const int step = b.prec == 2 ? 64 : 16;
+  return (float)(a.n_pad + step) * 0x1p-23f;
+}
+
 static sofa_status launch_slotc(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
   const int Spad = b.G * kGroup;
-  const float gam = (float)(a.n_pad + 16) * 0x1p-23f;
-  k_slotc<<<nblk(Spad, 256), 256, 0, st>>>(b.qmeta, b.perm, a.B, Spad, a.U, a.lb_f, gam, b.slotc);
+  k_slotc<<<nblk(Spad, 256), 256, 0, st>>>(b.qmeta, b.perm, a.B, Spad, a.U, a.lb_f, prune_gamma(a, b),
+                                           b.slotc);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -628,14 +917,7 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   SOFA_TRY(launch_slotc(a, b, st));
   unsigned grid = 256 * 2;
   if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
-  switch (a.n_pad / 16) {
-    case 4: k_bf16_tiles<4, true><<<grid, 256, 0, st>>>(a, b); break;
-    case 8: k_bf16_tiles<8, true><<<grid, 256, 0, st>>>(a, b); break;
-    case 16: k_bf16_tiles<16, true><<<grid, 256, 0, st>>>(a, b); break;
-    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
-  }
-  SOFA_HIP(hipGetLastError());
-  return SOFA_OK;
+  return launch_tiles<true>(a, b, grid, st);
 }
 
 sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
@@ -659,12 +941,7 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
   unsigned grid = 256 * 2;
   if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
   if (ev) (void)hipEventRecord(ev[0], st);
-  switch (a.n_pad / 16) {
-    case 4: k_bf16_tiles<4, false><<<grid, 256, 0, st>>>(a, b); break;
-    case 8: k_bf16_tiles<8, false><<<grid, 256, 0, st>>>(a, b); break;
-    case 16: k_bf16_tiles<16, false><<<grid, 256, 0, st>>>(a, b); break;
-    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256 (padded %d)", a.n_pad);
-  }
+  SOFA_TRY(launch_tiles<false>(a, b, grid, st));
   if (ev) (void)hipEventRecord(ev[1], st);
   dim3 gr((unsigned)a.B, kCandSplit);
   const int R = (a.k + 16 <= 64) ? 1 : 2;
@@ -677,7 +954,8 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
     SOFA_RC(1)
     SOFA_RC(2)
     SOFA_RC(4)
-    default: return set_error(SOFA_EINVAL, "the BF16 prune supports n <= 256");
+    SOFA_RC(8)
+    default: return set_error(SOFA_EINVAL, "the batched-distance prune supports n <= 512");
   }
 #undef SOFA_RC
   if (ev) (void)hipEventRecord(ev[2], st);

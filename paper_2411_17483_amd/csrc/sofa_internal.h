@@ -96,6 +96,12 @@ struct sofa_index {
   sofa::DevBuf xb;             // BF16 copy, MFMA-tile order
   sofa::DevBuf xb_meta;        // per row: ||x||^2 (rd), r_x (ru), ||xhat|| (ru) as float4
   sofa::DevBuf xb_leafmeta;    // per leaf: max ||xhat||, max r_x, max ||x||^2
+  // FP8 (e4m3) tier
+  int has_fp8 = 0;
+  sofa::DevBuf xf;             // FP8 copy, MFMA-tile order (two 16-byte halves per fragment)
+  sofa::DevBuf xf_cscale;      // per 256-row chunk: power-of-two scale
+  sofa::DevBuf xf_meta;        // per row, as xb_meta for the FP8 copy
+  sofa::DevBuf xf_leafmeta;    // per leaf, as xb_leafmeta for the FP8 copy
   sofa_workspace* own_ws = nullptr;
   int64_t device_bytes() const;
 };

@@ -23,7 +23,7 @@ EXPORTED = [
     "sofa_transform", "sofa_bins_eta_per_norm", "sofa_build", "sofa_index_get_info",
     "sofa_index_export", "sofa_index_free", "sofa_workspace_create", "sofa_workspace_bytes_for",
     "sofa_workspace_free", "sofa_knn", "sofa_knn_get_stats", "sofa_lower_bounds",
-    "sofa_bf16_lower_bounds", "sofa_radius_create", "sofa_radius_free", "sofa_radius_num_params",
+    "sofa_bf16_lower_bounds", "sofa_fp8_lower_bounds", "sofa_radius_create", "sofa_radius_free", "sofa_radius_num_params",
     "sofa_radius_get", "sofa_radius_set", "sofa_radius_standardize", "sofa_radius_gradients",
     "sofa_radius_train_step", "sofa_radius_fit", "sofa_radius_forward", "sofa_radius_calibrate",
     "sofa_radius_predict",
@@ -47,7 +47,7 @@ class BuildParams(ctypes.Structure):
 class IndexInfo(ctypes.Structure):
     _fields_ = [("N", _i64), ("n", _i32), ("n_pad", _i32), ("leaf_size", _i32), ("l", _i32),
                 ("alpha", _i32), ("n_leaves", _i64), ("device_bytes", _i64), ("eta_x", ctypes.c_double),
-                ("has_bf16", _i32)]
+                ("has_bf16", _i32), ("has_fp8", _i32)]
 
 
 class KnnParams(ctypes.Structure):
@@ -70,7 +70,8 @@ class KnnStats(ctypes.Structure):
                 ("ms_seed", ctypes.c_double), ("ms_refine", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("ms_bf16_tiles", ctypes.c_double),
                 ("ms_bf16_refine", ctypes.c_double), ("overflow_evicted", _i64),
-                ("overflow_bf16_drop", _i64), ("overflow_band", _i64), ("max_candidates", _i64)]
+                ("overflow_bf16_drop", _i64), ("overflow_band", _i64), ("max_candidates", _i64),
+                ("overflow_retries", _i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,6 +109,7 @@ def load():
     L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
     L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
     L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.sofa_fp8_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
     L.sofa_radius_create.argtypes = [ctypes.POINTER(RadiusParams), ctypes.POINTER(_vp)]
     L.sofa_radius_free.argtypes = [_vp]
     L.sofa_radius_free.restype = None
@@ -298,11 +300,18 @@ class Index:
 
     def bf16_lower_bounds(self, Q):
         """B x N batched-distance lower bounds (leaf order) from the BF16 MFMA kernel."""
+        return self._prune_lower_bounds(Q, load().sofa_bf16_lower_bounds)
+
+    def fp8_lower_bounds(self, Q):
+        """B x N batched-distance lower bounds (leaf order) from the FP8 MFMA kernel."""
+        return self._prune_lower_bounds(Q, load().sofa_fp8_lower_bounds)
+
+    def _prune_lower_bounds(self, Q, fn):
         import torch
         B = Q.shape[0]
         N = self.info()["N"]
         LB = torch.empty((B, N), dtype=torch.float32, device=Q.device)
-        _check(load().sofa_bf16_lower_bounds(self._h, _dev(Q, torch.float32), B, _dev(LB), _stream()))
+        _check(fn(self._h, _dev(Q, torch.float32), B, _dev(LB), _stream()))
         return LB
 
     def __del__(self):

@@ -422,6 +422,118 @@ def test_bf16_argument_errors(gpu_lib):
 
 
 # --------------------------------------------------------------------------- #
+# FP8 (e4m3) tier
+def _fp8_index(gpu_lib, X, m=2000, L=256, precision=2):
+    bins = _bins(gpu_lib, X, m)
+    return bins, gpu_lib.Index(bins, _t(X), leaf_size=L, precision=precision)
+
+
+def test_fp8_lower_bounds_never_exceed_distance(gpu_lib):
+    """The FP8 MFMA bound is below the FP64 distance on every pair: near
+    copies, a row that sets its chunk's scale, rows in the e4m3 subnormal
+    range, values half-way between e4m3 codes."""
+    N, n, B = 4096 + 17, 256, 40
+    X = synth.collection(N, n, "mix", seed=251)
+    rng = np.random.default_rng(6)
+    X[10] *= np.float32(300.0)                       # sets chunk 0's scale
+    X[11] *= np.float32(1e-5)                        # subnormal after scaling
+    X[300] *= np.float32(2e-3)
+    # half-way values of the e4m3 grid (for a unit scale): 1 + 1/16 lies
+    # between the codes 1 and 1 + 1/8
+    X[600] = np.where(np.arange(n) % 2 == 0, 1.0625, -1.0625).astype(np.float32)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=252)
+    Q[0] = X[7]
+    Q[1] = X[8] + np.float32(1e-4) * rng.standard_normal(n).astype(np.float32)
+    Q[2] = X[10] * np.float32(1.0001)
+    Q[3] = X[11]
+    Q[4] = X[600]
+    Q[5] = X[300] * np.float32(1e3)
+    bins, ix = _fp8_index(gpu_lib, X)
+    assert ix.info()["has_fp8"] == 1
+    LB = ix.fp8_lower_bounds(_t(Q)).cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    ids = ids.cpu().numpy()
+    Xd = X.astype(np.float64)[ids]
+    rel = []
+    for b in range(B):
+        d2 = np.sum((Xd - Q[b].astype(np.float64)) ** 2, axis=1)
+        assert np.all(LB[b] <= d2 * (1 + 1e-12) + 1e-30), (b, float(np.max(LB[b] - d2)))
+        rel.append((d2 - LB[b]) / np.maximum(d2, 1.0))
+    # e4m3 keeps 3 fraction bits: the slack is a few percent of |q||x| on
+    # typical pairs, far below the distance between unrelated series
+    assert np.median(np.concatenate(rel)) < 0.2
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_fp8_knn_matches_oracle(gpu_lib, k):
+    N, n, B = 30000 + 11, 256, 48
+    X = synth.collection(N, n, "mix", seed=261)
+    X[1000] = X[20]
+    X[29000] = X[20]
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=262)
+    Q[0] = X[20]
+    Q[1] = synth.collection(1, n, "hf", seed=4331)[0]
+    bins, ix = _fp8_index(gpu_lib, X, precision=3)
+    ids, d = ix.knn(_t(Q), k, prune=2)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    st = ix.stats()
+    assert st["series_bf16_checked"] > 0
+    assert st["overflow_fallbacks"] == 0
+    # the BF16 tier of the same index gives the same answer
+    ids1, d1 = ix.knn(_t(Q), k, prune=1)
+    assert np.array_equal(ids1.cpu().numpy(), ids.cpu().numpy())
+
+
+def test_fp8_knn_radius_and_capacity_paths(gpu_lib):
+    N, n, B, k = 40000, 256, 40, 10
+    X = synth.collection(N, n, "mix", seed=271)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=272)
+    bins, ix = _fp8_index(gpu_lib, X, L=512)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    kth = np.sqrt(ref_d2[:, -1]).astype(np.float32)
+    for radius in (None, np.full(B, 1e-3, np.float32), np.full(B, 1e3, np.float32),
+                   kth * np.float32(1.0005), kth * np.float32(0.999)):
+        for sampling in (0, 2):
+            ids, d = ix.knn(_t(Q), k, prune=2, sampling=sampling,
+                            radius=None if radius is None else _t(radius))
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    ids, d = ix.knn(_t(Q), k, prune=2, candidate_capacity=8)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    assert ix.stats()["overflow_fallbacks"] > 0
+
+
+def test_fp8_lengths_64_to_512(gpu_lib):
+    for n, N in ((64, 9000 + 7), (128, 7000 + 3), (512, 6000 + 5)):
+        X = synth.collection(N, n, "mix", seed=281 + n)
+        Q, _ = synth.queries(X, 20, sigma=0.1, seed=282)
+        bins = _bins(gpu_lib, X, 2000, pool=min(16, n // 2 - 1))
+        ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=2)
+        for k in (1, 9):
+            ids, d = ix.knn(_t(Q), k, prune=2)
+            ref_ids, ref_d2 = oracle.knn(X, Q, k)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
+def test_fp8_argument_errors(gpu_lib):
+    X = synth.collection(3000, 256, "rw", seed=291)
+    bins = _bins(gpu_lib, X, 1000)
+    bf = gpu_lib.Index(bins, _t(X), precision=1)
+    with pytest.raises(gpu_lib.SofaError):
+        bf.knn(_t(X[:2]), 1, prune=2)
+    with pytest.raises(gpu_lib.SofaError):
+        bf.fp8_lower_bounds(_t(X[:2]))
+    with pytest.raises(gpu_lib.SofaError):
+        bf.knn(_t(X[:2]), 1, prune=3)
+    with pytest.raises(gpu_lib.SofaError):
+        gpu_lib.Index(bins, _t(X), leaf_size=64, precision=2)
+    X10 = synth.collection(2000, 1024, "rw", seed=292)
+    b10 = _bins(gpu_lib, X10, 1000)
+    with pytest.raises(gpu_lib.SofaError):
+        gpu_lib.Index(b10, _t(X10), precision=2)
+
+
+# --------------------------------------------------------------------------- #
 # learned radius network
 def _mlp_params(seed, D=32, H1=256, H2=256):
     rng = np.random.default_rng(seed)
