@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--train-queries", type=int, default=1_000_000,
                     help="noisy-copy training queries for the radius network")
     ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--quantile", type=float, default=0.999)
+    ap.add_argument("--quantile", type=float, default=0.9999)
     ap.add_argument("--headline", default="learned_bf16",
                     help="path whose k-NN rate is the reported value")
     args = ap.parse_args()

@@ -6,6 +6,8 @@ valid for the exact value within that bound; lower bounds never above the
 FP64 distance; neighbour ids bit-identical to the oracle's (distance, id)
 ranking; distances within 1e-6 relative of sqrt(FP64 d^2).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -419,6 +421,29 @@ def test_bf16_argument_errors(gpu_lib):
     b5 = _bins(gpu_lib, X5, 1000)
     with pytest.raises(gpu_lib.SofaError):
         gpu_lib.Index(b5, _t(X5), precision=1)
+
+
+# --------------------------------------------------------------------------- #
+# stored oracle answers (tests/golden, written from the oracle alone)
+def test_golden_small_rw64(gpu_lib):
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "small_rw64.json")) as f:
+        g = json.load(f)
+    c = g["case"]
+    X = synth.collection(c["N"], c["n"], c["kind"], seed=c["seed"])
+    Q, _ = synth.queries(X, c["B"], sigma=c["sigma"], seed=c["qseed"])
+    bins = _bins(gpu_lib, X, c["m"], alpha=c["alpha"], binning=c["binning"], pool=c["P"])
+    info = bins.get()
+    assert info["sel"].tolist() == g["sel"]
+    ref_beta = np.array([[float.fromhex(v) for v in row] for row in g["beta_hex"]])
+    assert np.max(np.abs(info["beta"] - ref_beta)) <= 1e-12 * np.max(np.abs(ref_beta))
+    ref_d = np.sqrt(np.array([[float.fromhex(v) for v in row] for row in g["knn_d2_hex"]]))
+    for prec, prune in ((0, 0), (3, 1), (3, 2)):
+        ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=prec)
+        ids, d = ix.knn(_t(Q), c["k"], prune=prune)
+        assert ids.cpu().numpy().tolist() == g["knn_ids"], prune
+        assert np.all(np.abs(d.cpu().numpy() - ref_d) <= 1e-6 * ref_d)
 
 
 # --------------------------------------------------------------------------- #
