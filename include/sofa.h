@@ -346,6 +346,67 @@ sofa_status sofa_bf16_lower_bounds(const sofa_index* index, const float* d_queri
 sofa_status sofa_fp8_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
                                   float* d_lb, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching (not part of the paper,
+ * which answers one query at a time, Section V; the loop only schedules
+ * sofa_knn calls, so every answer is the exact one).
+ *
+ * Requests carry one query each, for any registered collection and any k.
+ * They wait in a queue per (collection, k).  `slots` batches run at once,
+ * each on its own HIP stream (default priority) with its own workspace and
+ * host thread, so their kernels overlap on the device.  A free slot takes
+ * the queue whose oldest request is oldest overall, up to max_batch of its
+ * requests, and admits the batch only if its workspace bytes
+ * (sofa_workspace_bytes_for) fit in memory_budget beside the batches in
+ * flight: otherwise it halves the batch, then waits for memory to free.  A
+ * query that alone exceeds the budget fails with SOFA_ENOMEM.  Requests
+ * that arrive while batches run join the next batch of their queue.  A
+ * result does not depend on the batch it ran in.
+ *
+ * The indexes and radius models stay owned by the caller and must outlive
+ * the server.  Threads: submit and wait may be called from any thread. */
+typedef struct sofa_server sofa_server;
+
+typedef struct {
+  int32_t slots;         /* concurrent batches (default 4, at most 16) */
+  int32_t max_batch;     /* queries per batch (default 256) */
+  int64_t memory_budget; /* device bytes for the workspaces of the batches in
+                          * flight (default 8 GiB); each slot's workspace
+                          * keeps the capacity of its largest batch */
+} sofa_server_params;
+
+typedef struct {
+  int64_t submitted, completed, batches;
+  int64_t max_batch;             /* largest batch run */
+  int64_t in_flight_bytes_peak;  /* largest sum of admitted workspace bytes */
+  int64_t memory_waits;          /* batches halved or delayed for memory */
+  double busy_ms;                /* summed wall time of the batches */
+} sofa_server_stats;
+
+sofa_status sofa_server_create(const sofa_server_params* params, sofa_server** out);
+/* Registers an index; prune as in sofa_knn_params (the index must hold the
+ * copy).  n <= 1024.  *out_id is the collection id used by submit. */
+sofa_status sofa_server_add_collection(sofa_server* server, const sofa_index* index, int32_t prune,
+                                       int32_t* out_id);
+/* Uses a learned-radius model for the collection's queries with k = the
+ * model's k (queries with other k run without a radius). */
+sofa_status sofa_server_set_model(sofa_server* server, int32_t collection, const sofa_radius* model);
+/* h_query: n FP32 host values (z-normalised), copied before returning.
+ * 1 <= k <= min(N, 100).  *ticket identifies the request. */
+sofa_status sofa_server_submit(sofa_server* server, int32_t collection, const float* h_query,
+                               int32_t k, int64_t* ticket);
+/* Waits for a request (timeout_ms < 0: no limit; SOFA_EBUSY on timeout, the
+ * ticket stays valid) and copies its k ids (int64, original rows) and
+ * distances (FP32, ascending by (distance, id)) to host arrays (either may
+ * be NULL).  times_ms (nullable, 3 doubles): submit-to-result latency,
+ * submit-to-start queueing, size of the batch it ran in.  The ticket is
+ * released on return (except on timeout). */
+sofa_status sofa_server_wait(sofa_server* server, int64_t ticket, int64_t* h_ids, float* h_dists,
+                             double* times_ms, int32_t timeout_ms);
+sofa_status sofa_server_get_stats(sofa_server* server, sofa_server_stats* out);
+/* Finishes the queued requests, stops the slots and frees the server. */
+void sofa_server_free(sofa_server* server);
+
 #ifdef __cplusplus
 }
 #endif

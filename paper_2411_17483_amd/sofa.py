@@ -26,7 +26,9 @@ EXPORTED = [
     "sofa_bf16_lower_bounds", "sofa_fp8_lower_bounds", "sofa_radius_create", "sofa_radius_free", "sofa_radius_num_params",
     "sofa_radius_get", "sofa_radius_set", "sofa_radius_standardize", "sofa_radius_gradients",
     "sofa_radius_train_step", "sofa_radius_fit", "sofa_radius_forward", "sofa_radius_calibrate",
-    "sofa_radius_predict",
+    "sofa_radius_predict", "sofa_server_create", "sofa_server_add_collection",
+    "sofa_server_set_model", "sofa_server_submit", "sofa_server_wait", "sofa_server_get_stats",
+    "sofa_server_free",
 ]
 
 
@@ -77,6 +79,18 @@ class KnnStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("slots", _i32), ("max_batch", _i32), ("memory_budget", _i64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("batches", _i64), ("max_batch", _i64),
+                ("in_flight_bytes_peak", _i64), ("memory_waits", _i64), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def load():
     """Load libsofa.so; raise if it has not been built."""
     global _lib
@@ -110,6 +124,14 @@ def load():
     L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
     L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
     L.sofa_fp8_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.sofa_server_create.argtypes = [ctypes.POINTER(ServerParams), ctypes.POINTER(_vp)]
+    L.sofa_server_add_collection.argtypes = [_vp, _vp, _i32, ctypes.POINTER(_i32)]
+    L.sofa_server_set_model.argtypes = [_vp, _i32, _vp]
+    L.sofa_server_submit.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(_i64)]
+    L.sofa_server_wait.argtypes = [_vp, _i64, _vp, _vp, _vp, _i32]
+    L.sofa_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    L.sofa_server_free.argtypes = [_vp]
+    L.sofa_server_free.restype = None
     L.sofa_radius_create.argtypes = [ctypes.POINTER(RadiusParams), ctypes.POINTER(_vp)]
     L.sofa_radius_free.argtypes = [_vp]
     L.sofa_radius_free.restype = None
@@ -400,3 +422,60 @@ class RadiusModel:
         if _lib is not None and getattr(self, "_h", None) and self._h.value:
             _lib.sofa_radius_free(self._h)
             self._h = _vp()
+
+
+class Server:
+    """The request loop (sofa_server_*): continuous batching of single-query
+    requests over registered indexes, admitted by workspace memory, run on
+    `slots` streams.  Keeps references to the indexes and models it serves."""
+
+    def __init__(self, slots=4, max_batch=256, memory_budget=8 << 30):
+        h = _vp()
+        p = ServerParams(int(slots), int(max_batch), int(memory_budget))
+        _check(load().sofa_server_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self._n = []
+
+    def add_collection(self, index, prune=0):
+        cid = _i32()
+        _check(load().sofa_server_add_collection(self._h, index._h, int(prune), ctypes.byref(cid)))
+        self._keep.append(index)
+        self._n.append(index.info()["n"])
+        return cid.value
+
+    def set_model(self, collection, model):
+        _check(load().sofa_server_set_model(self._h, int(collection), model._h))
+        self._keep.append(model)
+
+    def submit(self, collection, query, k):
+        """query: n FP32 values (host array).  Returns a ticket."""
+        q = np.ascontiguousarray(query, dtype=np.float32)
+        if 0 <= collection < len(self._n) and q.shape != (self._n[collection],):
+            raise ValueError(f"query must have {self._n[collection]} values")
+        t = _i64()
+        _check(load().sofa_server_submit(self._h, int(collection), q.ctypes.data, int(k),
+                                         ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket, k, timeout_ms=-1):
+        """(ids int64[k], dists float32[k], (latency_ms, queue_ms, batch_size))."""
+        ids = np.empty(k, dtype=np.int64)
+        d = np.empty(k, dtype=np.float32)
+        tm = np.zeros(3, dtype=np.float64)
+        _check(load().sofa_server_wait(self._h, int(ticket), ids.ctypes.data, d.ctypes.data,
+                                       tm.ctypes.data, int(timeout_ms)))
+        return ids, d, (float(tm[0]), float(tm[1]), int(tm[2]))
+
+    def stats(self):
+        s = ServerStats()
+        _check(load().sofa_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
+            _lib.sofa_server_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        self.close()
