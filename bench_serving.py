@@ -107,11 +107,13 @@ def run_level(srv, cids, pools, qps, duration, seed, ks=(1, 10, 100)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--qps", default="500,1500,4000")
+    ap.add_argument("--qps", default="100,400,1500,4000")
     ap.add_argument("--duration", type=float, default=6.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=256)
     ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--per-collection", type=int, default=1,
+                    help="batches of one collection in flight at once")
     ap.add_argument("--check", type=int, default=60, help="requests checked alone vs in the mix")
     args = ap.parse_args()
 
@@ -130,7 +132,7 @@ def main():
             f"{ix.info()['device_bytes'] / 1e9:.1f} GB")
 
     srv = sofa.Server(slots=args.slots, max_batch=args.max_batch,
-                      memory_budget=int(args.budget_gb * (1 << 30)))
+                      memory_budget=int(args.budget_gb * (1 << 30)), per_collection=args.per_collection)
     cids = [srv.add_collection(ix, prune) for _, ix, _, prune in colls]
     pools = [Q for _, _, Q, _ in colls]
     # warm-up: every (collection, k) once
@@ -160,6 +162,7 @@ def main():
     out = {"metric": "serving p50/p99 latency and queries/s, 3 HBM-resident collections, "
                      "Poisson arrivals, k in {1,10,100}",
            "collections": build, "slots": args.slots, "max_batch": args.max_batch,
+           "per_collection": args.per_collection,
            "memory_budget_gb": args.budget_gb, "alone_equals_mix": same, "checked": len(sub),
            "levels": levels, "server_stats": st}
     print(json.dumps(out), flush=True)

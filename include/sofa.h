@@ -352,16 +352,20 @@ sofa_status sofa_fp8_lower_bounds(const sofa_index* index, const float* d_querie
  * sofa_knn calls, so every answer is the exact one).
  *
  * Requests carry one query each, for any registered collection and any k.
- * They wait in a queue per (collection, k).  `slots` batches run at once,
- * each on its own HIP stream (default priority) with its own workspace and
- * host thread, so their kernels overlap on the device.  A free slot takes
- * the queue whose oldest request is oldest overall, up to max_batch of its
+ * They wait in a queue per collection.  `slots` batches run at once, each on
+ * its own HIP stream (default priority) with its own workspace and host
+ * thread, so their kernels overlap on the device.  A free slot takes, among
+ * the collections with fewer than per_collection batches in flight, the
+ * queue whose oldest request is oldest overall, up to max_batch of its
  * requests, and admits the batch only if its workspace bytes
  * (sofa_workspace_bytes_for) fit in memory_budget beside the batches in
  * flight: otherwise it halves the batch, then waits for memory to free.  A
  * query that alone exceeds the budget fails with SOFA_ENOMEM.  Requests
- * that arrive while batches run join the next batch of their queue.  A
- * result does not depend on the batch it ran in.
+ * that arrive while batches run join the next batch of their collection.
+ * A batch runs at the largest k of its requests and each request keeps its
+ * first k results, which are exactly its own k nearest (the ranking is the
+ * total order on (distance, id)): a result does not depend on the batch it
+ * ran in.
  *
  * The indexes and radius models stay owned by the caller and must outlive
  * the server.  Threads: submit and wait may be called from any thread. */
@@ -373,6 +377,7 @@ typedef struct {
   int64_t memory_budget; /* device bytes for the workspaces of the batches in
                           * flight (default 8 GiB); each slot's workspace
                           * keeps the capacity of its largest batch */
+  int32_t per_collection; /* batches of one collection in flight (default 1) */
 } sofa_server_params;
 
 typedef struct {

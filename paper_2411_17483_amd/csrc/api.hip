@@ -410,9 +410,21 @@ struct Layout {
   size_t total;
 };
 
-constexpr int kBf16Cap = 32768;  // BF16 candidates per query and pass
-int bf16_cap(const sofa_knn_params* p) {
-  return (p && p->candidate_capacity > 0) ? p->candidate_capacity : kBf16Cap;
+// Candidate slots per query and pass of the batched-distance prune.  The
+// FP8 bound is looser (3 fraction bits), so its lists are longer: sized so
+// that a pass rarely overflows into the retry and exhaustive paths.
+// The FP8 lists of a batch are kept within 2 GiB (never below the BF16 size).
+constexpr int kBf16Cap = 32768;
+constexpr int kFp8Cap = 1 << 18, kFp8CapLargeK = 1 << 20;
+constexpr int64_t kFp8ListBytes = 1ll << 31;
+int bf16_cap(const sofa_knn_params* p, int k, int64_t B) {
+  if (p && p->candidate_capacity > 0) return p->candidate_capacity;
+  if (p && p->prune == 2) {
+    const int64_t want = k > 16 ? kFp8CapLargeK : kFp8Cap;
+    const int64_t fit = kFp8ListBytes / 4 / std::max<int64_t>(B, 1);
+    return (int)std::max<int64_t>(kBf16Cap, std::min(want, fit));
+  }
+  return kBf16Cap;
 }
 // no-radius BF16 search: chunk samples of stride 1024, then 32, then the
 // rest, each pass pruning with the bound the previous passes established
@@ -440,7 +452,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_BAD] = 4;
   sz[W_HIST] = (size_t)B * 256 * 4;
   sz[W_HBASE] = (size_t)B * 4;
-  sz[W_CAND] = bf ? (size_t)B * bf16_cap(p) * 4 : 0;
+  sz[W_CAND] = bf ? (size_t)B * bf16_cap(p, k, B) * 4 : 0;
   sz[W_CCNT] = bf ? (size_t)B * 4 : 0;
   sz[W_CEV] = bf ? (size_t)B * 4 : 0;
   sz[W_QCNT] = bf ? (size_t)B * 4 : 0;
@@ -622,7 +634,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.cand = (uint32_t*)at(W_CAND);
     b.ccnt = (uint32_t*)at(W_CCNT);
     b.cevmin = cev;
-    b.cap = bf16_cap(p);
+    b.cap = bf16_cap(p, k, B);
     b.counter = (uint32_t*)at(W_BCTR);
     SOFA_TRY(launch_bf16_queries(a, b, st));
     const int64_t n_chunks = (ix->N + 255) / 256;

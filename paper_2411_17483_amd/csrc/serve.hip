@@ -2,19 +2,24 @@
 // over HBM-resident indexes.
 //
 // Requests (one query each, any registered collection, any k) wait in a
-// queue per (collection, k).  A fixed number of slots run batches; each slot
-// owns a HIP stream (default priority), a workspace, pinned staging buffers
-// and a host thread, so batches on different slots overlap on the device.
-// Whenever a slot is free it takes the queue whose oldest request is the
+// queue per collection.  A fixed number of slots run batches; each slot owns
+// a HIP stream (default priority), a workspace, pinned staging buffers and a
+// host thread, so batches on different slots overlap on the device.
+// Whenever a slot is free it takes, among the collections with fewer than
+// `per_collection` batches in flight, the queue whose oldest request is the
 // oldest overall, up to max_batch requests of it, and admits the batch only
 // if its workspace bytes fit beside the batches already in flight (halving
 // the batch, then waiting for memory to free up).  Requests that arrive
-// while batches run are picked up by the next free slot: batching is
-// continuous, not a queue in front of one batch at a time.
+// while batches run join the next batch of their collection: batching is
+// continuous, not a queue in front of one batch at a time.  A batch of a
+// large collection costs about one pass over its rows whatever its size, so
+// limiting the batches in flight per collection makes the batches larger
+// instead of running many small passes side by side.
 //
-// A query's answer does not depend on the batch it ran in: every batch
-// returns the exact (distance, id) ranking, so a result is the same alone
-// and in any mix.
+// A batch runs at the largest k of its requests and each request keeps its
+// first k results: the ranking is the total order on (distance, id), so
+// those are exactly its own k nearest.  A query's answer therefore does not
+// depend on the batch it ran in, and is the same alone and in any mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -72,13 +77,15 @@ struct sofa_server {
 
   int device = 0;
   int max_batch = 256;
+  int per_coll = 1;
   int64_t budget = 0;
   std::vector<Coll> colls;
   std::vector<Slot> slots;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_mem;
-  std::map<std::pair<int, int>, std::deque<Req*>> pending;
+  std::map<int, std::deque<Req*>> pending;  // per collection
+  std::map<int, int> busy;                  // batches in flight per collection
   std::unordered_map<int64_t, Req*> reqs;
   int64_t next_ticket = 1;
   int64_t in_flight_bytes = 0;
@@ -102,18 +109,32 @@ void sofa_server::worker(int si) {
   Slot& sl = slots[si];
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_work.wait(lk, [&] { return stop || !pending.empty(); });
-    if (pending.empty()) {
-      if (stop) break;
+    // a collection with a request and room for another batch in flight
+    auto eligible = [&]() {
+      auto best = pending.end();
+      for (auto it = pending.begin(); it != pending.end(); ++it) {
+        if (busy[it->first] >= per_coll) continue;
+        if (best == pending.end() || it->second.front()->t_submit < best->second.front()->t_submit)
+          best = it;
+      }
+      return best;
+    };
+    cv_work.wait(lk, [&] { return (stop && pending.empty()) || eligible() != pending.end(); });
+    auto best = eligible();
+    if (best == pending.end()) {
+      if (stop && pending.empty()) break;
       continue;
     }
-    // the queue whose head request is the oldest
-    auto best = pending.begin();
-    for (auto it = pending.begin(); it != pending.end(); ++it)
-      if (it->second.front()->t_submit < best->second.front()->t_submit) best = it;
-    const int ci = best->first.first, k = best->first.second;
+    const int ci = best->first;
     const Coll c = colls[ci];  // a copy: colls may grow once the lock is released
     int b = (int)std::min<size_t>(best->second.size(), (size_t)max_batch);
+    // the batch runs at the largest k among its requests
+    auto kmax = [&](int cnt) {
+      int km = 1;
+      for (int i = 0; i < cnt; i++) km = std::max(km, best->second[i]->k);
+      return km;
+    };
+    int k = kmax(b);
     int64_t need = 0;
     bool admitted = false;
     for (;;) {
@@ -124,6 +145,7 @@ void sofa_server::worker(int si) {
       }
       if (b > 1) {
         b = std::max(1, b / 2);
+        k = kmax(b);
         stats.memory_waits++;
         continue;
       }
@@ -152,6 +174,7 @@ void sofa_server::worker(int si) {
     best->second.erase(best->second.begin(), best->second.begin() + b);
     if (best->second.empty()) pending.erase(best);
     in_flight_bytes += need;
+    busy[ci]++;
     stats.batches++;
     stats.max_batch = std::max<int64_t>(stats.max_batch, b);
     stats.in_flight_bytes_peak = std::max(stats.in_flight_bytes_peak, in_flight_bytes);
@@ -189,17 +212,20 @@ void sofa_server::worker(int si) {
       r->st = st;
       r->err = err;
       if (st == SOFA_OK) {
-        r->ids.assign(sl.hids + (size_t)i * k, sl.hids + (size_t)(i + 1) * k);
-        r->d.assign(sl.hd + (size_t)i * k, sl.hd + (size_t)(i + 1) * k);
+        // the first r->k of the batch's k results
+        r->ids.assign(sl.hids + (size_t)i * k, sl.hids + (size_t)i * k + r->k);
+        r->d.assign(sl.hd + (size_t)i * k, sl.hd + (size_t)i * k + r->k);
       }
       r->t_done = t1;
       r->done = true;
     }
     in_flight_bytes -= need;
+    busy[ci]--;
     stats.completed += b;
     stats.busy_ms += t1 - t0;
     cv_done.notify_all();
     cv_mem.notify_all();
+    cv_work.notify_all();  // the collection may take another batch now
   }
 }
 
@@ -209,10 +235,12 @@ extern "C" sofa_status sofa_server_create(const sofa_server_params* params, sofa
   const int n_slots = params && params->slots > 0 ? params->slots : 4;
   const int max_batch = params && params->max_batch > 0 ? params->max_batch : 256;
   const int64_t budget = params && params->memory_budget > 0 ? params->memory_budget : (8ll << 30);
+  const int per_coll = params && params->per_collection > 0 ? params->per_collection : 1;
   if (n_slots > 16) return set_error(SOFA_EINVAL, "slots=%d above 16", n_slots);
   if (max_batch > 65535) return set_error(SOFA_EINVAL, "max_batch=%d above 65535", max_batch);
   sofa_server* s = new sofa_server();
   s->max_batch = max_batch;
+  s->per_coll = per_coll;
   s->budget = budget;
   (void)hipGetDevice(&s->device);
   s->slots.resize(n_slots);
@@ -280,7 +308,7 @@ extern "C" sofa_status sofa_server_submit(sofa_server* s, int32_t coll, const fl
   r->q.assign(h_query, h_query + ix->n);
   r->t_submit = now_ms();
   s->reqs[r->ticket] = r;
-  s->pending[{coll, k}].push_back(r);
+  s->pending[coll].push_back(r);
   s->stats.submitted++;
   s->start();
   s->cv_work.notify_one();

@@ -80,7 +80,8 @@ class KnnStats(ctypes.Structure):
 
 
 class ServerParams(ctypes.Structure):
-    _fields_ = [("slots", _i32), ("max_batch", _i32), ("memory_budget", _i64)]
+    _fields_ = [("slots", _i32), ("max_batch", _i32), ("memory_budget", _i64),
+                ("per_collection", _i32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -429,9 +430,9 @@ class Server:
     requests over registered indexes, admitted by workspace memory, run on
     `slots` streams.  Keeps references to the indexes and models it serves."""
 
-    def __init__(self, slots=4, max_batch=256, memory_budget=8 << 30):
+    def __init__(self, slots=4, max_batch=256, memory_budget=8 << 30, per_collection=1):
         h = _vp()
-        p = ServerParams(int(slots), int(max_batch), int(memory_budget))
+        p = ServerParams(int(slots), int(max_batch), int(memory_budget), int(per_collection))
         _check(load().sofa_server_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self._keep = []
