@@ -37,6 +37,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bf16_tiles_10Mx256_k10_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes of the BF16 tile kernel per search from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE, calibrated on a copy of known size), or
+    (None, reason) when the kernel's source has changed since it was taken."""
+    import hashlib
+    try:
+        line = [l for l in open(TRAFFIC_PROFILE) if l.startswith("traffic_json: ")][0]
+        t = json.loads(line[len("traffic_json: "):])
+        src = open(os.path.join(ROOT, t["source"]), "rb").read()
+    except (OSError, IndexError, ValueError, KeyError):
+        return None, "no counter summary"
+    if hashlib.sha256(src).hexdigest() != t["sha256"]:
+        return None, "kernel changed since the counters were taken"
+    return t["bytes_per_search"], (f"profiles/{os.path.basename(TRAFFIC_PROFILE)}: {t['workload']}, "
+                                   f"FETCH_SIZE x {t['fetch_factor']:.4f} + WRITE_SIZE x {t['write_factor']:.4f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +79,11 @@ def main():
     ap.add_argument("--quantile", type=float, default=0.9999)
     ap.add_argument("--headline", default="learned_bf16",
                     help="path whose k-NN rate is the reported value")
+    ap.add_argument("--no-radius", action="store_true",
+                    help="skip the radius networks and the learned paths (short profiling runs)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -94,14 +119,23 @@ def main():
     # of noisy-copy training queries (own seed).  The labels come from the
     # BF16-prune search, which returns the same exact neighbours as the plain
     # search (checked below on the benchmark batch) in a fraction of the time.
+    if args.copy_probe_mb > 0:
+        a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"copy probe: {args.copy_probe_mb} MiB read, {args.copy_probe_mb} MiB written")
+
     t0 = time.perf_counter()
-    ntr = args.train_queries
-    Qtr, _ = synth.queries(X, ntr, sigma=0.1, seed=args.seed + 2)
-    Qtr_d = torch.from_numpy(Qtr).to(dev)
-    feat, _, _ = bins.transform(Qtr_d, sel=False, words=False)
-    n_fit = ntr - min(10000, ntr // 10)
+    ntr = 0 if args.no_radius else args.train_queries
     models, model_info = {}, {}
-    for kk in (k, 1):
+    if ntr > 0:
+        Qtr, _ = synth.queries(X, ntr, sigma=0.1, seed=args.seed + 2)
+        Qtr_d = torch.from_numpy(Qtr).to(dev)
+        feat, _, _ = bins.transform(Qtr_d, sel=False, words=False)
+        n_fit = ntr - min(10000, ntr // 10)
+    for kk in ((k, 1) if ntr > 0 else ()):
         lab = []
         for i in range(0, ntr, 4096):
             _, dd = ix.knn(Qtr_d[i:i + 4096].contiguous(), kk, prune=1)
@@ -123,13 +157,16 @@ def main():
         log(f"radius model k={kk}: loss {losses[0]:.4f} -> {losses[-1]:.4f}, held-out rmse "
             f"{model_info[f'k{kk}']['heldout_rmse']:.4f}, margin {m.get()['margin']:.4f}")
     t_train = time.perf_counter() - t0
-    del Qtr_d, feat
-    log(f"radius training {t_train:.1f}s")
+    if ntr > 0:
+        del Qtr_d, feat
+        log(f"radius training {t_train:.1f}s")
 
     paths = {"plain": dict(prune=0), "bf16": dict(prune=1), "fp8": dict(prune=2),
              "learned_bf16": dict(prune=1, model="learned", sampling=1),
              "learned_bf16_1pass": dict(prune=1, model="learned", sampling=2),
              "learned_fp8": dict(prune=2, model="learned", sampling=1)}
+    if args.no_radius:
+        paths = {name: kw for name, kw in paths.items() if kw.get("model") != "learned"}
     headline = args.headline
     if headline not in paths:
         raise SystemExit(f"unknown headline path {headline}")
@@ -215,8 +252,12 @@ def main():
         ms = stg["ms_bf16_tiles"]
         ach = flops / (ms * 1e-3)
         peak = PEAK_FP8_MFMA if paths[headline]["prune"] == 2 else PEAK_BF16_MFMA
+        traffic, traffic_src = None, None
+        if paths[headline]["prune"] == 1:
+            traffic, traffic_src = measured_traffic()
         roofline = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                    "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
+                    "traffic_source": traffic_src,
                     "kernel": "k_bf16_tiles", "ms_per_launch": ms,
                     "work_per_launch": {"flop": flops, "pairs_needed": pairs,
                                         "pairs_computed": cnt["series_bf16_checked"]}}
