@@ -535,10 +535,79 @@ struct ChunkState {
   float xmin[2];
 };
 
+// max of the 16 accumulators of a lane's fragment, as a depth-3 tree
+__device__ __forceinline__ float max16(const f16v& v) {
+  auto mx3 = [](float x, float y, float z) { return fmaxf(fmaxf(x, y), z); };
+  const float m0 = mx3(v[0], v[1], v[2]), m1 = mx3(v[3], v[4], v[5]), m2 = mx3(v[6], v[7], v[8]);
+  const float m3 = mx3(v[9], v[10], v[11]), m4 = mx3(v[12], v[13], v[14]);
+  return fmaxf(mx3(m0, m1, m2), mx3(m3, m4, v[15]));
+}
+
+// epilogue of one 32-query column block: D[i][j] with j = lane%32 (query),
+// i = 8(e/4) + 4(lane/32) + e%4 (row of the row block r)
+template <int PREC, bool DUMP>
+__device__ __forceinline__ void col_epilogue(const SearchArgs& a, const Bf16Args& b, const ChunkState& cs,
+                                             const float* xn2s, int g, int cb, int q, float cq, bool mbit,
+                                             float f, const f16v& acc0, const f16v& acc1) {
+  const int wave = cs.wave, lane = cs.lane;
+  if (DUMP) {
+    // inspection: the lower bound t - o of every pair
+    const float4 qm = b.qmeta[g * kGroup + cb * 32 + (lane & 31)];
+    const float o = -qm.x + 2.0f * (cs.gam * qm.z + qm.y) * cs.lmx.x + 2.0f * qm.w * cs.lmx.y +
+                    (qm.x + cs.lmx.z) * 0x1p-20f;
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+        const float t = fmaf(-f, r ? acc1[e] : acc0[e], xn2s[ri]);
+        if (cs.c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + cs.c0 + ri] = t - o;
+      }
+    return;
+  }
+  const bool any = fmaf(-f, max16(acc0), cs.xmin[0]) <= cq || fmaf(-f, max16(acc1), cs.xmin[1]) <= cq;
+  if (!__ballot(mbit && any)) return;
+  // rare: exact per-pair test and one append atomic per lane
+  uint32_t hits[2];
+#pragma unroll
+  for (int r = 0; r < 2; r++) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+      h |= fmaf(-f, r ? acc1[e] : acc0[e], xn2s[ri]) <= cq ? (1u << e) : 0u;
+    }
+    hits[r] = h;
+  }
+  const uint32_t nh = mbit ? (uint32_t)(__popc(hits[0]) + __popc(hits[1])) : 0u;
+  if (nh) {
+    uint32_t slot = atomicAdd(b.ccnt + q, nh);
+    bool dropped = false;
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      uint32_t h = hits[r];
+      while (h) {
+        const int e = __builtin_ctz(h);
+        h &= h - 1;
+        const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+        if (slot < (uint32_t)b.cap)
+          b.cand[(int64_t)q * b.cap + slot] = (uint32_t)(cs.c0 + ri);
+        else
+          dropped = true;
+        slot++;
+      }
+    }
+    // a dropped candidate: the query is finished exhaustively
+    if (dropped && b.cevmin[q] != 0u) atomicMin(b.cevmin + q, 0u);
+  }
+}
+
 // one group: thresholds from the terms loaded one group ahead, prefetch of
-// the next group (gn; the current one again when gn < 0, unused), the two
-// column blocks, and the barrier that publishes the next buffer
-template <int PREC, int KS, bool DUMP>
+// the next group (gn; the current one again when gn < 0, unused), the
+// column blocks, and the barrier that publishes the next buffer.  JOINT:
+// both column blocks' MFMAs interleaved (4 per pair of fragment reads, 64
+// accumulators), for one wave per SIMD; otherwise one block after the other.
+template <int PREC, int KS, bool DUMP, bool JOINT>
 __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& b,
                                            const ChunkState& cs,
                                            const typename TileTraits<PREC>::frag (&av)[2][KS],
@@ -556,84 +625,46 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
   const int gp = gn >= 0 ? gn : g;
   stage_group<PREC, KS>(b, gp, wave, lane, nxt);
   load_cols<PREC>(b, cs.blk, gp, lane, cols);
-#pragma unroll
-  for (int cb = 0; cb < 2; cb++) {
-    // this lane's query column: threshold cq on t = |x|^2 - f P
-    const int q = cb ? q1 : q0;
-    const float cq = cb ? cq1 : cq0;
-    const bool mbit = cb ? mb1 : mb0;
-    const float f = cb ? f1 : f0;
-    // a 32-query block with no surviving (query, leaf) pair is skipped
-    if (!DUMP && !__ballot(mbit)) continue;
-    st_pairs += 64 * 32;
-    f16v acc[2];
+  // a 32-query block with no surviving (query, leaf) pair is skipped
+  const bool act0 = DUMP || __ballot(mb0), act1 = DUMP || __ballot(mb1);
+  if (JOINT && act0 && act1) {
+    f16v acc[2][2];
 #pragma unroll
     for (int r = 0; r < 2; r++)
 #pragma unroll
-      for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) acc[r][c][e] = 0.0f;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      const auto bq = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
-      acc[0] = mma<PREC>(av[0][ks], bq, acc[0]);
-      acc[1] = mma<PREC>(av[1][ks], bq, acc[1]);
+      const auto b0 = load_frag<PREC>(cur + (0 * KS + ks) * 64 * H + lane);
+      const auto b1 = load_frag<PREC>(cur + (1 * KS + ks) * 64 * H + lane);
+      acc[0][0] = mma<PREC>(av[0][ks], b0, acc[0][0]);
+      acc[1][0] = mma<PREC>(av[1][ks], b0, acc[1][0]);
+      acc[0][1] = mma<PREC>(av[0][ks], b1, acc[0][1]);
+      acc[1][1] = mma<PREC>(av[1][ks], b1, acc[1][1]);
     }
-    // D[i][j]: j = lane%32 (query), i = 8(e/4) + 4(lane/32) + e%4 (row)
-    if (DUMP) {
-      // inspection: the lower bound t - o of every pair
-      const float4 qm = b.qmeta[g * kGroup + cb * 32 + (lane & 31)];
-      const float o = -qm.x + 2.0f * (cs.gam * qm.z + qm.y) * cs.lmx.x + 2.0f * qm.w * cs.lmx.y +
-                      (qm.x + cs.lmx.z) * 0x1p-20f;
+    st_pairs += 64 * 64;
+    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, 0, q0, cq0, mb0, f0, acc[0][0], acc[1][0]);
+    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, 1, q1, cq1, mb1, f1, acc[0][1], acc[1][1]);
+  } else {
+#pragma unroll
+    for (int cb = 0; cb < 2; cb++) {
+      if (!(cb ? act1 : act0)) continue;
+      st_pairs += 64 * 32;
+      f16v acc[2];
 #pragma unroll
       for (int r = 0; r < 2; r++)
 #pragma unroll
-        for (int e = 0; e < 16; e++) {
-          const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-          const float t = fmaf(-f, acc[r][e], xn2s[ri]);
-          if (cs.c0 + ri < a.N && q >= 0) b.dump[(int64_t)q * a.N + cs.c0 + ri] = t - o;
-        }
-      continue;
-    }
-    bool any = false;
+        for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
-      float m = acc[r][0];
-#pragma unroll
-      for (int e = 1; e < 16; e++) m = fmaxf(m, acc[r][e]);
-      any |= fmaf(-f, m, cs.xmin[r]) <= cq;
-    }
-    if (!__ballot(mbit && any)) continue;
-    // rare: exact per-pair test and one append atomic per lane
-    uint32_t hits[2];
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-      uint32_t h = 0;
-#pragma unroll
-      for (int e = 0; e < 16; e++) {
-        const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-        h |= fmaf(-f, acc[r][e], xn2s[ri]) <= cq ? (1u << e) : 0u;
+      for (int ks = 0; ks < KS; ks++) {
+        const auto bq = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
+        acc[0] = mma<PREC>(av[0][ks], bq, acc[0]);
+        acc[1] = mma<PREC>(av[1][ks], bq, acc[1]);
       }
-      hits[r] = h;
-    }
-    const uint32_t nh = mbit ? (uint32_t)(__popc(hits[0]) + __popc(hits[1])) : 0u;
-    if (nh) {
-      uint32_t slot = atomicAdd(b.ccnt + q, nh);
-      bool dropped = false;
-#pragma unroll
-      for (int r = 0; r < 2; r++) {
-        uint32_t h = hits[r];
-        while (h) {
-          const int e = __builtin_ctz(h);
-          h &= h - 1;
-          const int ri = 64 * wave + 32 * r + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-          if (slot < (uint32_t)b.cap)
-            b.cand[(int64_t)q * b.cap + slot] = (uint32_t)(cs.c0 + ri);
-          else
-            dropped = true;
-          slot++;
-        }
-      }
-      // a dropped candidate: the query is finished exhaustively
-      if (dropped && b.cevmin[q] != 0u) atomicMin(b.cevmin + q, 0u);
+      col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, cb, cb ? q1 : q0, cb ? cq1 : cq0, cb ? mb1 : mb0,
+                               cb ? f1 : f0, acc[0], acc[1]);
     }
   }
   // the next group's fragments have landed; every wave is done with cur
@@ -641,8 +672,8 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
   __syncthreads();
 }
 
-template <int PREC, int KS, bool DUMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+template <int PREC, int KS, bool DUMP, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES)))
 void k_bf16_tiles(SearchArgs a, Bf16Args b) {
   typedef typename TileTraits<PREC>::frag frag;
   constexpr int H = TileTraits<PREC>::kHalves;
@@ -721,21 +752,27 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     // groups alternate between the two buffers
     while (g >= 0) {
       int gn = next_group();
-      group_step<PREC, KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
+      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
       g = gn;
       if (g < 0) break;
       gn = next_group();
-      group_step<PREC, KS, DUMP>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
+      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
       g = gn;
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
 }
 
+// waves per SIMD of the tile kernel: 2 (one column block after the other;
+// the two waves of a SIMD hide each other's epilogues and LDS waits).  1
+// runs both column blocks of a group together with 512 registers per wave;
+// measured slower on 10M x 256 (the lone wave cannot hide its own stalls).
+constexpr int kTileWaves = 2;
+
 // launch over the supported (precision, K steps) pairs
 template <bool DUMP>
 static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, hipStream_t st) {
-#define SOFA_TILE(P, K) k_bf16_tiles<P, K, DUMP><<<grid, 256, 0, st>>>(a, b)
+#define SOFA_TILE(P, K) k_bf16_tiles<P, K, DUMP, kTileWaves><<<grid, 256, 0, st>>>(a, b)
   if (b.prec == 1) {
     switch (a.n_pad / 16) {
       case 4: SOFA_TILE(1, 4); break;
@@ -915,7 +952,7 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   b.n_items = (a.N + 255) / 256;
   SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
   SOFA_TRY(launch_slotc(a, b, st));
-  unsigned grid = 256 * 2;
+  unsigned grid = 256 * kTileWaves;
   if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
   return launch_tiles<true>(a, b, grid, st);
 }
@@ -938,7 +975,7 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
   SOFA_TRY(launch_fill_u32(b.ccnt, 0u, a.B, st));
   // the bounds U of this pass (earlier passes tighten them)
   SOFA_TRY(launch_slotc(a, b, st));
-  unsigned grid = 256 * 2;
+  unsigned grid = 256 * kTileWaves;
   if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
   if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_tiles<false>(a, b, grid, st));
