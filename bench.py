@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published FP32 vector peak
 PEAK_BF16_MFMA = 2.5e15       # FLOP/s, MI355X published dense BF16 matrix peak
 PEAK_FP8_MFMA = 5.0e15        # FLOP/s, MI355X published dense FP8 matrix peak
+PEAK_HBM = 8.0e12             # B/s, MI355X published HBM3E bandwidth
 
 
 def log(*a):
@@ -119,6 +120,22 @@ def main():
     # of noisy-copy training queries (own seed).  The labels come from the
     # BF16-prune search, which returns the same exact neighbours as the plain
     # search (checked below on the benchmark batch) in a fraction of the time.
+    # the SFA word scan alone (16 B word per row, table lookups in LDS, one
+    # FP32 bound written per row and query), as an HBM-bandwidth figure
+    word_scan = []
+    for bq in (1, 2, 4):
+        times = []
+        for _ in range(6):
+            _, lbt, ms = ix.lower_bounds(Qd[:bq].contiguous(), tables=False, lb=True, timed=True)
+            times.append(ms)
+            del lbt
+        ms = float(np.median(times[1:]))
+        nbytes = N * 16 + bq * N * 4
+        word_scan.append({"queries": bq, "ms": ms, "bytes": nbytes, "GB_per_s": nbytes / (ms * 1e6),
+                          "frac_hbm": nbytes / (ms * 1e-3) / PEAK_HBM})
+        log(f"word scan B={bq}: {ms * 1e3:.1f} us, {nbytes / (ms * 1e6):.0f} GB/s")
+    torch.cuda.empty_cache()
+
     if args.copy_probe_mb > 0:
         a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -290,7 +307,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "k": k, "queries": int(len(lat)), "path": headline},
-        "paths": results, "paths_ids_identical": agree,
+        "paths": results, "paths_ids_identical": agree, "word_scan": word_scan,
         "parity_sample": parity,
         "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
         "radius_models": model_info,

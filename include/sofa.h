@@ -202,10 +202,10 @@ typedef struct {
    * smaller value only costs time: when in-band candidates are dropped the
    * query is finished by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
-  /* BF16/FP8 prune only: 0 (default) runs chunk samples of stride 1024 and 32
-   * before the remaining chunks when no radius is given (each pass prunes
-   * with the bound the earlier ones established) and one pass with a radius;
-   * 1 always runs the sampled passes; 2 always runs one pass. */
+  /* BF16/FP8 prune only: 0 (default) and 1 run chunk samples of stride 1024
+   * and 32 before the remaining chunks (each pass prunes with the bound the
+   * earlier ones established, which also tightens a loose radius); 2 runs
+   * one pass over all chunks (best when the radius is tight, e.g. k = 1). */
   int32_t sampling;
 } sofa_knn_params;
 
@@ -253,10 +253,13 @@ sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index
 /* Lower-bound tables and bounds for inspection: for each query, the FP32
  * table T[j][s] = w_j * mind_j(s, v_j)^2 over word position j and symbol s
  * (Eq. 3, widened by the projection error bounds and rounded down), and the
- * word lower bound of every (query, leaf-order row) pair.
- *  d_tables (nullable) B x 16 x 256 FP32;  d_lb (nullable) B x N FP32. */
+ * word lower bound of every (query, leaf-order row) pair: a full scan of the
+ * packed words (16 B per row) with the tables in LDS.
+ *  d_tables (nullable) B x 16 x 256 FP32;  d_lb (nullable) B x N FP32;
+ *  scan_ms (nullable): duration of the word scan kernel alone, from HIP
+ *  events on `stream`.  Synchronous. */
 sofa_status sofa_lower_bounds(const sofa_index* index, const float* d_queries, int64_t B,
-                              float* d_tables, float* d_lb, void* stream);
+                              float* d_tables, float* d_lb, void* stream, double* scan_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Learned radius.  A small network predicts ln(d_k), the logarithm of a

@@ -639,7 +639,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_bf16_queries(a, b, st));
     const int64_t n_chunks = (ix->N + 255) / 256;
     const int sampling = p->sampling;
-    if (sampling == 2 || (sampling == 0 && has_radius)) {
+    if (sampling == 2) {
       SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, st, ev ? ev + 7 : nullptr));
       bf_passes = 1;
     } else {
@@ -797,7 +797,7 @@ sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
 }
 
 extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_queries, int64_t B,
-                                         float* d_tables, float* d_lb, void* stream) {
+                                         float* d_tables, float* d_lb, void* stream, double* scan_ms) {
   if (!ix || B < 0 || (B > 0 && !d_queries)) return set_error(SOFA_EINVAL, "bad arguments");
   if (B == 0) return SOFA_OK;
   hipStream_t st = S(stream);
@@ -826,7 +826,26 @@ extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_qu
                           bad.as<unsigned>(), st));
   if (d_tables)
     SOFA_HIP(hipMemcpyAsync(d_tables, tab.p, (size_t)B * kTable * 4, hipMemcpyDeviceToDevice, st));
-  if (d_lb) SOFA_TRY(launch_all_lb(a, d_lb, st));
+  if (d_lb) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (scan_ms) {
+      SOFA_HIP(hipEventCreate(&e0));
+      SOFA_HIP(hipEventCreate(&e1));
+      SOFA_HIP(hipEventRecord(e0, st));
+    }
+    sofa_status s = launch_all_lb(a, d_lb, st);
+    if (scan_ms) {
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      *scan_ms = ms;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      (void)hipGetLastError();
+    }
+    SOFA_TRY(s);
+  }
   SOFA_HIP(hipStreamSynchronize(st));
   return SOFA_OK;
 }

@@ -454,17 +454,39 @@ __global__ void k_pad_queries(const float* __restrict__ Q, int64_t B, int n, int
 }
 
 // word lower bound of every (query, leaf-order row) pair, for inspection
+template <int QB>
 __global__ __launch_bounds__(256) void k_all_lb(const float* __restrict__ tables,
-                                                const uint8_t* __restrict__ words, int64_t N,
+                                                const uint8_t* __restrict__ words, int64_t N, int B,
                                                 float* __restrict__ out) {
-  __shared__ float T[kTable];
-  const int q = blockIdx.y;
-  const float4* src = reinterpret_cast<const float4*>(tables + (int64_t)q * kTable);
-  for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T)[i] = src[i];
+  // QB queries per workgroup share every word load; their tables sit in LDS
+  __shared__ float T[QB][kTable];
+  const int q0 = blockIdx.y * QB;
+  for (int qq = 0; qq < QB; qq++) {
+    const int q = q0 + qq < B ? q0 + qq : B - 1;
+    const float4* src = reinterpret_cast<const float4*>(tables + (int64_t)q * kTable);
+    for (int i = threadIdx.x; i < kTable / 4; i += 256) reinterpret_cast<float4*>(T[qq])[i] = src[i];
+  }
   __syncthreads();
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256) {
-    uint4 w = *reinterpret_cast<const uint4*>(words + p * kWordBytes);
-    out[(int64_t)q * N + p] = lb_word(T, w);
+  // independent 16-byte word loads per thread in flight (coalesced:
+  // consecutive lanes read consecutive words), then the table lookups
+  constexpr int U = QB == 1 ? 4 : 8;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t p0 = (int64_t)blockIdx.x * 256 + threadIdx.x; p0 < N; p0 += U * stride) {
+    uint4 w[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t p = p0 + u * stride;
+      w[u] = p < N ? *reinterpret_cast<const uint4*>(words + p * kWordBytes) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int qq = 0; qq < QB; qq++) {
+      if (q0 + qq >= B) break;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t p = p0 + u * stride;
+        if (p < N) out[(int64_t)(q0 + qq) * N + p] = lb_word(T[qq], w[u]);
+      }
+    }
   }
 }
 
@@ -477,10 +499,15 @@ sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) 
 }
 
 sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st) {
-  unsigned gx = nblk(a.N, 256);
-  if (gx > 512) gx = 512;
-  dim3 g(gx, (unsigned)a.B);
-  k_all_lb<<<g, 256, 0, st>>>(a.tables, a.words, a.N, d_lb);
+  unsigned gx = nblk(a.N, a.B == 1 ? 1024 : 2048);
+  if (gx > 2048) gx = 2048;
+  if (a.B == 1) {
+    k_all_lb<1><<<dim3(gx, 1), 256, 0, st>>>(a.tables, a.words, a.N, a.B, d_lb);
+  } else if (a.B == 2) {
+    k_all_lb<2><<<dim3(gx, 1), 256, 0, st>>>(a.tables, a.words, a.N, a.B, d_lb);
+  } else {
+    k_all_lb<4><<<dim3(gx, (unsigned)((a.B + 3) / 4)), 256, 0, st>>>(a.tables, a.words, a.N, a.B, d_lb);
+  }
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }

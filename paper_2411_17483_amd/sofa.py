@@ -122,7 +122,7 @@ def load():
     L.sofa_workspace_free.restype = None
     L.sofa_knn.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(KnnParams), _vp, _vp, _vp]
     L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
-    L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+    L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
     L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
     L.sofa_fp8_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
     L.sofa_server_create.argtypes = [ctypes.POINTER(ServerParams), ctypes.POINTER(_vp)]
@@ -309,17 +309,20 @@ class Index:
         _check(load().sofa_workspace_bytes_for(self._h, B, k, prune, ctypes.byref(b)))
         return b.value
 
-    def lower_bounds(self, Q, tables=True, lb=True):
-        """(tables B x 16 x 256, word bounds B x N in leaf order) as device tensors."""
+    def lower_bounds(self, Q, tables=True, lb=True, timed=False):
+        """(tables B x 16 x 256, word bounds B x N in leaf order) as device
+        tensors; with timed=True also the word-scan kernel's duration in ms."""
         import torch
         B = Q.shape[0]
         N = self.info()["N"]
         T = torch.empty((B, 16, 256), dtype=torch.float32, device=Q.device) if tables else None
         LB = torch.empty((B, N), dtype=torch.float32, device=Q.device) if lb else None
+        ms = ctypes.c_double(0.0)
         _check(load().sofa_lower_bounds(self._h, _dev(Q, torch.float32), B,
                                         None if T is None else _dev(T),
-                                        None if LB is None else _dev(LB), _stream()))
-        return T, LB
+                                        None if LB is None else _dev(LB), _stream(),
+                                        ctypes.byref(ms) if timed else None))
+        return (T, LB, ms.value) if timed else (T, LB)
 
     def bf16_lower_bounds(self, Q):
         """B x N batched-distance lower bounds (leaf order) from the BF16 MFMA kernel."""

@@ -41,3 +41,43 @@ def test_errors_without_device_work():
     assert b"l=0" in lib.sofa_last_error()
     st = lib.sofa_knn(None, None, 1, 1, None, None, None, None)
     assert st == sofa.SOFA_EINVAL
+
+
+# public struct name in include/sofa.h -> ctypes structure in the binding
+_STRUCTS = {
+    "sofa_bin_params": "BinParams",
+    "sofa_build_params": "BuildParams",
+    "sofa_index_info": "IndexInfo",
+    "sofa_knn_params": "KnnParams",
+    "sofa_knn_stats": "KnnStats",
+    "sofa_radius_params": "RadiusParams",
+    "sofa_server_params": "ServerParams",
+    "sofa_server_stats": "ServerStats",
+}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """sizeof and every field offset of the public structs, as the C compiler
+    lays them out from include/sofa.h, equal the ctypes structures."""
+    import subprocess
+    from paper_2411_17483_amd import sofa
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sofa.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(sofa, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, key, val = line.split()
+        got[(name, key)] = int(val)
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(sofa, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)

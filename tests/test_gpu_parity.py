@@ -126,6 +126,26 @@ def test_index_layout_properties(gpu_lib):
     assert np.all(keys0.view(np.uint64)[1:] >= keys0.view(np.uint64)[:-1])
 
 
+@pytest.mark.parametrize("B", [1, 2, 3, 5])
+def test_word_scan_equals_table_sums(gpu_lib, B):
+    """The word scan writes, for each query and leaf-order row, the sum over
+    word positions of the query's table at the row's symbol (Eq. 3 summed as
+    in Eq. 2): recomputed here from the exported words and tables."""
+    N, n = 5000 + 13, 256
+    X = synth.collection(N, n, "mix", seed=15)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=16)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256)
+    T, LB, ms = ix.lower_bounds(_t(Q), timed=True)
+    assert ms > 0.0
+    T, LB = T.cpu().numpy().astype(np.float64), LB.cpu().numpy().astype(np.float64)
+    words, _, _, _ = ix.export()
+    W = words.cpu().numpy().reshape(N, 16).astype(np.int64)
+    for b in range(B):
+        ref = T[b][np.arange(16)[None, :], W].sum(axis=1)
+        assert np.all(np.abs(LB[b] - ref) <= 1e-5 * ref + 1e-6), b
+
+
 @pytest.mark.parametrize("binning", [0, 1])
 def test_lower_bounds_never_exceed_distance(gpu_lib, binning):
     N, n, B = 3000, 256, 24
@@ -671,3 +691,40 @@ def test_learned_radius_search_is_exact(gpu_lib):
     m1 = gpu_lib.RadiusModel(k=1)
     with pytest.raises(gpu_lib.SofaError):
         ix.knn(_t(Qte), k, model=m1)
+
+
+def test_learned_radius_gains_over_the_search_without_it(gpu_lib):
+    """What the trained network buys: with the predicted radius seeding the
+    bound, the same exact answers need fewer exact distances (FP32 refine)
+    than the search seeded by the best leaf alone, on both the plain SFA scan
+    and the BF16 prune.  Trained on the GPU by the library's own kernels."""
+    import torch
+    N, n = 60000, 256
+    X = synth.collection(N, n, "mix", seed=311)
+    bins, ix = _bf16_index(gpu_lib, X)
+    Qtr, _ = synth.queries(X, 4000, sigma=0.1, seed=312)
+    Qte, _ = synth.queries(X, 96, sigma=0.1, seed=313)
+    feat, _, _ = bins.transform(_t(Qtr), sel=False, words=False)
+    gains = {}
+    for k in (1, 10):
+        _, d_tr = ix.knn(_t(Qtr), k, prune=1)
+        target = torch.log(d_tr[:, -1]).contiguous()
+        m = gpu_lib.RadiusModel(k=k, seed=17)
+        m.standardize(feat)
+        m.fit(feat[:3500].contiguous(), target[:3500].contiguous(), epochs=40, batch=250)
+        m.calibrate(feat[3500:].contiguous(), target[3500:].contiguous(), 0.999)
+        ref_ids, ref_d2 = oracle.knn(X, Qte, k)
+        for prune in (0, 1):
+            ids0, d0 = ix.knn(_t(Qte), k, prune=prune)
+            base = ix.stats()
+            ids1, d1 = ix.knn(_t(Qte), k, prune=prune, model=m)
+            learned = ix.stats()
+            _check_knn(ids0.cpu().numpy(), d0.cpu().numpy(), ref_ids, ref_d2)
+            _check_knn(ids1.cpu().numpy(), d1.cpu().numpy(), ref_ids, ref_d2)
+            gains[(k, prune)] = (base["series_refined"], learned["series_refined"],
+                                 learned["radius_fallbacks"])
+    for key, (b, l, fb) in gains.items():
+        assert l < b, (key, gains)
+    # the seed alone leaves far more exact work at k = 1 on the BF16 prune
+    b, l, _ = gains[(1, 1)]
+    assert l * 2 <= b, gains
