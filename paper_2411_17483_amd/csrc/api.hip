@@ -401,7 +401,7 @@ int cap_for(int k, const sofa_knn_params* p) {
 enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
   W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
-  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_GMASK, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
   W_MLP, W_END
 };
 
@@ -457,7 +457,9 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_CEV] = bf ? (size_t)B * 4 : 0;
   sz[W_QCNT] = bf ? (size_t)B * 4 : 0;
   sz[W_PERM] = bf ? (size_t)B * 4 : 0;
-  sz[W_GMASK] = bf ? (size_t)ix->n_blocks * G * 8 : 0;
+  sz[W_LCNT] = bf ? (size_t)ix->n_leaves * 4 : 0;
+  sz[W_LOFF] = bf ? (size_t)ix->n_leaves * 8 : 0;
+  sz[W_LSLOT] = bf ? (size_t)ix->n_leaves * B * 2 : 0;  // worst case: every query needs every leaf
   sz[W_SMASK] = bf ? (size_t)ix->n_blocks * G * kGroup * 8 : 0;
   sz[W_SLOTC] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
@@ -627,7 +629,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.qscale = (float*)at(W_QSCALE);
     b.perm = (int32_t*)at(W_PERM);
     b.qcount = (uint32_t*)at(W_QCNT);
-    b.gmask = (uint64_t*)at(W_GMASK);
+    b.lcnt = (uint32_t*)at(W_LCNT);
+    b.loff = (int64_t*)at(W_LOFF);
+    b.lslot = (uint16_t*)at(W_LSLOT);
     b.smask = (uint64_t*)at(W_SMASK);
     b.slotc = (float4*)at(W_SLOTC);
     b.G = (int)((B + kGroup - 1) / kGroup);
@@ -860,7 +864,8 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   if (B > 65535) return set_error(SOFA_EINVAL, "B too large");
   hipStream_t st = S(stream);
   const int64_t G = (B + kGroup - 1) / kGroup;
-  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, gm, sm, sc, perm, qb, qmeta, qscale, ctr, U, stats;
+  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, lcnt, loff, lslot, sm, sc, perm, qb, qmeta, qscale, ctr, U,
+      stats;
   SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
   SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
   SOFA_TRY(qn.alloc((size_t)B * 8));
@@ -870,7 +875,9 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   SOFA_TRY(U.alloc((size_t)B * 4));
   SOFA_TRY(bad.alloc(4));
   SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8));
-  SOFA_TRY(gm.alloc((size_t)ix->n_blocks * G * 8));
+  SOFA_TRY(lcnt.alloc((size_t)ix->n_leaves * 4));
+  SOFA_TRY(loff.alloc((size_t)ix->n_leaves * 8));
+  SOFA_TRY(lslot.alloc((size_t)ix->n_leaves * B * 2));
   SOFA_TRY(sm.alloc((size_t)ix->n_blocks * G * kGroup * 8));
   SOFA_TRY(sc.alloc((size_t)G * kGroup * 16));
   SOFA_TRY(perm.alloc((size_t)B * 4));
@@ -920,7 +927,9 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   b.qscale = qscale.as<float>();
   b.perm = perm.as<int32_t>();
   b.qcount = u0.as<uint32_t>();  // scratch for the density sort
-  b.gmask = gm.as<uint64_t>();
+  b.lcnt = lcnt.as<uint32_t>();
+  b.loff = loff.as<int64_t>();
+  b.lslot = lslot.as<uint16_t>();
   b.smask = sm.as<uint64_t>();
   b.slotc = sc.as<float4>();
   b.G = (int)G;

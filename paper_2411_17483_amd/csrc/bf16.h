@@ -13,13 +13,15 @@ struct Bf16Args {
   const float4* meta;       // per row: |x|^2 (down), r_x (up), |xh| (up)
   const float4* leafmeta;   // per leaf: max |xh|, max r_x, max |x|^2
   const float* cscale;      // FP8: power-of-two scale per 256-row chunk
-  uint4* qb;                // BF16 or FP8 query fragments per sorted slot
+  uint4* qb;                // BF16 or FP8 query rows (n_pad values) per sorted slot
   float* qscale;            // FP8: power-of-two scale per sorted slot
   float4* qmeta;            // per slot: |q|^2 (down), r_q (up), |qh| (up), |q| (up)
   int32_t* perm;            // sorted slot -> query
   uint32_t* qcount;         // surviving leaves per query
-  uint64_t* gmask;          // n_blocks x G group survivor masks
   uint64_t* smask;          // n_blocks x (64 G) survivor masks in sorted-slot order
+  uint32_t* lcnt;           // n_leaves: queries whose (query, leaf) pair survives
+  int64_t* loff;            // n_leaves: start of each leaf's list in lslot
+  uint16_t* lslot;          // per leaf, the sorted slots of those queries, ascending
   float4* slotc;            // per slot and pass: bound terms (a, b, c) and the query id
   int G;                    // query groups
   uint32_t* cand;           // B x cap candidate rows

@@ -303,17 +303,55 @@ __global__ void k_smask(const uint64_t* __restrict__ masks, int64_t n_blocks, in
   smask[i] = s < B ? masks[b * B + perm[s]] : 0ull;
 }
 
-// gmask[blk][g]: bit i set when leaf blk*64+i survives for some query of group g
-__global__ void k_gmask(const uint64_t* __restrict__ smask, int64_t n_blocks, int G,
-                        uint64_t* __restrict__ gmask) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_blocks * G) return;
-  int64_t b = i / G;
-  int g = (int)(i % G);
-  uint64_t m = 0;
-  const uint64_t* sm = smask + b * (int64_t)G * kGroup + (int64_t)g * kGroup;
-  for (int s = 0; s < kGroup; s++) m |= sm[s];
-  gmask[i] = m;
+// Per leaf, the sorted slots of the queries for which the leaf survives
+// (one wave per leaf, ballot compaction in slot order).  PASS 0 counts,
+// PASS 1 writes at the leaf's offset.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_leaf_lists(const uint64_t* __restrict__ smask, int64_t n_leaves,
+                                                    int Spad, uint32_t* __restrict__ lcnt,
+                                                    const int64_t* __restrict__ loff,
+                                                    uint16_t* __restrict__ lslot) {
+  const int lane = threadIdx.x & 63;
+  const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (leaf >= n_leaves) return;
+  const uint64_t* sm = smask + (leaf / kLeavesPerItem) * (int64_t)Spad;
+  const int bit = (int)(leaf % kLeavesPerItem);
+  const int64_t base = PASS ? loff[leaf] : 0;
+  uint32_t c = 0;
+  for (int s0 = 0; s0 < Spad; s0 += 64) {
+    const bool on = (sm[s0 + lane] >> bit) & 1ull;
+    const uint64_t bal = __ballot(on);
+    if (PASS && on) lslot[base + c + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)(s0 + lane);
+    c += (uint32_t)__popcll(bal);
+  }
+  if (PASS == 0 && lane == 0) lcnt[leaf] = c;
+}
+
+// exclusive prefix sum of the leaf counts (one workgroup)
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t n,
+                                                      int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
+  int64_t sum = 0;
+  for (int64_t i = lo; i < hi; i++) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int i = 0; i < 1024; i++) {
+      const int64_t v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int64_t acc = part[t];
+  for (int64_t i = lo; i < hi; i++) {
+    off[i] = acc;
+    acc += cnt[i];
+  }
 }
 
 // per slot, for the current pass: with t = |x|^2 - 2P, a row survives when
@@ -335,18 +373,14 @@ __global__ void k_slotc(const float4* __restrict__ qmeta, const int32_t* __restr
   slotc[s] = c;
 }
 
-// swizzled BF16 query fragments per sorted slot and the query bound terms
-__global__ void k_qprep_bf16(const float* __restrict__ Qp, int B, int n_pad, int Spad,
+// BF16 query rows per sorted slot (n_pad values, zero past B); a lane's
+// fragment of the 32x32x16 B operand is 16 contiguous bytes of one row
+__global__ void k_qrows_bf16(const float* __restrict__ Qp, int B, int n_pad, int Spad,
                              const int32_t* __restrict__ perm, uint4* __restrict__ qb) {
-  const int KS = n_pad / 16;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)(Spad / 32) * KS * 64) return;
-  const int lane = (int)(i % 64);
-  const int64_t t = i / 64;
-  const int ks = (int)(t % KS);
-  const int cb = (int)(t / KS);
-  const int s = cb * 32 + lane % 32;
-  const int k0 = ks * 16 + 8 * (lane / 32);
+  const int per = n_pad / 8;
+  if (i >= (int64_t)Spad * per) return;
+  const int s = (int)(i / per), k0 = (int)(i % per) * 8;
   uint32_t w[4] = {0, 0, 0, 0};
   if (s < B) {
     const float* qr = Qp + (int64_t)perm[s] * n_pad;
@@ -375,8 +409,8 @@ __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp
   }
 }
 
-// FP8 query side: a power-of-two scale per slot, fragments in 32x32x64
-// operand order (two 16-byte halves per lane), the same bound terms
+// FP8 query side: a power-of-two scale per slot, e4m3 rows, the same bound
+// terms
 __global__ __launch_bounds__(256) void k_qscale_fp8(const float* __restrict__ Qp, int B, int n_pad,
                                                     const int32_t* __restrict__ perm, int Spad,
                                                     float* __restrict__ qscale) {
@@ -396,19 +430,13 @@ __global__ __launch_bounds__(256) void k_qscale_fp8(const float* __restrict__ Qp
   if (lane == 0) qscale[s] = fp8_scale_for(m);
 }
 
-__global__ void k_qprep_fp8(const float* __restrict__ Qp, int B, int n_pad, int Spad,
+__global__ void k_qrows_fp8(const float* __restrict__ Qp, int B, int n_pad, int Spad,
                             const int32_t* __restrict__ perm, const float* __restrict__ qscale,
                             uint4* __restrict__ qb) {
-  const int KS = n_pad / 64;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)(Spad / 32) * KS * 128) return;
-  const int lane = (int)(i % 64);
-  const int h = (int)((i / 64) % 2);
-  const int64_t t = i / 128;
-  const int ks = (int)(t % KS);
-  const int cb = (int)(t / KS);
-  const int s = cb * 32 + lane % 32;
-  const int k0 = ks * 64 + 32 * (lane / 32) + 16 * h;
+  const int per = n_pad / 16;
+  if (i >= (int64_t)Spad * per) return;
+  const int s = (int)(i / per), k0 = (int)(i % per) * 16;
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
   if (s < B) w = fp8_pack16(Qp + (int64_t)perm[s] * n_pad + k0, 1.0f / qscale[s]);
   qb[i] = w;
@@ -484,24 +512,40 @@ __device__ __forceinline__ f16v mma(typename TileTraits<PREC>::frag a, typename 
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
-// per-column terms of a group's two 32-query blocks (query slot order)
+// A group: 64 consecutive entries of the leaf's list of surviving queries
+// (sorted slots).  Each lane serves columns lane%32 and 32 + lane%32.
+struct GroupSlots {
+  int s0, s1;     // sorted slots of the lane's two columns
+  bool v0, v1;    // whether those columns exist (the last group may be short)
+};
+
+__device__ __forceinline__ GroupSlots group_slots(const Bf16Args& b, int64_t off, uint32_t cnt, int g,
+                                                  int lane) {
+  const uint32_t c0 = (uint32_t)g * kGroup + (lane & 31), c1 = c0 + 32;
+  GroupSlots r;
+  r.v0 = c0 < cnt;
+  r.v1 = c1 < cnt;
+  r.s0 = b.lslot[off + (r.v0 ? c0 : 0)];  // a short group repeats its first slot (unused)
+  r.s1 = b.lslot[off + (r.v1 ? c1 : 0)];
+  return r;
+}
+
+// per-column terms of a group's two 32-query blocks
 struct ColTerms {
   float4 c0, c1;    // bound terms (a, b, c) and query id
-  uint64_t m0, m1;  // survivor masks of the chunk's leaf block
   float s0, s1;     // FP8 query scales
+  bool v0, v1;
 };
 
 template <int PREC>
-__device__ __forceinline__ void load_cols(const Bf16Args& b, int64_t blk, int g, int lane,
-                                          ColTerms& t) {
-  const int s = g * kGroup + (lane & 31);
-  t.c0 = b.slotc[s];
-  t.c1 = b.slotc[s + 32];
-  t.m0 = b.smask[blk * (int64_t)b.G * kGroup + s];
-  t.m1 = b.smask[blk * (int64_t)b.G * kGroup + s + 32];
+__device__ __forceinline__ void load_cols(const Bf16Args& b, const GroupSlots& gs, ColTerms& t) {
+  t.c0 = b.slotc[gs.s0];
+  t.c1 = b.slotc[gs.s1];
+  t.v0 = gs.v0;
+  t.v1 = gs.v1;
   if constexpr (PREC == 2) {
-    t.s0 = b.qscale[s];
-    t.s1 = b.qscale[s + 32];
+    t.s0 = b.qscale[gs.s0];
+    t.s1 = b.qscale[gs.s1];
   } else {
     t.s0 = t.s1 = 1.0f;
   }
@@ -511,16 +555,26 @@ __device__ __forceinline__ void load_cols(const Bf16Args& b, int64_t blk, int g,
 template <int PREC, int KS>
 constexpr int group_units() { return 2 * KS * 64 * TileTraits<PREC>::kHalves; }
 
-// DMA of group g's fragments (1 KB pieces, a quarter of them per wave) into dst
+// LDS DMA of a group's B fragments into dst, gathered from the query rows:
+// piece p (64 lanes x 16 B, a quarter of the pieces per wave) is column
+// block cb, K step ks (and half hh for FP8); lane l reads the 16 contiguous
+// bytes of its column's row that the instruction's operand layout puts there
 template <int PREC, int KS>
-__device__ __forceinline__ void stage_group(const Bf16Args& b, int g, int wave, int lane, u4v* dst) {
-  constexpr int kPieces = group_units<PREC, KS>() / 64;
+__device__ __forceinline__ void stage_group(const Bf16Args& b, const GroupSlots& gs, int wave, int lane,
+                                            u4v* dst) {
+  constexpr int H = TileTraits<PREC>::kHalves;
+  constexpr int kPieces = 2 * KS * H;
+  constexpr int64_t kRowUnits = PREC == 1 ? 2 * KS : 4 * KS;  // u4v per query row
   static_assert(kPieces % 4 == 0, "whole pieces per wave");
-  const u4v* src = reinterpret_cast<const u4v*>(b.qb) + (int64_t)g * group_units<PREC, KS>();
+  const u4v* rows = reinterpret_cast<const u4v*>(b.qb);
 #pragma unroll
   for (int i = 0; i < kPieces / 4; i++) {
     const int piece = wave + 4 * i;
-    __builtin_amdgcn_global_load_lds((const void*)(src + piece * 64 + lane),
+    const int cb = piece / (KS * H), rem = piece % (KS * H);
+    const int ks = rem / H, hh = rem % H;
+    const int slot = cb ? gs.s1 : gs.s0;
+    const int u = PREC == 1 ? 2 * ks + (lane >> 5) : 4 * ks + 2 * (lane >> 5) + hh;
+    __builtin_amdgcn_global_load_lds((const void*)(rows + (int64_t)slot * kRowUnits + u),
                                      (__attribute__((address_space(3))) void*)(dst + piece * 64),
                                      16, 0, 0);
   }
@@ -547,12 +601,12 @@ __device__ __forceinline__ float max16(const f16v& v) {
 // i = 8(e/4) + 4(lane/32) + e%4 (row of the row block r)
 template <int PREC, bool DUMP>
 __device__ __forceinline__ void col_epilogue(const SearchArgs& a, const Bf16Args& b, const ChunkState& cs,
-                                             const float* xn2s, int g, int cb, int q, float cq, bool mbit,
+                                             const float* xn2s, int slot, int q, float cq, bool mbit,
                                              float f, const f16v& acc0, const f16v& acc1) {
   const int wave = cs.wave, lane = cs.lane;
   if (DUMP) {
     // inspection: the lower bound t - o of every pair
-    const float4 qm = b.qmeta[g * kGroup + cb * 32 + (lane & 31)];
+    const float4 qm = b.qmeta[slot];
     const float o = -qm.x + 2.0f * (cs.gam * qm.z + qm.y) * cs.lmx.x + 2.0f * qm.w * cs.lmx.y +
                     (qm.x + cs.lmx.z) * 0x1p-20f;
 #pragma unroll
@@ -602,30 +656,35 @@ __device__ __forceinline__ void col_epilogue(const SearchArgs& a, const Bf16Args
   }
 }
 
-// one group: thresholds from the terms loaded one group ahead, prefetch of
-// the next group (gn; the current one again when gn < 0, unused), the
-// column blocks, and the barrier that publishes the next buffer.  JOINT:
-// both column blocks' MFMAs interleaved (4 per pair of fragment reads, 64
-// accumulators), for one wave per SIMD; otherwise one block after the other.
+// one group: thresholds from the terms loaded one group ahead, the DMA and
+// terms of the next group (when there is one), the slots of the group after
+// it, the column blocks, and the barrier that publishes the next buffer.
+// JOINT: both column blocks' MFMAs interleaved (4 per pair of fragment
+// reads, 64 accumulators), for one wave per SIMD; otherwise one block after
+// the other.
 template <int PREC, int KS, bool DUMP, bool JOINT>
 __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& b,
                                            const ChunkState& cs,
                                            const typename TileTraits<PREC>::frag (&av)[2][KS],
-                                           const float* xn2s, int g, int gn, ColTerms& cols,
+                                           const float* xn2s, const GroupSlots& gcur, bool has_next,
+                                           const GroupSlots& gnext, bool has_next2, GroupSlots& gnext2,
+                                           int64_t off, uint32_t cnt, int g2, ColTerms& cols,
                                            const u4v* cur, u4v* nxt, unsigned long long& st_pairs) {
   constexpr int H = TileTraits<PREC>::kHalves;
   const int wave = cs.wave, lane = cs.lane;
-  const int q0 = __float_as_int(cols.c0.w), q1 = __float_as_int(cols.c1.w);
+  const int q0 = cols.v0 ? __float_as_int(cols.c0.w) : -1;
+  const int q1 = cols.v1 ? __float_as_int(cols.c1.w) : -1;
   const float cq0 = cols.c0.x + cols.c0.y * cs.lmx.x + cols.c0.z * cs.lmx.y + cs.lead;
   const float cq1 = cols.c1.x + cols.c1.y * cs.lmx.x + cols.c1.z * cs.lmx.y + cs.lead;
-  const bool mb0 = q0 >= 0 && ((cols.m0 >> cs.bit) & 1ull);
-  const bool mb1 = q1 >= 0 && ((cols.m1 >> cs.bit) & 1ull);
+  // every listed query needs the leaf
+  const bool mb0 = q0 >= 0, mb1 = q1 >= 0;
   const float f0 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s0;
   const float f1 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s1;
-  const int gp = gn >= 0 ? gn : g;
-  stage_group<PREC, KS>(b, gp, wave, lane, nxt);
-  load_cols<PREC>(b, cs.blk, gp, lane, cols);
-  // a 32-query block with no surviving (query, leaf) pair is skipped
+  if (has_next) {
+    stage_group<PREC, KS>(b, gnext, wave, lane, nxt);
+    load_cols<PREC>(b, gnext, cols);
+  }
+  if (has_next2) gnext2 = group_slots(b, off, cnt, g2, lane);
   const bool act0 = DUMP || __ballot(mb0), act1 = DUMP || __ballot(mb1);
   if (JOINT && act0 && act1) {
     f16v acc[2][2];
@@ -645,8 +704,8 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
       acc[1][1] = mma<PREC>(av[1][ks], b1, acc[1][1]);
     }
     st_pairs += 64 * 64;
-    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, 0, q0, cq0, mb0, f0, acc[0][0], acc[1][0]);
-    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, 1, q1, cq1, mb1, f1, acc[0][1], acc[1][1]);
+    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, gcur.s0, q0, cq0, mb0, f0, acc[0][0], acc[1][0]);
+    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, gcur.s1, q1, cq1, mb1, f1, acc[0][1], acc[1][1]);
   } else {
 #pragma unroll
     for (int cb = 0; cb < 2; cb++) {
@@ -663,11 +722,11 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
         acc[0] = mma<PREC>(av[0][ks], bq, acc[0]);
         acc[1] = mma<PREC>(av[1][ks], bq, acc[1]);
       }
-      col_epilogue<PREC, DUMP>(a, b, cs, xn2s, g, cb, cb ? q1 : q0, cb ? cq1 : cq0, cb ? mb1 : mb0,
-                               cb ? f1 : f0, acc[0], acc[1]);
+      col_epilogue<PREC, DUMP>(a, b, cs, xn2s, cb ? gcur.s1 : gcur.s0, cb ? q1 : q0, cb ? cq1 : cq0,
+                               cb ? mb1 : mb0, cb ? f1 : f0, acc[0], acc[1]);
     }
   }
-  // the next group's fragments have landed; every wave is done with cur
+  // the next group's fragments and terms have landed; every wave is done with cur
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
 }
@@ -702,25 +761,17 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     const int64_t leaf = cs.c0 / a.L;
     cs.blk = leaf / kLeavesPerItem;
     cs.bit = (int)(leaf % kLeavesPerItem);
-    // the chunk's groups with work, 64 at a time: one load per lane and a ballot
-    int w0 = 0;
-    uint64_t glist = __ballot(lane < b.G && ((b.gmask[cs.blk * b.G + lane] >> cs.bit) & 1ull));
-    auto next_group = [&]() -> int {
-      while (!glist) {
-        w0 += 64;
-        if (w0 >= b.G) return -1;
-        glist = __ballot(w0 + lane < b.G && ((b.gmask[cs.blk * b.G + w0 + lane] >> cs.bit) & 1ull));
-      }
-      const int g = w0 + __builtin_ctzll(glist);
-      glist &= glist - 1;
-      return g;
-    };
-    int g = next_group();
+    // the queries whose (query, leaf) pair survives, in groups of 64
+    const uint32_t cnt = b.lcnt[leaf];
+    const int64_t off = b.loff[leaf];
+    const int ng = (int)((cnt + kGroup - 1) / kGroup);
+    if (ng == 0) continue;  // uniform across the workgroup
+    GroupSlots gcur = group_slots(b, off, cnt, 0, lane);
     ColTerms cols;
-    if (g >= 0) {
-      stage_group<PREC, KS>(b, g, wave, lane, Bs0);
-      load_cols<PREC>(b, cs.blk, g, lane, cols);
-    }
+    stage_group<PREC, KS>(b, gcur, wave, lane, Bs0);
+    load_cols<PREC>(b, gcur, cols);
+    GroupSlots gnext = gcur;
+    if (ng > 1) gnext = group_slots(b, off, cnt, 1, lane);
     // A operand: this wave's 64 rows, all K steps, in registers
     const int64_t rb0 = (cs.c0 + 64 * wave) / 32;
     frag av[2][KS];
@@ -750,14 +801,18 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
       cs.xmin[r] = m;
     }
     // groups alternate between the two buffers
-    while (g >= 0) {
-      int gn = next_group();
-      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, g, gn, cols, Bs0, Bs1, st_pairs);
-      g = gn;
-      if (g < 0) break;
-      gn = next_group();
-      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, g, gn, cols, Bs1, Bs0, st_pairs);
-      g = gn;
+    for (int g = 0; g < ng; g += 2) {
+      GroupSlots gnext2 = gnext;
+      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, gcur, g + 1 < ng, gnext, g + 2 < ng,
+                                             gnext2, off, cnt, g + 2, cols, Bs0, Bs1, st_pairs);
+      if (g + 1 >= ng) break;
+      gcur = gnext;
+      gnext = gnext2;
+      GroupSlots gnext3 = gnext;
+      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, gcur, g + 2 < ng, gnext, g + 3 < ng,
+                                             gnext3, off, cnt, g + 3, cols, Bs1, Bs0, st_pairs);
+      gcur = gnext;
+      gnext = gnext3;
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
@@ -912,17 +967,18 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   k_qsort<<<nblk(B, 4), 256, 0, st>>>(b.qcount, a.best, B, a.n_leaves, b.perm);
   const int Spad = b.G * kGroup;
   k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
-  k_gmask<<<nblk(a.n_blocks * b.G, 256), 256, 0, st>>>(b.smask, a.n_blocks, b.G, b.gmask);
+  // per leaf, the slots of the queries that need it: count, offsets, fill
+  k_leaf_lists<0><<<nblk(a.n_leaves, 4), 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
+  k_scan_counts<<<1, 1024, 0, st>>>(b.lcnt, a.n_leaves, b.loff);
+  k_leaf_lists<1><<<nblk(a.n_leaves, 4), 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
   if (b.prec == 2) {
-    const int KS = a.n_pad / 64;
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
-    k_qprep_fp8<<<nblk((int64_t)(Spad / 32) * KS * 128, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
-                                                                            b.perm, b.qscale, b.qb);
+    k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
+                                                                          b.qscale, b.qb);
     k_qmeta_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale, b.qmeta);
   } else {
-    const int KS = a.n_pad / 16;
-    k_qprep_bf16<<<nblk((int64_t)(Spad / 32) * KS * 64, 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad,
-                                                                             b.perm, b.qb);
+    k_qrows_bf16<<<nblk((int64_t)Spad * (a.n_pad / 8), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
+                                                                          b.qb);
     k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
   }
   SOFA_HIP(hipGetLastError());
