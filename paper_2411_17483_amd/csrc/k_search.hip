@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
 
 // 2. envelope bounds of every (query, leaf).  pass 0: atomicMin of
 // (bound bits << 32 | leaf) per query; pass 1: survivor masks per 64-leaf block.
-constexpr int kSegLeaves = 4096;
+constexpr int kSegLeaves = 16384;  // leaves per workgroup: one 16 KB table load serves them all
 
 template <int PASS>
 __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
@@ -103,22 +103,32 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   if (PASS == 1) thr = __uint_as_float(a.U[q]) * (1.0f + 0x1p-16f);
   uint64_t best = kEmpty;
   unsigned long long visited = 0;
-  for (int it = 0; it < kSegLeaves / 256; it++) {
-    int64_t leaf = seg0 + it * 256 + threadIdx.x;
-    bool valid = leaf < a.n_leaves;
-    float lb = INFINITY;
-    if (valid) {
-      const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
-      lb = lb_leaf(T, sq, e[0], e[1]);
+  // two leaves per thread and iteration (independent lookup chains)
+  for (int it = 0; it < kSegLeaves / 256; it += 2) {
+    float lb2[2];
+    bool valid2[2];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      const int64_t leaf = seg0 + (it + u) * 256 + threadIdx.x;
+      valid2[u] = leaf < a.n_leaves;
+      lb2[u] = INFINITY;
+      if (valid2[u]) {
+        const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
+        lb2[u] = lb_leaf(T, sq, e[0], e[1]);
+      }
     }
-    if (PASS == 0) {
-      uint64_t key = ((uint64_t)__float_as_uint(lb) << 32) | (uint64_t)(uint32_t)leaf;
-      if (valid && key < best) best = key;
-    } else {
-      uint64_t m = __ballot(valid && lb <= thr);
-      int64_t blk = (seg0 + it * 256 + (threadIdx.x & ~63)) / kLeavesPerItem;
-      if (lane == 0 && blk < a.n_blocks) a.masks[blk * a.B + q] = m;
-      visited += (lane == 0) ? __popcll(m) : 0;
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      const int64_t leaf = seg0 + (it + u) * 256 + threadIdx.x;
+      if (PASS == 0) {
+        uint64_t key = ((uint64_t)__float_as_uint(lb2[u]) << 32) | (uint64_t)(uint32_t)leaf;
+        if (valid2[u] && key < best) best = key;
+      } else {
+        uint64_t m = __ballot(valid2[u] && lb2[u] <= thr);
+        int64_t blk = (seg0 + (it + u) * 256 + (threadIdx.x & ~63)) / kLeavesPerItem;
+        if (lane == 0 && blk < a.n_blocks) a.masks[blk * a.B + q] = m;
+        visited += (lane == 0) ? __popcll(m) : 0;
+      }
     }
   }
   if (PASS == 0) {
