@@ -716,11 +716,20 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
       for (int r = 0; r < 2; r++)
 #pragma unroll
         for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
+      // B fragments read from LDS two K steps ahead of their MFMAs (one for
+      // the widest FP8 rows, which leave too few registers); the scheduling
+      // barriers keep the compiler from sinking the reads back to their use
+      constexpr int kAhead = (PREC == 2 && KS >= 8) ? 1 : 2;
+      typename TileTraits<PREC>::frag bq[KS];
+#pragma unroll
+      for (int ks = 0; ks < kAhead && ks < KS; ks++) bq[ks] = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
 #pragma unroll
       for (int ks = 0; ks < KS; ks++) {
-        const auto bq = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
-        acc[0] = mma<PREC>(av[0][ks], bq, acc[0]);
-        acc[1] = mma<PREC>(av[1][ks], bq, acc[1]);
+        if (ks + kAhead < KS) bq[ks + kAhead] = load_frag<PREC>(cur + (cb * KS + ks + kAhead) * 64 * H + lane);
+        __builtin_amdgcn_sched_barrier(0);
+        acc[0] = mma<PREC>(av[0][ks], bq[ks], acc[0]);
+        acc[1] = mma<PREC>(av[1][ks], bq[ks], acc[1]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       col_epilogue<PREC, DUMP>(a, b, cs, xn2s, cb ? gcur.s1 : gcur.s0, cb ? q1 : q0, cb ? cq1 : cq0,
                                cb ? mb1 : mb0, cb ? f1 : f0, acc[0], acc[1]);
@@ -855,9 +864,75 @@ static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned
 // exact FP32 refinement of the candidate lists: workgroup (q, z) of a
 // (B x kCandSplit) grid; wave w takes 64-candidate chunks z*4+w, +4*kCandSplit, ...
 constexpr int kCandSplit = 8;
+constexpr int kRefRows = 4;  // rows per 16-lane group and step: 16 rows of a wave in flight
+
+// FP32 squared distances of kRefRows rows per 16-lane group (lane li owns
+// elements li*4 + 64*it), the loads of every row issued before any sum.
+// Past the first 256 elements a row continues only while its partial sum
+// stays within `abandon`; abandoned and inactive rows return +inf.
+template <int NIT>
+__device__ __forceinline__ void dist_rows(const float* __restrict__ X, int n_pad,
+                                          const uint32_t (&pos)[kRefRows], const bool (&act)[kRefRows],
+                                          const float4 (&q)[NIT], int li, float abandon,
+                                          float (&d)[kRefRows]) {
+  constexpr int H = NIT < 4 ? NIT : 4;  // float4 steps per lane loaded together
+  float acc[kRefRows];
+  bool live[kRefRows];
+#pragma unroll
+  for (int r = 0; r < kRefRows; r++) {
+    acc[r] = 0.0f;
+    live[r] = act[r];
+  }
+#pragma unroll
+  for (int h0 = 0; h0 < NIT; h0 += H) {
+    float4 x[kRefRows][H];
+#pragma unroll
+    for (int r = 0; r < kRefRows; r++)
+      if (live[r]) {
+#pragma unroll
+        for (int it = 0; it < H; it++)
+          x[r][it] = *reinterpret_cast<const float4*>(X + (int64_t)pos[r] * n_pad + li * 4 + 64 * (h0 + it));
+      }
+#pragma unroll
+    for (int r = 0; r < kRefRows; r++)
+      if (live[r]) {
+#pragma unroll
+        for (int it = 0; it < H; it++) {
+          const float4 qv = q[h0 + it];
+          const float d0 = qv.x - x[r][it].x, d1 = qv.y - x[r][it].y;
+          const float d2 = qv.z - x[r][it].z, d3 = qv.w - x[r][it].w;
+          acc[r] = fmaf(d0, d0, acc[r]);
+          acc[r] = fmaf(d1, d1, acc[r]);
+          acc[r] = fmaf(d2, d2, acc[r]);
+          acc[r] = fmaf(d3, d3, acc[r]);
+        }
+      }
+    if (h0 + H < NIT) {
+#pragma unroll
+      for (int r = 0; r < kRefRows; r++) {
+        float p = acc[r];
+        p += __shfl_xor(p, 8);
+        p += __shfl_xor(p, 4);
+        p += __shfl_xor(p, 2);
+        p += __shfl_xor(p, 1);
+        live[r] = live[r] && p <= abandon;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRefRows; r++) {
+    float p = acc[r];
+    p += __shfl_xor(p, 8);
+    p += __shfl_xor(p, 4);
+    p += __shfl_xor(p, 2);
+    p += __shfl_xor(p, 1);
+    d[r] = live[r] ? p : INFINITY;
+  }
+}
 
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
+  constexpr int kStep = 4 * kRefRows;  // candidates per step of a wave
   const int q = blockIdx.x, z = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const uint32_t cnt_all = b.ccnt[q];
@@ -881,37 +956,41 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
     const float ug = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
     Umin = ug < Umin ? ug : Umin;
     while (bal) {
-      int c0[4], c1[4];
+      // the next kStep candidates in lane order: the t-th goes to group t % 4,
+      // row t / 4 (-1: none)
+      int c[kStep];
 #pragma unroll
-      for (int gi = 0; gi < 4; gi++) {
-        c0[gi] = bal ? __builtin_ctzll(bal) : -1;
+      for (int t = 0; t < kStep; t++) {
+        c[t] = bal ? __builtin_ctzll(bal) : -1;
         bal = bal ? (bal & (bal - 1)) : 0ull;
       }
+      int cm[kRefRows];
+      uint32_t pm[kRefRows];
+      bool am[kRefRows];
 #pragma unroll
-      for (int gi = 0; gi < 4; gi++) {
-        c1[gi] = bal ? __builtin_ctzll(bal) : -1;
-        bal = bal ? (bal & (bal - 1)) : 0ull;
+      for (int r = 0; r < kRefRows; r++) {
+        const int t0 = c[4 * r], t1 = c[4 * r + 1], t2 = c[4 * r + 2], t3 = c[4 * r + 3];
+        cm[r] = g == 0 ? t0 : (g == 1 ? t1 : (g == 2 ? t2 : t3));
+        am[r] = cm[r] >= 0;
+        pm[r] = __shfl(pos, am[r] ? cm[r] : 0);
       }
-      uint32_t p0[4], p1[4];
-#pragma unroll
-      for (int gi = 0; gi < 4; gi++) {
-        p0[gi] = __shfl(pos, c0[gi] >= 0 ? c0[gi] : 0);
-        p1[gi] = __shfl(pos, c1[gi] >= 0 ? c1[gi] : 0);
-      }
-      const int ca = c0[g], cbb = c1[g];
-      const float abandon = Umin * a.abandon_f;
-      float da = dist4<NIT>(a.X + (int64_t)p0[g] * a.n_pad, ca >= 0, qr, li, abandon);
-      float db = INFINITY;
-      if (c1[0] >= 0) db = dist4<NIT>(a.X + (int64_t)p1[g] * a.n_pad, cbb >= 0, qr, li, abandon);
+      float d[kRefRows];
+      dist_rows<NIT>(a.X, a.n_pad, pm, am, qr, li, Umin * a.abandon_f, d);
       float band = Umin * a.band_f;
-      uint64_t ins = __ballot(li == 0 && ((ca >= 0 && da <= band) || (cbb >= 0 && db <= band)));
+      bool mine = false;
+#pragma unroll
+      for (int r = 0; r < kRefRows; r++) mine = mine || (am[r] && d[r] <= band);
+      uint64_t ins = __ballot(li == 0 && mine);
       while (ins) {
         const int gl = __builtin_ctzll(ins);
         ins &= ins - 1;
-        const int gg = gl >> 4;
-        const float dA = __shfl(da, gl), dB = __shfl(db, gl);
-        if (c0[gg] >= 0 && dA <= band) wl.insert(((uint64_t)__float_as_uint(dA) << 32) | p0[gg], lane);
-        if (c1[gg] >= 0 && dB <= band) wl.insert(((uint64_t)__float_as_uint(dB) << 32) | p1[gg], lane);
+#pragma unroll
+        for (int r = 0; r < kRefRows; r++) {
+          const float dr = __shfl(d[r], gl);
+          const bool ar = __shfl((int)am[r], gl) != 0;
+          const uint32_t pr = __shfl(pm[r], gl);
+          if (ar && dr <= band) wl.insert(((uint64_t)__float_as_uint(dr) << 32) | pr, lane);
+        }
         const uint64_t kth = wl.at(a.k - 1);
         if (kth != kEmpty) {
           const float uw = key_d(kth) * a.upd_f;
