@@ -350,13 +350,26 @@ extern "C" sofa_status sofa_index_export(const sofa_index* ix, uint8_t* d_words,
 }
 
 // ============================================================================
+// sampled BF16 passes: chunk strides, coarsest first, each dividing the one
+// before; a pass covers the multiples of its stride that are not multiples
+// of the previous stride and selects candidates with the bound U that the
+// earlier passes established.  The (query, leaf) lists are fixed before the
+// first pass, so finer sampling cuts only the candidate refinement: worth
+// two more passes from k = 4 on (10M x 256: k = 10 refines 0.9M instead of
+// 1.6M rows), not at k = 1, where each pass costs more than it saves.
+constexpr int kPassesFew[] = {1024, 32, 1};
+constexpr int kPassesMany[] = {1024, 128, 16, 2, 1};
+constexpr int kManyFromK = 4;
+constexpr int kMaxPasses = 8;
+static_assert(sizeof(kPassesMany) / sizeof(int) <= kMaxPasses, "event slots");
+
 struct sofa_workspace {
   int64_t max_bytes = 0;
   DevBuf buf;
   DevBuf exh;
   std::mutex mu;
   sofa_knn_stats stats{};
-  hipEvent_t ev[16] = {};
+  hipEvent_t ev[7 + 3 * kMaxPasses] = {};
   bool ev_ok = false;
   ~sofa_workspace() {
     if (ev_ok)
@@ -426,9 +439,6 @@ int bf16_cap(const sofa_knn_params* p, int k, int64_t B) {
   }
   return kBf16Cap;
 }
-// no-radius BF16 search: chunk samples of stride 1024, then 32, then the
-// rest, each pass pruning with the bound the previous passes established
-constexpr int kSample0 = 1024, kSample1 = 32;
 
 Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
   size_t sz[W_END];
@@ -647,14 +657,19 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, st, ev ? ev + 7 : nullptr));
       bf_passes = 1;
     } else {
-      const int64_t n0 = (n_chunks + kSample0 - 1) / kSample0;
-      const int64_t n01 = (n_chunks + kSample1 - 1) / kSample1;
-      // multiples of 1024; multiples of 32 that are not multiples of 1024; the rest
-      SOFA_TRY(launch_bf16_pass(a, b, kSample0, 0, 1, n0, 0, st, ev ? ev + 7 : nullptr));
-      SOFA_TRY(launch_bf16_pass(a, b, kSample1, 0, 0, n01 - n0, kSample0 / kSample1, st,
-                                ev ? ev + 10 : nullptr));
-      SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 0, n_chunks - n01, kSample1, st, ev ? ev + 13 : nullptr));
-      bf_passes = 3;
+      const bool many = k >= kManyFromK;
+      const int* strides = many ? kPassesMany : kPassesFew;
+      const int n_passes = many ? (int)(sizeof(kPassesMany) / sizeof(int)) : (int)(sizeof(kPassesFew) / sizeof(int));
+      int64_t prev = 0;
+      for (int ps = 0; ps < n_passes; ps++) {
+        const int64_t sp = strides[ps];
+        const int64_t n_sp = (n_chunks + sp - 1) / sp;
+        const int64_t n_prev = prev ? (n_chunks + prev - 1) / prev : 0;
+        SOFA_TRY(launch_bf16_pass(a, b, sp, 0, prev ? 0 : 1, n_sp - n_prev, prev ? (int)(prev / sp) : 0, st,
+                                  ev ? ev + 7 + 3 * ps : nullptr));
+        prev = sp;
+      }
+      bf_passes = n_passes;
     }
     SOFA_TRY(launch_finalize(a, d_ids, d_d, status, st, ev));
   }

@@ -303,54 +303,98 @@ __global__ void k_smask(const uint64_t* __restrict__ masks, int64_t n_blocks, in
   smask[i] = s < B ? masks[b * B + perm[s]] : 0ull;
 }
 
-// Per leaf, the sorted slots of the queries for which the leaf survives
-// (one wave per leaf, ballot compaction in slot order).  PASS 0 counts,
-// PASS 1 writes at the leaf's offset.
+// per leaf, the sorted slots of the queries whose (query, leaf) pair
+// survives: one workgroup per 64-leaf mask block, whose mask row is staged
+// through LDS 1024 slots at a time; wave w handles leaves 16w .. 16w + 15 of
+// the block.  PASS 0 counts (lcnt); PASS 1 fills lslot from the offsets loff.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_leaf_lists(const uint64_t* __restrict__ smask, int64_t n_leaves,
                                                     int Spad, uint32_t* __restrict__ lcnt,
                                                     const int64_t* __restrict__ loff,
                                                     uint16_t* __restrict__ lslot) {
-  const int lane = threadIdx.x & 63;
-  const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (leaf >= n_leaves) return;
-  const uint64_t* sm = smask + (leaf / kLeavesPerItem) * (int64_t)Spad;
-  const int bit = (int)(leaf % kLeavesPerItem);
-  const int64_t base = PASS ? loff[leaf] : 0;
-  uint32_t c = 0;
-  for (int s0 = 0; s0 < Spad; s0 += 64) {
-    const bool on = (sm[s0 + lane] >> bit) & 1ull;
-    const uint64_t bal = __ballot(on);
-    if (PASS && on) lslot[base + c + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)(s0 + lane);
-    c += (uint32_t)__popcll(bal);
+  constexpr int kRow = 1024;
+  __shared__ uint64_t row[kRow];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t* sm = smask + (int64_t)blockIdx.x * Spad;
+  const int64_t leaf0 = (int64_t)blockIdx.x * kLeavesPerItem + 16 * wave;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t c[16];
+  int64_t base[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    c[j] = 0;
+    base[j] = (PASS && leaf0 + j < n_leaves) ? loff[leaf0 + j] : 0;
   }
-  if (PASS == 0 && lane == 0) lcnt[leaf] = c;
-}
-
-// exclusive prefix sum of the leaf counts (one workgroup)
-__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t n,
-                                                      int64_t* __restrict__ off) {
-  __shared__ int64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
-  int64_t sum = 0;
-  for (int64_t i = lo; i < hi; i++) sum += cnt[i];
-  part[t] = sum;
-  __syncthreads();
-  if (t == 0) {
-    int64_t acc = 0;
-    for (int i = 0; i < 1024; i++) {
-      const int64_t v = part[i];
-      part[i] = acc;
-      acc += v;
+  for (int s0 = 0; s0 < Spad; s0 += kRow) {
+    const int m = Spad - s0 < kRow ? Spad - s0 : kRow;  // a multiple of 64
+    __syncthreads();  // the previous piece has been read
+    for (int i = threadIdx.x; i < m; i += 256) row[i] = sm[s0 + i];
+    __syncthreads();
+    for (int t0 = 0; t0 < m; t0 += 64) {
+      const uint64_t wv = row[t0 + lane] >> (16 * wave);
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        const bool on = leaf0 + j < n_leaves && ((wv >> j) & 1ull);
+        const uint64_t bal = __ballot(on);
+        if (PASS && on) lslot[base[j] + c[j] + __popcll(bal & lt)] = (uint16_t)(s0 + t0 + lane);
+        c[j] += (uint32_t)__popcll(bal);
+      }
     }
   }
-  __syncthreads();
-  int64_t acc = part[t];
-  for (int64_t i = lo; i < hi; i++) {
-    off[i] = acc;
-    acc += cnt[i];
+  if (PASS == 0 && lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (leaf0 + j < n_leaves) lcnt[leaf0 + j] = c[j];
+  }
+}
+
+// exclusive prefix sum of the leaf counts: one workgroup walks tiles of 4096
+// counts (4 per thread, a block-wide scan each) while the next tile loads
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t n,
+                                                      int64_t* __restrict__ off) {
+  constexpr int kTile = 4096;
+  __shared__ int64_t wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t cur[4], nxt[4];
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    const int64_t i = 4 * t + e;
+    cur[e] = i < n ? cnt[i] : 0u;
+  }
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += kTile) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int64_t i = base + kTile + 4 * t + e;
+      nxt[e] = i < n ? cnt[i] : 0u;
+    }
+    const int64_t sv = (int64_t)cur[0] + cur[1] + cur[2] + cur[3];
+    int64_t incl = sv;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int64_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const int64_t v = wsum[i];
+      wpre += i < w ? v : 0;
+      tot += v;
+    }
+    int64_t ex = carry + wpre + incl - sv;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int64_t i = base + 4 * t + e;
+      if (i < n) off[i] = ex;
+      ex += cur[e];
+    }
+    carry += tot;
+    __syncthreads();  // wsum is rewritten by the next tile
+#pragma unroll
+    for (int e = 0; e < 4; e++) cur[e] = nxt[e];
   }
 }
 
@@ -1047,9 +1091,9 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   const int Spad = b.G * kGroup;
   k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
   // per leaf, the slots of the queries that need it: count, offsets, fill
-  k_leaf_lists<0><<<nblk(a.n_leaves, 4), 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
+  k_leaf_lists<0><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
   k_scan_counts<<<1, 1024, 0, st>>>(b.lcnt, a.n_leaves, b.loff);
-  k_leaf_lists<1><<<nblk(a.n_leaves, 4), 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
+  k_leaf_lists<1><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
   if (b.prec == 2) {
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
     k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
