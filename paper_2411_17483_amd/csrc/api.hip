@@ -412,7 +412,7 @@ int cap_for(int k, const sofa_knn_params* p) {
 
 // workspace regions of one batch
 enum {
-  W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_CTR, W_RES, W_RCNT, W_FLAG,
+  W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_LBH, W_CTR, W_RES, W_RCNT, W_FLAG,
   W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
   W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
   W_MLP, W_END
@@ -453,6 +453,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_U0] = (size_t)B * 4;
   sz[W_BEST] = (size_t)B * 8;
   sz[W_MASK] = (size_t)ix->n_blocks * B * 8;
+  sz[W_LBH] = (size_t)ix->n_blocks * kLeavesPerItem * B * 2;
   sz[W_CTR] = 64;
   sz[W_RES] = (size_t)B * cap_for(k, p) * 8;
   sz[W_RCNT] = (size_t)B * 4;
@@ -584,6 +585,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   a.U0 = (float*)at(W_U0);
   a.best = (uint64_t*)at(W_BEST);
   a.masks = (uint64_t*)at(W_MASK);
+  a.lbh = (uint16_t*)at(W_LBH);
   a.counter = (uint32_t*)at(W_CTR);
   a.res = (uint64_t*)at(W_RES);
   a.rescnt = (uint32_t*)at(W_RCNT);

@@ -7,8 +7,10 @@
 //                the query's own symbols, in HBM (16 KB per query).
 //  2. k_leaf_lb  every (query, leaf): envelope bound sum_j T[j][clamp(s_q,lo,hi)]
 //                (valid because each table row is unimodal with its zero at the
-//                query's own symbol).  Pass 0 finds the best leaf per query;
-//                pass 1 writes a 64-leaf survivor mask per (leaf block, query).
+//                query's own symbol), computed once: it finds the best leaf
+//                per query and keeps every bound as an FP16 code rounded
+//                down; after the seed, k_leaf_mask turns the codes into a
+//                64-leaf survivor mask per (leaf block, query).
 //  3. k_seed     exact distances to the best leaf's rows (the approximate search
 //                of Section IV-A) give the first best-so-far bound.
 //  4. k_refine   persistent kernel over (leaf block, query) items, leaf-block
@@ -85,11 +87,31 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
   }
 }
 
-// 2. envelope bounds of every (query, leaf).  pass 0: atomicMin of
-// (bound bits << 32 | leaf) per query; pass 1: survivor masks per 64-leaf block.
+// 2. envelope bounds of every (query, leaf), computed once: the smallest
+// (bound bits << 32 | leaf) per query goes to `best` (atomicMin) and every
+// bound is kept as an FP16 code rounded down, from which k_leaf_mask makes
+// the survivor masks once the seed has set U.
 constexpr int kSegLeaves = 16384;  // leaves per workgroup: one 16 KB table load serves them all
 
-template <int PASS>
+// FP16 code of a non-negative bound, rounded down; +inf stays +inf, finite
+// values above the largest code clamp to it
+__device__ __forceinline__ uint16_t f16_down(float x) {
+  const uint32_t f = __float_as_uint(x);
+  if (f & 0x80000000u) return 0;                // cannot occur; 0 keeps the leaf
+  if (f >= 0x7F800000u) return 0x7C00u;         // +inf
+  const int e = (int)(f >> 23) - 127 + 15;
+  if (e >= 31) return 0x7BFFu;
+  if (e <= 0) return (uint16_t)(x * 0x1p24f);   // subnormal: floor(x / 2^-24), exact scaling
+  return (uint16_t)((e << 10) | ((f >> 13) & 0x3FFu));
+}
+
+__device__ __forceinline__ float f16_val(uint16_t h) {
+  const uint32_t e = (h >> 10) & 0x1Fu, m = h & 0x3FFu;
+  if (e == 0) return (float)m * 0x1p-24f;
+  if (e == 31) return INFINITY;
+  return __uint_as_float(((e + 112u) << 23) | (m << 13));
+}
+
 __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __shared__ float T[kTable];
   const int q = blockIdx.y;
@@ -99,10 +121,8 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __syncthreads();
   const uint4 sq = a.sq[q];
   const int lane = threadIdx.x & 63;
-  float thr = 0.0f;
-  if (PASS == 1) thr = __uint_as_float(a.U[q]) * (1.0f + 0x1p-16f);
+  uint16_t* lbh = a.lbh + (int64_t)q * (a.n_blocks * kLeavesPerItem);
   uint64_t best = kEmpty;
-  unsigned long long visited = 0;
   // two leaves per thread and iteration (independent lookup chains)
   for (int it = 0; it < kSegLeaves / 256; it += 2) {
     float lb2[2];
@@ -120,26 +140,60 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
 #pragma unroll
     for (int u = 0; u < 2; u++) {
       const int64_t leaf = seg0 + (it + u) * 256 + threadIdx.x;
-      if (PASS == 0) {
-        uint64_t key = ((uint64_t)__float_as_uint(lb2[u]) << 32) | (uint64_t)(uint32_t)leaf;
-        if (valid2[u] && key < best) best = key;
-      } else {
-        uint64_t m = __ballot(valid2[u] && lb2[u] <= thr);
-        int64_t blk = (seg0 + (it + u) * 256 + (threadIdx.x & ~63)) / kLeavesPerItem;
-        if (lane == 0 && blk < a.n_blocks) a.masks[blk * a.B + q] = m;
-        visited += (lane == 0) ? __popcll(m) : 0;
+      const uint64_t key = ((uint64_t)__float_as_uint(lb2[u]) << 32) | (uint64_t)(uint32_t)leaf;
+      if (valid2[u]) {
+        best = key < best ? key : best;
+        lbh[leaf] = f16_down(lb2[u]);
       }
     }
   }
-  if (PASS == 0) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      uint64_t o = __shfl_xor(best, off);
-      best = o < best ? o : best;
+  for (int off = 32; off > 0; off >>= 1) {
+    uint64_t o = __shfl_xor(best, off);
+    best = o < best ? o : best;
+  }
+  if (lane == 0 && best != kEmpty) atomicMin(reinterpret_cast<unsigned long long*>(a.best) + q, best);
+}
+
+// survivor masks per 64-leaf block from the stored bounds: a leaf survives
+// when its bound is within U (with the slack of the FP32 bound sum).
+// Workgroup (x, q) takes blocks 256x .. 256x + 255 of query q, eight per
+// wave and step; one statistics atomic per workgroup.
+constexpr int kMaskBlocksPerStep = 8;
+constexpr int kMaskBlocksPerGroup = 256;
+
+__global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
+  __shared__ unsigned long long vis[4];
+  const int q = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float thr = __uint_as_float(a.U[q]) * (1.0f + 0x1p-16f);
+  const uint16_t* lbh = a.lbh + (int64_t)q * (a.n_blocks * kLeavesPerItem);
+  unsigned long long visited = 0;
+  for (int step = 0; step < kMaskBlocksPerGroup / (4 * kMaskBlocksPerStep); step++) {
+    const int64_t blk0 =
+        (int64_t)blockIdx.x * kMaskBlocksPerGroup + (step * 4 + wave) * kMaskBlocksPerStep;
+    if (blk0 >= a.n_blocks) break;
+    uint16_t h[kMaskBlocksPerStep];
+#pragma unroll
+    for (int i = 0; i < kMaskBlocksPerStep; i++) {
+      const int64_t leaf = (blk0 + i) * kLeavesPerItem + lane;
+      h[i] = leaf < a.n_leaves ? lbh[leaf] : (uint16_t)0;
     }
-    if (lane == 0 && best != kEmpty) atomicMin(reinterpret_cast<unsigned long long*>(a.best) + q, best);
-  } else {
-    if (lane == 0 && visited && a.stats) atomicAdd(a.stats + 0, visited);
+#pragma unroll
+    for (int i = 0; i < kMaskBlocksPerStep; i++) {
+      const bool valid = (blk0 + i) * kLeavesPerItem + lane < a.n_leaves;
+      const uint64_t m = __ballot(valid && f16_val(h[i]) <= thr);
+      if (lane == 0 && blk0 + i < a.n_blocks) {
+        a.masks[(blk0 + i) * a.B + q] = m;
+        visited += (unsigned long long)__popcll(m);
+      }
+    }
+  }
+  if (lane == 0) vis[wave] = visited;
+  __syncthreads();
+  if (threadIdx.x == 0 && a.stats) {
+    const unsigned long long v = vis[0] + vis[1] + vis[2] + vis[3];
+    if (v) atomicAdd(a.stats + 0, v);
   }
 }
 
@@ -530,11 +584,12 @@ template <int NIT, int R>
 static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) {
   dim3 gl((unsigned)((a.n_leaves + kSegLeaves - 1) / kSegLeaves), (unsigned)a.B);
   mark(ev, 1, st);
-  k_leaf_lb<0><<<gl, 256, 0, st>>>(a);
+  k_leaf_lb<<<gl, 256, 0, st>>>(a);
   mark(ev, 2, st);
   k_seed<NIT, R><<<nblk(a.B, 4), 256, 0, st>>>(a);
   mark(ev, 3, st);
-  k_leaf_lb<1><<<gl, 256, 0, st>>>(a);
+  const dim3 gm(nblk(a.n_blocks, kMaskBlocksPerGroup), (unsigned)a.B);
+  k_leaf_mask<<<gm, 256, 0, st>>>(a);
   mark(ev, 4, st);
 }
 
