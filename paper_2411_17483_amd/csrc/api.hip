@@ -662,8 +662,15 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       const bool many = k >= kManyFromK;
       const int* strides = many ? kPassesMany : kPassesFew;
       const int n_passes = many ? (int)(sizeof(kPassesMany) / sizeof(int)) : (int)(sizeof(kPassesFew) / sizeof(int));
+      // the (query, leaf) lists are rebuilt from the bounds U of the earlier
+      // passes before each of the last two passes of the five-pass schedule
+      // (10M x 256, k = 10: 6.5G instead of 7.5G tile pairs) and, without a
+      // radius, before the last pass of the three-pass one; a radius near
+      // the k = 1 distance leaves nothing to gain there
+      const int relist_from = many ? n_passes - 2 : (has_radius ? n_passes : n_passes - 1);
       int64_t prev = 0;
       for (int ps = 0; ps < n_passes; ps++) {
+        if (ps >= relist_from) SOFA_TRY(launch_bf16_relist(a, b, st));
         const int64_t sp = strides[ps];
         const int64_t n_sp = (n_chunks + sp - 1) / sp;
         const int64_t n_prev = prev ? (n_chunks + prev - 1) / prev : 0;

@@ -42,6 +42,9 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
 sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                              uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st);
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st);
+// rebuild the (query, leaf) lists from the current bounds U, keeping the slot
+// order: later passes see only the pairs that still survive
+sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
 // ev (nullable): events recorded before the tile kernel, between it and the
 // candidate refinement, and after

@@ -1079,6 +1079,25 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
   return SOFA_OK;
 }
 
+// slot-order masks, then per leaf the slots of the queries that need it:
+// count, offsets, fill
+static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+  const int Spad = b.G * kGroup;
+  k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
+  k_leaf_lists<0><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
+  k_scan_counts<<<1, 1024, 0, st>>>(b.lcnt, a.n_leaves, b.loff);
+  k_leaf_lists<1><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
+}
+
+sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+  SearchArgs m = a;
+  m.stats = nullptr;  // the first masks counted the visited leaves
+  SOFA_TRY(launch_leaf_mask(m, st));
+  launch_lists(a, b, st);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st) {
   const int B = a.B;
   SOFA_TRY(launch_fill_u32(b.qcount, 0u, B, st));
@@ -1089,11 +1108,7 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   }
   k_qsort<<<nblk(B, 4), 256, 0, st>>>(b.qcount, a.best, B, a.n_leaves, b.perm);
   const int Spad = b.G * kGroup;
-  k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, B, Spad, b.perm, b.smask);
-  // per leaf, the slots of the queries that need it: count, offsets, fill
-  k_leaf_lists<0><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
-  k_scan_counts<<<1, 1024, 0, st>>>(b.lcnt, a.n_leaves, b.loff);
-  k_leaf_lists<1><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
+  launch_lists(a, b, st);
   if (b.prec == 2) {
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
     k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,

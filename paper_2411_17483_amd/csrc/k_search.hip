@@ -588,9 +588,15 @@ static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) 
   mark(ev, 2, st);
   k_seed<NIT, R><<<nblk(a.B, 4), 256, 0, st>>>(a);
   mark(ev, 3, st);
+  (void)launch_leaf_mask(a, st);
+  mark(ev, 4, st);
+}
+
+sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st) {
   const dim3 gm(nblk(a.n_blocks, kMaskBlocksPerGroup), (unsigned)a.B);
   k_leaf_mask<<<gm, 256, 0, st>>>(a);
-  mark(ev, 4, st);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
 }
 
 template <int NIT>

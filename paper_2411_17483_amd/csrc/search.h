@@ -45,6 +45,8 @@ sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* rad
 sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                           hipStream_t st, hipEvent_t* ev);
 sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev);
+// survivor masks from the stored envelope bounds and the current U
+sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st);
 sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                             hipStream_t st, hipEvent_t* ev);
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
