@@ -217,12 +217,12 @@ def main():
                               ("ms_prepare", "ms_leaf", "ms_seed", "ms_refine", "ms_finalize",
                                "ms_bf16_tiles", "ms_bf16_refine")},
                 "counters": {s: st[s] for s in ("leaves_total", "leaves_visited", "series_lb_checked",
-                                                 "series_refined", "series_bf16_checked",
+                                                 "series_refined", "series_bf16_checked", "series_bf16_needed",
                                                  "radius_fallbacks", "overflow_fallbacks")},
             }
             if kw.get("prune", 0):
-                # MFMA rate of the tile kernel on the pairs whose leaf survived
-                pairs = st["leaves_visited"] * args.leaf
+                # MFMA rate of the tile kernel on the (query, row) pairs of its lists
+                pairs = st["series_bf16_needed"]
                 tms = res[f"k{kk}"]["stages_ms"]["ms_bf16_tiles"]
                 peak = PEAK_FP8_MFMA if kw["prune"] == 2 else PEAK_BF16_MFMA
                 if tms > 0:
@@ -262,9 +262,10 @@ def main():
                     "kernel": "k_refine", "ms_per_launch": ms,
                     "work_per_launch": {"flop": flops, "words_checked": words, "rows_refined": rows}}
     else:
-        # algorithmic work: 2n flop for every (query, row) pair whose leaf
-        # survived the envelope bound
-        pairs = cnt["leaves_visited"] * args.leaf
+        # algorithmic work: 2n flop for every (query, row) pair on the tile
+        # kernel's lists (the leaf survived the envelope bound under the
+        # bound of its pass), without the padding of the 64-query groups
+        pairs = cnt["series_bf16_needed"]
         flops = 2.0 * n * pairs
         ms = stg["ms_bf16_tiles"]
         ach = flops / (ms * 1e-3)

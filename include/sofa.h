@@ -245,6 +245,10 @@ typedef struct {
    * more with their tightened bound as the radius (on the BF16 tier when the
    * index has it) before any exhaustive pass */
   int64_t overflow_retries;
+  /* (query, row) pairs the batched-distance tiles had to evaluate: the rows
+   * of each leaf times the queries on the leaf's list when its pass ran
+   * (series_bf16_checked counts them in whole groups of 64 queries) */
+  int64_t series_bf16_needed;
 } sofa_knn_stats;
 
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,

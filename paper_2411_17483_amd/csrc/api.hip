@@ -717,6 +717,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   stats.series_lb_checked += (int64_t)hstats[1];
   stats.series_refined += (int64_t)hstats[2];
   stats.series_bf16_checked += (int64_t)hstats[3];
+  stats.series_bf16_needed += (int64_t)hstats[5];
   stats.max_candidates = std::max<int64_t>(stats.max_candidates, (int64_t)hstats[4]);
   for (int64_t q = 0; q < B; q++) {
     if (hst[q] == 2) stats.overflow_evicted++;

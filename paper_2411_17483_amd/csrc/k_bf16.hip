@@ -799,7 +799,7 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
   cs.gam = (float)(KS * TileTraits<PREC>::kStep + TileTraits<PREC>::kStep) * 0x1p-23f;
   const int wave = cs.wave, lane = cs.lane;
   const u4v* xv = reinterpret_cast<const u4v*>(b.xb);
-  unsigned long long st_pairs = 0;
+  unsigned long long st_pairs = 0, st_needed = 0;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
     __syncthreads();
@@ -819,6 +819,7 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     const int64_t off = b.loff[leaf];
     const int ng = (int)((cnt + kGroup - 1) / kGroup);
     if (ng == 0) continue;  // uniform across the workgroup
+    st_needed += (unsigned long long)cnt * (unsigned long long)(a.N - cs.c0 < 256 ? a.N - cs.c0 : 256);
     GroupSlots gcur = group_slots(b, off, cnt, 0, lane);
     ColTerms cols;
     stage_group<PREC, KS>(b, gcur, wave, lane, Bs0);
@@ -869,6 +870,7 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     }
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
+  if (threadIdx.x == 0 && st_needed && a.stats) atomicAdd(a.stats + 5, st_needed);
 }
 
 // waves per SIMD of the tile kernel: 2 (one column block after the other;

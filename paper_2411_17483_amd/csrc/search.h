@@ -32,6 +32,8 @@ struct SearchArgs {
   float* hbase;          // B histogram range [0, hbase) (the bound after the seed)
   const uint32_t* cevmin;  // nullable: B smallest lower bound of a dropped BF16 candidate
   unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
+                              // [3] tile pairs computed [4] most candidates of a query
+                              // [5] tile pairs needed
   // factors derived from the FP32 error bounds
   float lb_f, band_f, upd_f, abandon_f;
   double eta_x;

@@ -728,3 +728,24 @@ def test_learned_radius_gains_over_the_search_without_it(gpu_lib):
     # the seed alone leaves far more exact work at k = 1 on the BF16 prune
     b, l, _ = gains[(1, 1)]
     assert l * 2 <= b, gains
+
+
+def test_tile_pair_counters(gpu_lib):
+    """The tile kernel's pair counters on a k = 10 search without a radius
+    (five sampled passes, the lists rebuilt before the last two): the pairs it
+    had to evaluate (rows of each listed leaf times the leaf's queries) never
+    exceed the pairs whose leaf passed the first envelope bound, and the pairs
+    computed in whole 64-query groups exceed them by less than one group per
+    leaf."""
+    N, n, L = 60000 + 77, 256, 256
+    X = synth.collection(N, n, "mix", seed=321)
+    bins, ix = _bf16_index(gpu_lib, X)
+    Q, _ = synth.queries(X, 150, sigma=0.1, seed=322)
+    ref_ids, ref_d2 = oracle.knn(X, Q, 10)
+    ids, d = ix.knn(_t(Q), 10, prune=1)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    st = ix.stats()
+    need, done = st["series_bf16_needed"], st["series_bf16_checked"]
+    n_leaves = (N + L - 1) // L
+    assert 0 < need <= st["leaves_visited"] * L, st
+    assert need <= done < need + n_leaves * 64 * L, st
