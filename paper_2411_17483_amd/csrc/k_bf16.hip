@@ -910,72 +910,6 @@ static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned
 // exact FP32 refinement of the candidate lists: workgroup (q, z) of a
 // (B x kCandSplit) grid; wave w takes 64-candidate chunks z*4+w, +4*kCandSplit, ...
 constexpr int kCandSplit = 8;
-constexpr int kRefRows = 4;  // rows per 16-lane group and step: 16 rows of a wave in flight
-
-// FP32 squared distances of kRefRows rows per 16-lane group (lane li owns
-// elements li*4 + 64*it), the loads of every row issued before any sum.
-// Past the first 256 elements a row continues only while its partial sum
-// stays within `abandon`; abandoned and inactive rows return +inf.
-template <int NIT>
-__device__ __forceinline__ void dist_rows(const float* __restrict__ X, int n_pad,
-                                          const uint32_t (&pos)[kRefRows], const bool (&act)[kRefRows],
-                                          const float4 (&q)[NIT], int li, float abandon,
-                                          float (&d)[kRefRows]) {
-  constexpr int H = NIT < 4 ? NIT : 4;  // float4 steps per lane loaded together
-  float acc[kRefRows];
-  bool live[kRefRows];
-#pragma unroll
-  for (int r = 0; r < kRefRows; r++) {
-    acc[r] = 0.0f;
-    live[r] = act[r];
-  }
-#pragma unroll
-  for (int h0 = 0; h0 < NIT; h0 += H) {
-    float4 x[kRefRows][H];
-#pragma unroll
-    for (int r = 0; r < kRefRows; r++)
-      if (live[r]) {
-#pragma unroll
-        for (int it = 0; it < H; it++)
-          x[r][it] = *reinterpret_cast<const float4*>(X + (int64_t)pos[r] * n_pad + li * 4 + 64 * (h0 + it));
-      }
-#pragma unroll
-    for (int r = 0; r < kRefRows; r++)
-      if (live[r]) {
-#pragma unroll
-        for (int it = 0; it < H; it++) {
-          const float4 qv = q[h0 + it];
-          const float d0 = qv.x - x[r][it].x, d1 = qv.y - x[r][it].y;
-          const float d2 = qv.z - x[r][it].z, d3 = qv.w - x[r][it].w;
-          acc[r] = fmaf(d0, d0, acc[r]);
-          acc[r] = fmaf(d1, d1, acc[r]);
-          acc[r] = fmaf(d2, d2, acc[r]);
-          acc[r] = fmaf(d3, d3, acc[r]);
-        }
-      }
-    if (h0 + H < NIT) {
-#pragma unroll
-      for (int r = 0; r < kRefRows; r++) {
-        float p = acc[r];
-        p += __shfl_xor(p, 8);
-        p += __shfl_xor(p, 4);
-        p += __shfl_xor(p, 2);
-        p += __shfl_xor(p, 1);
-        live[r] = live[r] && p <= abandon;
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < kRefRows; r++) {
-    float p = acc[r];
-    p += __shfl_xor(p, 8);
-    p += __shfl_xor(p, 4);
-    p += __shfl_xor(p, 2);
-    p += __shfl_xor(p, 1);
-    d[r] = live[r] ? p : INFINITY;
-  }
-}
-
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
   constexpr int kStep = 4 * kRefRows;  // candidates per step of a wave

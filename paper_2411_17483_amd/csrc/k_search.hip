@@ -219,18 +219,29 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
   WaveList<R> wl;
   wl.reset();
   float Umin = U0;
-  for (int64_t p0 = start; p0 < end; p0 += 4) {
-    int64_t p = p0 + g;
-    bool act = p < end;
-    float d = dist4<NIT>(a.X + (act ? p : start) * a.n_pad, act, qr, li, Umin * a.abandon_f);
+  // 16 rows per step: row p0 + 4r + g in 16-lane group g, slot r
+  for (int64_t p0 = start; p0 < end; p0 += 4 * kRefRows) {
+    uint32_t pm[kRefRows];
+    bool am[kRefRows];
 #pragma unroll
-    for (int gi = 0; gi < 4; gi++) {
-      float dd = __shfl(d, 16 * gi);
-      if (p0 + gi < end && dd <= Umin * a.band_f) {
-        uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)(p0 + gi);
-        wl.insert(key, lane);
-      }
+    for (int r = 0; r < kRefRows; r++) {
+      const int64_t p = p0 + 4 * r + g;
+      am[r] = p < end;
+      pm[r] = (uint32_t)(am[r] ? p : start);
     }
+    float d[kRefRows];
+    dist_rows<NIT>(a.X, a.n_pad, pm, am, qr, li, Umin * a.abandon_f, d);
+#pragma unroll
+    for (int r = 0; r < kRefRows; r++)
+#pragma unroll
+      for (int gi = 0; gi < 4; gi++) {
+        const int64_t p = p0 + 4 * r + gi;
+        const float dd = __shfl(d[r], 16 * gi);
+        if (p < end && dd <= Umin * a.band_f) {
+          const uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)p;
+          wl.insert(key, lane);
+        }
+      }
     uint64_t kth = wl.at(a.k - 1);
     if (kth != kEmpty) {
       float uw = key_d(kth) * a.upd_f;
