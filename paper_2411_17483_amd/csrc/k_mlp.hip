@@ -149,6 +149,61 @@ static void gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak, 
   k_gemm<EPI><<<g, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, Zin);
 }
 
+// forward layer Z = A W^T + bias, H = g(Z) with A: M x K (row stride lda)
+// and W: N x K (row n contiguous): 32 x 32 output tiles and K steps of 64,
+// so that a batch of a thousand rows fills the chip in a few steps.  Every
+// output is the same FMA chain as k_gemm's (k increasing from a zero
+// accumulator, then + bias), so both give identical values.
+constexpr int kFt = 32, kFk = 64;
+
+__global__ __launch_bounds__(256) void k_fwd(int M, int N, int K, const float* __restrict__ A, int64_t lda,
+                                             const float* __restrict__ W, const float* __restrict__ bias,
+                                             float* __restrict__ Z, float* __restrict__ H) {
+  __shared__ float As[kFk][kFt + 1];
+  __shared__ float Ws[kFk][kFt + 1];
+  const int t = threadIdx.x, tm = t / 16, tn = t % 16;  // rows 2tm, 2tm+1; columns 2tn, 2tn+1
+  const int m0 = blockIdx.y * kFt, n0 = blockIdx.x * kFt;
+  float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+  for (int k0 = 0; k0 < K; k0 += kFk) {
+    // 64 x 32 values of each operand, 8 per thread, consecutive threads on consecutive k
+    float av[8], wv[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int idx = t + 256 * e, kk = idx % kFk, r = idx / kFk;
+      const int k = k0 + kk, m = m0 + r, n = n0 + r;
+      av[e] = (m < M && k < K) ? A[(int64_t)m * lda + k] : 0.0f;
+      wv[e] = (n < N && k < K) ? W[(int64_t)n * K + k] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int idx = t + 256 * e, kk = idx % kFk, r = idx / kFk;
+      As[kk][r] = av[e];
+      Ws[kk][r] = wv[e];
+    }
+    __syncthreads();
+    const int kn = K - k0 < kFk ? K - k0 : kFk;
+    for (int kk = 0; kk < kn; kk++) {
+      const float a0 = As[kk][2 * tm], a1 = As[kk][2 * tm + 1];
+      const float w0 = Ws[kk][2 * tn], w1 = Ws[kk][2 * tn + 1];
+      acc[0][0] = fmaf(a0, w0, acc[0][0]);
+      acc[0][1] = fmaf(a0, w1, acc[0][1]);
+      acc[1][0] = fmaf(a1, w0, acc[1][0]);
+      acc[1][1] = fmaf(a1, w1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int m = m0 + 2 * tm + i, n = n0 + 2 * tn + j;
+      if (m >= M || n >= N) continue;
+      const float z = acc[i][j] + bias[n];
+      Z[(int64_t)m * N + n] = z;
+      H[(int64_t)m * N + n] = gelu(z);
+    }
+}
+
 // split-K: partial products over K slices into P[s][M][N], then a fixed-order sum
 __global__ void k_sum_slices(const float* __restrict__ P, int S, int64_t MN, float* __restrict__ C) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,8 +436,10 @@ void mlp_forward(const sofa_radius* m, const float* feat, int64_t ld, int64_t B,
   const float* wr = m->wr.as<float>();
   k_standardize<<<nblk(B * d.D, 256), 256, 0, st>>>(feat, ld, B, d.D, m->mu.as<float>(),
                                                     m->sd.as<float>(), a.xs);
-  gemm<1>((int)B, d.H1, d.D, a.xs, d.D, 1, wr + d.oW1, 1, d.D, a.z1, d.H1, wr + d.ob1, a.h1, nullptr, st);
-  gemm<1>((int)B, d.H2, d.H1, a.h1, d.H1, 1, wr + d.oW2, 1, d.H1, a.z2, d.H2, wr + d.ob2, a.h2, nullptr, st);
+  const dim3 g1((unsigned)((d.H1 + kFt - 1) / kFt), (unsigned)((B + kFt - 1) / kFt));
+  k_fwd<<<g1, 256, 0, st>>>((int)B, d.H1, d.D, a.xs, d.D, wr + d.oW1, wr + d.ob1, a.z1, a.h1);
+  const dim3 g2((unsigned)((d.H2 + kFt - 1) / kFt), (unsigned)((B + kFt - 1) / kFt));
+  k_fwd<<<g2, 256, 0, st>>>((int)B, d.H2, d.H1, a.h1, d.H1, wr + d.oW2, wr + d.ob2, a.z2, a.h2);
   k_out<<<nblk(B, 4), 256, 0, st>>>(a.h2, B, d.H2, wr + d.oW3, wr + d.ob3, a.y);
 }
 
