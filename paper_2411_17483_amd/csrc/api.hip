@@ -371,9 +371,22 @@ struct sofa_workspace {
   sofa_knn_stats stats{};
   hipEvent_t ev[7 + 3 * kMaxPasses] = {};
   bool ev_ok = false;
+  uint8_t* hback = nullptr;  // pinned: what the host reads back after a call
+  size_t hback_bytes = 0;
   ~sofa_workspace() {
     if (ev_ok)
       for (auto& e : ev) (void)hipEventDestroy(e);
+    if (hback) (void)hipHostFree(hback);
+  }
+  uint8_t* host_back(size_t bytes) {
+    if (bytes > hback_bytes) {
+      if (hback) (void)hipHostFree(hback);
+      hback = nullptr;
+      hback_bytes = 0;
+      if (hipHostMalloc((void**)&hback, bytes) != hipSuccess) return nullptr;
+      hback_bytes = bytes;
+    }
+    return hback;
   }
   hipEvent_t* events() {
     if (!ev_ok) {
@@ -412,8 +425,9 @@ int cap_for(int k, const sofa_knn_params* p) {
 
 // workspace regions of one batch
 enum {
-  W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_U, W_U0, W_BEST, W_MASK, W_LBH, W_CTR, W_RES, W_RCNT, W_FLAG,
-  W_STAT, W_STATS, W_BAD, W_HIST, W_HBASE,
+  W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_BEST, W_MASK, W_LBH, W_CTR, W_RES, W_RCNT, W_FLAG, W_HIST, W_HBASE,
+  // read back by the host after the call: adjacent, one copy
+  W_U, W_U0, W_STAT, W_STATS, W_BAD,
   W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
   W_MLP, W_END
 };
@@ -682,17 +696,18 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     }
     SOFA_TRY(launch_finalize(a, d_ids, d_d, status, st, ev));
   }
-  std::vector<int32_t> hst(B);
-  std::vector<float> hu0(B);
-  std::vector<uint32_t> hu(B);
-  unsigned hbad = 0;
-  unsigned long long hstats[8];
-  SOFA_HIP(hipMemcpyAsync(hst.data(), status, 4 * B, hipMemcpyDeviceToHost, st));
-  SOFA_HIP(hipMemcpyAsync(hu0.data(), a.U0, 4 * B, hipMemcpyDeviceToHost, st));
-  SOFA_HIP(hipMemcpyAsync(hu.data(), a.U, 4 * B, hipMemcpyDeviceToHost, st));
-  SOFA_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
-  SOFA_HIP(hipMemcpyAsync(hstats, a.stats, 64, hipMemcpyDeviceToHost, st));
+  // the bounds, statuses and counters in one copy to pinned memory
+  const size_t back0 = lay.off[W_U], back1 = lay.off[W_BAD] + 4;
+  uint8_t* hb = ws->host_back(back1 - back0);
+  if (!hb) return set_error(SOFA_ENOMEM, "pinned host buffer of %zu bytes", back1 - back0);
+  SOFA_HIP(hipMemcpyAsync(hb, base + back0, back1 - back0, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipStreamSynchronize(st));
+  const int32_t* hst = reinterpret_cast<const int32_t*>(hb + (lay.off[W_STAT] - back0));
+  const float* hu0 = reinterpret_cast<const float*>(hb + (lay.off[W_U0] - back0));
+  const uint32_t* hu = reinterpret_cast<const uint32_t*>(hb + (lay.off[W_U] - back0));
+  const unsigned hbad = *reinterpret_cast<const unsigned*>(hb + (lay.off[W_BAD] - back0));
+  const unsigned long long* hstats =
+      reinterpret_cast<const unsigned long long*>(hb + (lay.off[W_STATS] - back0));
   if (hbad) return set_error(SOFA_EINVAL, "the queries contain non-finite values");
   if (ev && stats.queries == 0) {
     float t[6] = {0, 0, 0, 0, 0, 0};
