@@ -21,6 +21,8 @@ struct Bf16Args {
   uint64_t* smask;          // n_blocks x (64 G) survivor masks in sorted-slot order
   uint32_t* lcnt;           // n_leaves: queries whose (query, leaf) pair survives
   int64_t* loff;            // n_leaves: start of each leaf's list in lslot
+  uint32_t* bsum;           // 4 n_blocks: list entries of each 16-leaf sub-block
+  int64_t* boff;            // 4 n_blocks: start of each sub-block's lists in lslot
   uint16_t* lslot;          // per leaf, the sorted slots of those queries, ascending
   float4* slotc;            // per slot and pass: bound terms (a, b, c) and the query id
   int G;                    // query groups

@@ -304,36 +304,60 @@ __global__ void k_smask(const uint64_t* __restrict__ masks, int64_t n_blocks, in
 }
 
 // per leaf, the sorted slots of the queries whose (query, leaf) pair
-// survives: one workgroup per 64-leaf mask block, whose mask row is staged
-// through LDS 1024 slots at a time; wave w handles leaves 16w .. 16w + 15 of
-// the block.  PASS 0 counts (lcnt); PASS 1 fills lslot from the offsets loff.
+// survives.  Workgroup g takes the 16 leaves of sub-block g (a quarter of
+// mask block g / 4), whose mask row it stages through LDS 1024 slots at a
+// time; wave w handles leaves 4w .. 4w + 3 of the sub-block.  PASS 0 counts
+// (lcnt) and sums the sub-block (bsum); PASS 1 takes the sub-block's offset
+// from boff (the exclusive scan of bsum), writes each leaf's offset (loff)
+// and fills lslot.
+constexpr int kSubLeaves = 16;
+constexpr int kSubPerBlock = kLeavesPerItem / kSubLeaves;
+
 template <int PASS>
 __global__ __launch_bounds__(256) void k_leaf_lists(const uint64_t* __restrict__ smask, int64_t n_leaves,
                                                     int Spad, uint32_t* __restrict__ lcnt,
-                                                    const int64_t* __restrict__ loff,
+                                                    uint32_t* __restrict__ bsum,
+                                                    const int64_t* __restrict__ boff,
+                                                    int64_t* __restrict__ loff,
                                                     uint16_t* __restrict__ lslot) {
   constexpr int kRow = 1024;
   __shared__ uint64_t row[kRow];
+  __shared__ uint32_t wsum[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t* sm = smask + (int64_t)blockIdx.x * Spad;
-  const int64_t leaf0 = (int64_t)blockIdx.x * kLeavesPerItem + 16 * wave;
+  const int64_t sub = blockIdx.x;
+  const int64_t blk = sub / kSubPerBlock;
+  const int shift = (int)(sub % kSubPerBlock) * kSubLeaves + 4 * wave;  // bit of leaf j: shift + j
+  const uint64_t* sm = smask + blk * Spad;
+  const int64_t leaf0 = sub * kSubLeaves + 4 * wave;
   const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t c[16];
-  int64_t base[16];
+  uint32_t c[4];
+  int64_t base[4];
+  if (PASS) {
+    // offsets of the sub-block's leaves: an exclusive scan of their counts
+    const int64_t leaf = sub * kSubLeaves + lane;
+    const uint32_t cl = lane < kSubLeaves && leaf < n_leaves ? lcnt[leaf] : 0u;
+    uint32_t incl = cl;
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
-    c[j] = 0;
-    base[j] = (PASS && leaf0 + j < n_leaves) ? loff[leaf0 + j] : 0;
+    for (int o = 1; o < kSubLeaves; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const int64_t off = boff[sub] + (int64_t)(incl - cl);
+    if (wave == 0 && lane < kSubLeaves && leaf < n_leaves) loff[leaf] = off;
+#pragma unroll
+    for (int j = 0; j < 4; j++) base[j] = __shfl(off, 4 * wave + j);
   }
+#pragma unroll
+  for (int j = 0; j < 4; j++) c[j] = 0;
   for (int s0 = 0; s0 < Spad; s0 += kRow) {
     const int m = Spad - s0 < kRow ? Spad - s0 : kRow;  // a multiple of 64
     __syncthreads();  // the previous piece has been read
     for (int i = threadIdx.x; i < m; i += 256) row[i] = sm[s0 + i];
     __syncthreads();
     for (int t0 = 0; t0 < m; t0 += 64) {
-      const uint64_t wv = row[t0 + lane] >> (16 * wave);
+      const uint64_t wv = row[t0 + lane] >> shift;
 #pragma unroll
-      for (int j = 0; j < 16; j++) {
+      for (int j = 0; j < 4; j++) {
         const bool on = leaf0 + j < n_leaves && ((wv >> j) & 1ull);
         const uint64_t bal = __ballot(on);
         if (PASS && on) lslot[base[j] + c[j] + __popcll(bal & lt)] = (uint16_t)(s0 + t0 + lane);
@@ -341,15 +365,22 @@ __global__ __launch_bounds__(256) void k_leaf_lists(const uint64_t* __restrict__
       }
     }
   }
-  if (PASS == 0 && lane == 0) {
+  if (PASS == 0) {
+    uint32_t tot = 0;
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (leaf0 + j < n_leaves) lcnt[leaf0 + j] = c[j];
+    for (int j = 0; j < 4; j++) {
+      if (lane == 0 && leaf0 + j < n_leaves) lcnt[leaf0 + j] = c[j];
+      tot += c[j];
+    }
+    if (lane == 0) wsum[wave] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[sub] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   }
 }
 
-// exclusive prefix sum of the leaf counts: one workgroup walks tiles of 4096
-// counts (4 per thread, a block-wide scan each) while the next tile loads
+// exclusive prefix sum of counts (the leaf blocks' list lengths): one
+// workgroup walks tiles of 4096 counts (4 per thread, a block-wide scan
+// each) while the next tile loads
 __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t n,
                                                       int64_t* __restrict__ off) {
   constexpr int kTile = 4096;
@@ -401,10 +432,15 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 // per slot, for the current pass: with t = |x|^2 - 2P, a row survives when
 //   t <= a + b * max|xh| + c * max r_x + 2^-20 * max|x|^2   (leaf maxima)
 // where a = U lb_f - |q|^2 (1 - 2^-20), b = 2 (g |qh| + r_q), c = 2 |q|; .w = query id
+// With ccnt (B entries) and the work counter given, the same launch clears
+// them for the pass.
 __global__ void k_slotc(const float4* __restrict__ qmeta, const int32_t* __restrict__ perm, int B,
                         int Spad, const uint32_t* __restrict__ U, float lb_f, float gam,
-                        float4* __restrict__ slotc) {
+                        float4* __restrict__ slotc, uint32_t* __restrict__ ccnt,
+                        uint32_t* __restrict__ counter) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (counter && s == 0) *counter = 0u;
+  if (ccnt && s < B) ccnt[s] = 0u;
   if (s >= Spad) return;
   float4 c = make_float4(-INFINITY, 0.0f, 0.0f, __int_as_float(-1));
   if (s < B) {
@@ -1019,10 +1055,13 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
 // count, offsets, fill
 static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
   const int Spad = b.G * kGroup;
+  const int64_t n_sub = a.n_blocks * kSubPerBlock;
   k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
-  k_leaf_lists<0><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, nullptr);
-  k_scan_counts<<<1, 1024, 0, st>>>(b.lcnt, a.n_leaves, b.loff);
-  k_leaf_lists<1><<<(unsigned)a.n_blocks, 256, 0, st>>>(b.smask, a.n_leaves, Spad, nullptr, b.loff, b.lslot);
+  k_leaf_lists<0><<<(unsigned)n_sub, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, b.bsum, nullptr, nullptr,
+                                                   nullptr);
+  k_scan_counts<<<1, 1024, 0, st>>>(b.bsum, n_sub, b.boff);
+  k_leaf_lists<1><<<(unsigned)n_sub, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, nullptr, b.boff, b.loff,
+                                                   b.lslot);
 }
 
 sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
@@ -1065,10 +1104,12 @@ static float prune_gamma(const SearchArgs& a, const Bf16Args& b) {
   return (float)(a.n_pad + step) * 0x1p-23f;
 }
 
-static sofa_status launch_slotc(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
-  const int Spad = b.G * kGroup;
+// the bound terms of every slot from the current U; the candidate counts
+// (when `clear_ccnt`) and the work counter cleared in the same launch
+static sofa_status launch_slotc(const SearchArgs& a, const Bf16Args& b, bool clear_ccnt, hipStream_t st) {
+  const int Spad = b.G * kGroup;  // >= B
   k_slotc<<<nblk(Spad, 256), 256, 0, st>>>(b.qmeta, b.perm, a.B, Spad, a.U, a.lb_f, prune_gamma(a, b),
-                                           b.slotc);
+                                           b.slotc, clear_ccnt ? b.ccnt : nullptr, b.counter);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -1080,8 +1121,7 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   b.chunk_first = 0;
   b.chunk_stride = 1;
   b.n_items = (a.N + 255) / 256;
-  SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
-  SOFA_TRY(launch_slotc(a, b, st));
+  SOFA_TRY(launch_slotc(a, b, false, st));
   unsigned grid = 256 * kTileWaves;
   if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
   return launch_tiles<true>(a, b, grid, st);
@@ -1101,10 +1141,8 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
       for (int i = 0; i < 3; i++) (void)hipEventRecord(ev[i], st);
     return SOFA_OK;
   }
-  SOFA_TRY(launch_fill_u32(b.counter, 0u, 1, st));
-  SOFA_TRY(launch_fill_u32(b.ccnt, 0u, a.B, st));
-  // the bounds U of this pass (earlier passes tighten them)
-  SOFA_TRY(launch_slotc(a, b, st));
+  // the bounds U of this pass (earlier passes tighten them), cleared counts
+  SOFA_TRY(launch_slotc(a, b, true, st));
   unsigned grid = 256 * kTileWaves;
   if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
   if (ev) (void)hipEventRecord(ev[0], st);

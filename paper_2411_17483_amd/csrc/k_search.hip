@@ -105,13 +105,6 @@ __device__ __forceinline__ uint16_t f16_down(float x) {
   return (uint16_t)((e << 10) | ((f >> 13) & 0x3FFu));
 }
 
-__device__ __forceinline__ float f16_val(uint16_t h) {
-  const uint32_t e = (h >> 10) & 0x1Fu, m = h & 0x3FFu;
-  if (e == 0) return (float)m * 0x1p-24f;
-  if (e == 31) return INFINITY;
-  return __uint_as_float(((e + 112u) << 23) | (m << 13));
-}
-
 __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __shared__ float T[kTable];
   const int q = blockIdx.y;
@@ -121,7 +114,6 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __syncthreads();
   const uint4 sq = a.sq[q];
   const int lane = threadIdx.x & 63;
-  uint16_t* lbh = a.lbh + (int64_t)q * (a.n_blocks * kLeavesPerItem);
   uint64_t best = kEmpty;
   // two leaves per thread and iteration (independent lookup chains)
   for (int it = 0; it < kSegLeaves / 256; it += 2) {
@@ -143,7 +135,7 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
       const uint64_t key = ((uint64_t)__float_as_uint(lb2[u]) << 32) | (uint64_t)(uint32_t)leaf;
       if (valid2[u]) {
         best = key < best ? key : best;
-        lbh[leaf] = f16_down(lb2[u]);
+        a.lbh[((leaf / kLeavesPerItem) * a.B + q) * kLeavesPerItem + leaf % kLeavesPerItem] = f16_down(lb2[u]);
       }
     }
   }
@@ -156,44 +148,50 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
 }
 
 // survivor masks per 64-leaf block from the stored bounds: a leaf survives
-// when its bound is within U (with the slack of the FP32 bound sum).
-// Workgroup (x, q) takes blocks 256x .. 256x + 255 of query q, eight per
-// wave and step; one statistics atomic per workgroup.
-constexpr int kMaskBlocksPerStep = 8;
-constexpr int kMaskBlocksPerGroup = 256;
-
+// when its bound is within U (with the slack of the FP32 bound sum).  The
+// codes of non-negative values order like the values, so the test is an
+// integer compare against the code of U rounded down.  Workgroup (blk, y):
+// thread t takes query 256y + t, reads its 64 codes of the block (128
+// contiguous bytes) and writes the block's mask (consecutive queries,
+// consecutive words); one statistics atomic per workgroup.
 __global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
   __shared__ unsigned long long vis[4];
-  const int q = blockIdx.y;
+  const int64_t blk = blockIdx.x;
+  const int q = blockIdx.y * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float thr = __uint_as_float(a.U[q]) * (1.0f + 0x1p-16f);
-  const uint16_t* lbh = a.lbh + (int64_t)q * (a.n_blocks * kLeavesPerItem);
   unsigned long long visited = 0;
-  for (int step = 0; step < kMaskBlocksPerGroup / (4 * kMaskBlocksPerStep); step++) {
-    const int64_t blk0 =
-        (int64_t)blockIdx.x * kMaskBlocksPerGroup + (step * 4 + wave) * kMaskBlocksPerStep;
-    if (blk0 >= a.n_blocks) break;
-    uint16_t h[kMaskBlocksPerStep];
+  if (q < a.B) {
+    const uint32_t t = f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
+    const int64_t nl = a.n_leaves - blk * kLeavesPerItem;  // leaves of this block
+    const uint64_t valid = nl >= kLeavesPerItem ? ~0ull : ((1ull << nl) - 1ull);
+    const uint4* src = reinterpret_cast<const uint4*>(a.lbh + (blk * a.B + q) * kLeavesPerItem);
+    uint4 v[8];
 #pragma unroll
-    for (int i = 0; i < kMaskBlocksPerStep; i++) {
-      const int64_t leaf = (blk0 + i) * kLeavesPerItem + lane;
-      h[i] = leaf < a.n_leaves ? lbh[leaf] : (uint16_t)0;
-    }
+    for (int i = 0; i < 8; i++) v[i] = src[i];
+    uint64_t m = 0;
 #pragma unroll
-    for (int i = 0; i < kMaskBlocksPerStep; i++) {
-      const bool valid = (blk0 + i) * kLeavesPerItem + lane < a.n_leaves;
-      const uint64_t m = __ballot(valid && f16_val(h[i]) <= thr);
-      if (lane == 0 && blk0 + i < a.n_blocks) {
-        a.masks[(blk0 + i) * a.B + q] = m;
-        visited += (unsigned long long)__popcll(m);
+    for (int i = 0; i < 8; i++) {
+      const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int bit = 8 * i + 2 * e;
+        m |= (uint64_t)((w[e] & 0xFFFFu) <= t) << bit;
+        m |= (uint64_t)((w[e] >> 16) <= t) << (bit + 1);
       }
     }
+    m &= valid;
+    a.masks[blk * a.B + q] = m;
+    visited = (unsigned long long)__popcll(m);
   }
-  if (lane == 0) vis[wave] = visited;
-  __syncthreads();
-  if (threadIdx.x == 0 && a.stats) {
-    const unsigned long long v = vis[0] + vis[1] + vis[2] + vis[3];
-    if (v) atomicAdd(a.stats + 0, v);
+  if (a.stats) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) visited += __shfl_xor(visited, o);
+    if (lane == 0) vis[wave] = visited;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long v = vis[0] + vis[1] + vis[2] + vis[3];
+      if (v) atomicAdd(a.stats + 0, v);
+    }
   }
 }
 
@@ -604,7 +602,7 @@ static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) 
 }
 
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st) {
-  const dim3 gm(nblk(a.n_blocks, kMaskBlocksPerGroup), (unsigned)a.B);
+  const dim3 gm((unsigned)a.n_blocks, nblk(a.B, 256));
   k_leaf_mask<<<gm, 256, 0, st>>>(a);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
@@ -632,13 +630,22 @@ sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* rad
   return SOFA_OK;
 }
 
+// the per-call state cleared in one launch: best leaves, result counts,
+// smallest evicted keys, histograms, work-queue counters
+__global__ void k_front_clear(SearchArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.B) {
+    a.best[i] = kEmpty;
+    a.rescnt[i] = 0u;
+    a.evmin[i] = kEmpty;
+  }
+  if (i < (int64_t)a.B * kHistBins) a.hist[i] = 0u;
+  if (i < kQueues) a.counter[i] = 0u;
+}
+
 static sofa_status front_fills(const SearchArgs& a, hipStream_t st) {
-  const int64_t B = a.B;
-  k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.best, kEmpty, B);
-  k_fill_u32<<<nblk(B, 256), 256, 0, st>>>(a.rescnt, 0u, B);
-  k_fill_u64<<<nblk(B, 256), 256, 0, st>>>(a.evmin, kEmpty, B);
-  k_fill_u32<<<nblk(B * kHistBins, 256), 256, 0, st>>>(a.hist, 0u, B * kHistBins);
-  k_fill_u32<<<1, 256, 0, st>>>(a.counter, 0u, kQueues);
+  const int64_t n = std::max<int64_t>((int64_t)a.B * kHistBins, kQueues);
+  k_front_clear<<<nblk(n, 256), 256, 0, st>>>(a);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }

@@ -23,7 +23,7 @@ struct SearchArgs {
   float* U0;             // B radius bounds (+inf when none)
   uint64_t* best;        // B best leaf (bound bits << 32 | leaf)
   uint64_t* masks;       // n_blocks x B survivor masks
-  uint16_t* lbh;         // B x (n_blocks x 64) envelope bounds, FP16 codes rounded down
+  uint16_t* lbh;         // n_blocks x B x 64 envelope bounds, FP16 codes rounded down
   uint32_t* counter;     // work-queue counters (one per XCD queue)
   uint64_t* res;         // B x cap candidates (d32 bits << 32 | position)
   uint32_t* rescnt;      // B
