@@ -38,13 +38,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bf16_tiles_10Mx256_k10_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bf16_tiles_learned_10Mx256_k10_traffic.md")
 
 
-def measured_traffic():
-    """HBM bytes of the BF16 tile kernel per search from the committed counter
-    summary (FETCH_SIZE / WRITE_SIZE, calibrated on a copy of known size), or
-    (None, reason) when the kernel's source has changed since it was taken."""
+def measured_traffic(path):
+    """HBM bytes per launch of the BF16 tile kernel on `path` from the
+    committed counter summary (FETCH_SIZE / WRITE_SIZE of one search's
+    launches, calibrated on a copy of known size), or (None, reason) when the
+    summary covers another path or the kernel's source has changed since."""
     import hashlib
     try:
         line = [l for l in open(TRAFFIC_PROFILE) if l.startswith("traffic_json: ")][0]
@@ -54,8 +55,11 @@ def measured_traffic():
         return None, "no counter summary"
     if hashlib.sha256(src).hexdigest() != t["sha256"]:
         return None, "kernel changed since the counters were taken"
-    return t["bytes_per_search"], (f"profiles/{os.path.basename(TRAFFIC_PROFILE)}: {t['workload']}, "
-                                   f"FETCH_SIZE x {t['fetch_factor']:.4f} + WRITE_SIZE x {t['write_factor']:.4f}")
+    if t.get("path") != path:
+        return None, f"counters taken on path {t.get('path')}"
+    return t["bytes_per_search"] / t["launches"], (
+        f"profiles/{os.path.basename(TRAFFIC_PROFILE)}: {t['workload']}, mean of its {t['launches']} launches, "
+        f"FETCH_SIZE x {t['fetch_factor']:.4f} + WRITE_SIZE x {t['write_factor']:.4f}")
 
 
 def main():
@@ -69,7 +73,7 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--latency-queries", type=int, default=200)
-    ap.add_argument("--cpu-queries", type=int, default=32)
+    ap.add_argument("--cpu-queries", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path at k (for profiling runs)")
@@ -218,6 +222,7 @@ def main():
                                "ms_bf16_tiles", "ms_bf16_refine")},
                 "counters": {s: st[s] for s in ("leaves_total", "leaves_visited", "series_lb_checked",
                                                  "series_refined", "series_bf16_checked", "series_bf16_needed",
+                                                 "prune_passes",
                                                  "radius_fallbacks", "overflow_fallbacks")},
             }
             if kw.get("prune", 0):
@@ -265,6 +270,9 @@ def main():
         # algorithmic work: 2n flop for every (query, row) pair on the tile
         # kernel's lists (the leaf survived the envelope bound under the
         # bound of its pass), without the padding of the 64-query groups
+        # one launch per sampled pass: per-launch figures are the search's
+        # totals over its launches (the same ratio as the whole search)
+        launches = max(1, int(cnt["prune_passes"]))
         pairs = cnt["series_bf16_needed"]
         flops = 2.0 * n * pairs
         ms = stg["ms_bf16_tiles"]
@@ -272,13 +280,14 @@ def main():
         peak = PEAK_FP8_MFMA if paths[headline]["prune"] == 2 else PEAK_BF16_MFMA
         traffic, traffic_src = None, None
         if paths[headline]["prune"] == 1:
-            traffic, traffic_src = measured_traffic()
+            traffic, traffic_src = measured_traffic(headline)
         roofline = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
                     "traffic_source": traffic_src,
-                    "kernel": "k_bf16_tiles", "ms_per_launch": ms,
-                    "work_per_launch": {"flop": flops, "pairs_needed": pairs,
-                                        "pairs_computed": cnt["series_bf16_checked"]}}
+                    "kernel": "k_bf16_tiles", "launches_per_search": launches,
+                    "ms_per_launch": ms / launches, "ms_per_search": ms,
+                    "work_per_launch": {"flop": flops / launches, "pairs_needed": pairs / launches,
+                                        "pairs_computed": cnt["series_bf16_checked"] / launches}}
 
     cpu = None
     parity = None

@@ -249,6 +249,8 @@ typedef struct {
    * of each leaf times the queries on the leaf's list when its pass ran
    * (series_bf16_checked counts them in whole groups of 64 queries) */
   int64_t series_bf16_needed;
+  /* launches of the batched-distance tile kernel (one per sampled pass) */
+  int64_t prune_passes;
 } sofa_knn_stats;
 
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,

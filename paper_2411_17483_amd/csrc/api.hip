@@ -737,6 +737,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   stats.series_refined += (int64_t)hstats[2];
   stats.series_bf16_checked += (int64_t)hstats[3];
   stats.series_bf16_needed += (int64_t)hstats[5];
+  stats.prune_passes += bf_passes;
   stats.max_candidates = std::max<int64_t>(stats.max_candidates, (int64_t)hstats[4]);
   for (int64_t q = 0; q < B; q++) {
     if (hst[q] == 2) stats.overflow_evicted++;
@@ -807,6 +808,8 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.series_lb_checked += s2.series_lb_checked;
     stats.series_refined += s2.series_refined;
     stats.series_bf16_checked += s2.series_bf16_checked;
+    stats.series_bf16_needed += s2.series_bf16_needed;
+    stats.prune_passes += s2.prune_passes;
     stats.overflow_fallbacks += s2.overflow_fallbacks;
     stats.overflow_evicted += s2.overflow_evicted;
     stats.overflow_bf16_drop += s2.overflow_bf16_drop;

@@ -73,7 +73,8 @@ class KnnStats(ctypes.Structure):
                 ("ms_finalize", ctypes.c_double), ("ms_bf16_tiles", ctypes.c_double),
                 ("ms_bf16_refine", ctypes.c_double), ("overflow_evicted", _i64),
                 ("overflow_bf16_drop", _i64), ("overflow_band", _i64), ("max_candidates", _i64),
-                ("overflow_retries", _i64), ("series_bf16_needed", _i64)]
+                ("overflow_retries", _i64), ("series_bf16_needed", _i64),
+                ("prune_passes", _i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
