@@ -749,3 +749,21 @@ def test_tile_pair_counters(gpu_lib):
     n_leaves = (N + L - 1) // L
     assert 0 < need <= st["leaves_visited"] * L, st
     assert need <= done < need + n_leaves * 64 * L, st
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_prune_batch_above_1024_queries(gpu_lib, k):
+    """A batch of 1,500 queries (1,536 slots: the per-leaf lists are built
+    from mask rows staged in two pieces) on both prune tiers, with and
+    without list rebuilds (k = 10 rebuilds before its last two passes, k = 1
+    without a radius before its last), against the oracle."""
+    N, n, B = 12000 + 13, 64, 1500
+    X = synth.collection(N, n, "mix", seed=341)
+    bins, ix = _fp8_index(gpu_lib, X, precision=3)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=342)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    for prune in (1, 2):
+        ids, d = ix.knn(_t(Q), k, prune=prune)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+        st = ix.stats()
+        assert 0 < st["series_bf16_needed"] <= st["series_bf16_checked"], (prune, st)
