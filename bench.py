@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--quantile", type=float, default=0.9999)
     ap.add_argument("--headline", default="learned_bf16",
                     help="path whose k-NN rate is the reported value")
+    ap.add_argument("--no-isax", action="store_true", help="skip the iSAX summary comparison")
     ap.add_argument("--no-radius", action="store_true",
                     help="skip the radius networks and the learned paths (short profiling runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -255,6 +256,56 @@ def main():
         lat.append((time.perf_counter() - t0) * 1e3)
     lat = np.array(lat) if lat else np.zeros(1)
 
+    # the iSAX summary (PAA means, N(0,1) breakpoints) through the same path
+    # on the same data: rows left to the exact distance, tile pairs, queries/s,
+    # and the tightness of both summaries' word bounds on a sample of pairs
+    isax = None
+    if not args.headline_only and not args.no_isax:
+        Xd = torch.from_numpy(X).to(dev)
+        ibins = sofa.Bins.learn(Xd, max(1, N // 100), summary=1)
+        iix = sofa.Index(ibins, Xd, leaf_size=args.leaf, precision=1)
+        del Xd
+        torch.cuda.empty_cache()
+        isax = {"paths": {}}
+        for name, kw, steps in (("plain", dict(prune=0), 2), ("bf16", dict(prune=1), args.steps)):
+            iix.knn(Qd, k, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ids_i, _ = iix.knn(Qd, k, **kw)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            st = iix.stats()
+            isax["paths"][name] = {
+                "queries_per_s": B / sec, "ms_per_step": sec * 1e3,
+                "ids_identical_to_sfa": bool(np.array_equal(ids_i.cpu().numpy(), ids_by_path[headline])),
+                "counters": {c: st[c] for c in ("leaves_visited", "series_lb_checked", "series_refined",
+                                                "series_bf16_needed")},
+                "sfa_counters": {c: results[name][f"k{k}"]["counters"][c]
+                                 for c in ("leaves_visited", "series_lb_checked", "series_refined",
+                                           "series_bf16_needed")}}
+            log(f"isax {name} k={k}: {sec * 1e3:.2f} ms/step ({B / sec:.0f} q/s), refined "
+                f"{st['series_refined']} (SFA {results[name][f'k{k}']['counters']['series_refined']})")
+        # TLB: mean over sampled (query, row) pairs of the word bound / the distance
+        rng = np.random.default_rng(args.seed + 7)
+        pos = np.sort(rng.choice(N, size=min(N, 20000), replace=False))
+        tq = min(B, 16)
+        tlb = {}
+        for name, index in (("sfa", ix), ("isax", iix)):
+            _, ids_l, _, _ = index.export()
+            rows = ids_l.cpu().numpy()[pos]
+            _, lbw = index.lower_bounds(Qd[:tq].contiguous(), tables=False, lb=True)
+            lbw = lbw[:, torch.from_numpy(pos).to(dev)].cpu().numpy().astype(np.float64)
+            Xr = X[rows].astype(np.float64)
+            d2 = np.stack([((Xr - Q[b].astype(np.float64)) ** 2).sum(-1) for b in range(tq)])
+            tlb[name] = float(np.mean(np.sqrt(np.maximum(lbw, 0.0)) / np.sqrt(np.maximum(d2, 1e-300))))
+            del lbw
+        isax["tlb"] = {"sfa": tlb["sfa"], "isax": tlb["isax"],
+                       "sample": f"first {tq} queries x {pos.size} random rows, word bounds"}
+        log(f"TLB of the word bound: SFA {tlb['sfa']:.4f}, iSAX {tlb['isax']:.4f}")
+        del iix, ibins
+        torch.cuda.empty_cache()
+
     h = results[headline][f"k{k}"]
     cnt, stg = h["counters"], h["stages_ms"]
     if headline == "plain":
@@ -317,7 +368,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "k": k, "queries": int(len(lat)), "path": headline},
-        "paths": results, "paths_ids_identical": agree, "word_scan": word_scan,
+        "paths": results, "paths_ids_identical": agree, "word_scan": word_scan, "isax_summary": isax,
         "parity_sample": parity,
         "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
         "radius_models": model_info,

@@ -65,6 +65,15 @@ typedef struct {
   int32_t alpha;   /* symbols per value, 1..256 (default 256) */
   int32_t pool;    /* DFT coefficients in the pool, 1..32 and <= n/2-1 (default 16) */
   int32_t binning; /* 0 = equi-depth (default), 1 = equi-width */
+  /* 0 = SFA (default: Section IV-E, Algorithms 1-2).  1 = iSAX (Section
+   * IV-D): the means of l equal segments (n % l == 0), each scaled by
+   * sqrt(n/l) so that the basis rows are orthonormal, kept in time order and
+   * quantised with the alpha-1 equal-depth quantiles of N(0,1) (scaled the
+   * same way); `pool` and `binning` are ignored (the pool becomes the l
+   * segment values) and the lower bound weighs every value by 1 instead of
+   * SFA's 2.  The whole path (tables, envelopes, scans, prune tiers) is the
+   * same for both. */
+  int32_t summary;
 } sofa_bin_params;
 
 /* Learns bins from the stride sample of m rows of d_series (rows

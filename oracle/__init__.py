@@ -72,6 +72,16 @@ def _load():
         L.orc_sfa_lb2.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
         L.orc_sfa_lb2.restype = ctypes.c_double
         L.orc_dft_lb2.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.orc_paa.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
+        L.orc_paa.restype = None
+        L.orc_isax_breakpoints.argtypes = [ctypes.c_int, _vp]
+        L.orc_isax_breakpoints.restype = None
+        L.orc_isax_word.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+        L.orc_isax_word.restype = None
+        L.orc_isax_lb2.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_isax_lb2.restype = ctypes.c_double
+        L.orc_paa_dist2.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int]
+        L.orc_paa_dist2.restype = ctypes.c_double
         L.orc_dft_lb2.restype = ctypes.c_double
         L.orc_knn.argtypes = [_vp, ctypes.c_long, ctypes.c_int, _vp, ctypes.c_long, ctypes.c_int,
                               _vp, _vp, ctypes.c_int]
@@ -207,6 +217,50 @@ def sfa_lb2(qsel, word, beta, w=None):
     w = _f64(np.full(l, 2.0) if w is None else w)
     return _load().orc_sfa_lb2(qsel.ctypes.data, word.ctypes.data, beta.ctypes.data,
                                w.ctypes.data, l, am1 + 1)
+
+
+def paa(x, l):
+    """PAA means of one series over l equal segments (Section IV-D)."""
+    x = _f32(x)
+    out = np.zeros(l, dtype=np.float64)
+    _load().orc_paa(x.ctypes.data, x.shape[0], l, out.ctypes.data)
+    return out
+
+
+def isax_breakpoints(alpha):
+    """The alpha-1 equal-depth breakpoints of N(0,1)."""
+    out = np.zeros(max(alpha - 1, 1), dtype=np.float64)
+    _load().orc_isax_breakpoints(alpha, out.ctypes.data)
+    return out[:alpha - 1]
+
+
+def isax_words(X, l, alpha):
+    """(words m x l uint8, PAA means m x l) of the rows of X."""
+    X = _f32(np.atleast_2d(X))
+    m, n = X.shape
+    beta = _f64(np.append(isax_breakpoints(alpha), 0.0))
+    W = np.zeros((m, l), dtype=np.uint8)
+    M = np.zeros((m, l), dtype=np.float64)
+    L = _load()
+    for i in range(m):
+        L.orc_isax_word(X[i].ctypes.data, n, l, alpha, beta.ctypes.data, W[i].ctypes.data,
+                        M[i].ctypes.data)
+    return W, M
+
+
+def isax_lb2(qpaa, word, n, alpha):
+    """Squared iSAX lower bound of one query's PAA means against one word."""
+    qpaa = _f64(qpaa)
+    word = np.ascontiguousarray(word, dtype=np.uint8)
+    beta = _f64(np.append(isax_breakpoints(alpha), 0.0))
+    return _load().orc_isax_lb2(qpaa.ctypes.data, word.ctypes.data, beta.ctypes.data, n,
+                                qpaa.shape[0], alpha)
+
+
+def paa_dist2(q, x, l):
+    """Squared PAA distance n/l * sum (mean_j(q) - mean_j(x))^2."""
+    q, x = _f32(q), _f32(x)
+    return _load().orc_paa_dist2(q.ctypes.data, x.ctypes.data, q.shape[0], l)
 
 
 def dft_lb2(a, b, w):

@@ -16,7 +16,9 @@
  * pair of small sets, unquantised full-spectrum lower bound == distance,
  * brute-force k-NN against numpy lexsort, equi-depth/equi-width breakpoints on
  * constructed samples, MLP gradients against central finite differences,
- * Adam's first step.  The TLB diagnostic (orc_tlb) is "parity unpinned": the
+ * Adam's first step, iSAX breakpoints against an independent normal quantile,
+ * PAA bound == distance on piecewise-constant series.  The TLB diagnostic
+ * (orc_tlb) is "parity unpinned": the
  * paper reports TLB only on datasets that are not available.
  */
 #include <math.h>
@@ -225,6 +227,76 @@ double orc_sfa_lb2(const double* qsel, const unsigned char* word, const double* 
     s += w[j] * m * m;
   }
   return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* iSAX (Section IV-D): the series is cut into l segments of equal length
+ * n/l, each segment is replaced by its mean (PAA), and each mean is quantised
+ * with breakpoints that split N(0,1) into alpha equally likely bins. */
+
+/* PAA: the mean of each of the l segments (n divisible by l). */
+void orc_paa(const float* x, int n, int l, double* out) {
+  int seg = n / l;
+  for (int j = 0; j < l; j++) {
+    double s = 0.0;
+    for (int t = j * seg; t < (j + 1) * seg; t++) s += (double)x[t];
+    out[j] = s / (double)seg;
+  }
+}
+
+/* The alpha-1 breakpoints: beta(a) solves Phi(beta) = a/alpha with
+ * Phi(x) = erfc(-x/sqrt(2))/2; found by halving an interval in which Phi
+ * crosses a/alpha until its ends are adjacent doubles. */
+void orc_isax_breakpoints(int alpha, double* beta) {
+  for (int a = 1; a < alpha; a++) {
+    double p = (double)a / (double)alpha, lo = -50.0, hi = 50.0;
+    for (;;) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (0.5 * erfc(-mid / sqrt(2.0)) < p) lo = mid;
+      else hi = mid;
+    }
+    beta[a - 1] = 0.5 * (lo + hi);
+  }
+}
+
+/* iSAX word: the symbol of each PAA mean (half-open bins, as orc_symbol). */
+void orc_isax_word(const float* x, int n, int l, int alpha, const double* beta,
+                   unsigned char* word, double* paa) {
+  double* m = (double*)malloc(sizeof(double) * l);
+  orc_paa(x, n, l, m);
+  for (int j = 0; j < l; j++) {
+    if (paa) paa[j] = m[j];
+    word[j] = (unsigned char)orc_symbol(m[j], beta, alpha);
+  }
+  free(m);
+}
+
+/* Squared iSAX lower bound of a query's PAA means against a word: n/l times
+ * the sum of squared gaps between each query mean and the bin of the word's
+ * symbol (the same gap as orc_mind, one breakpoint set for every segment). */
+double orc_isax_lb2(const double* qpaa, const unsigned char* word, const double* beta, int n,
+                    int l, int alpha) {
+  double s = 0.0;
+  for (int j = 0; j < l; j++) {
+    double m = orc_mind(qpaa[j], word[j], beta, alpha);
+    s += m * m;
+  }
+  return (double)(n / l) * s;
+}
+
+/* Squared PAA distance (the unquantised bound): n/l times the sum of squared
+ * differences of the segment means. */
+double orc_paa_dist2(const float* q, const float* x, int n, int l) {
+  double* a = (double*)malloc(sizeof(double) * l);
+  double* b = (double*)malloc(sizeof(double) * l);
+  orc_paa(q, n, l, a);
+  orc_paa(x, n, l, b);
+  double s = 0.0;
+  for (int j = 0; j < l; j++) s += (a[j] - b[j]) * (a[j] - b[j]);
+  free(a);
+  free(b);
+  return (double)(n / l) * s;
 }
 
 /* Squared DFT lower bound (Eq. 1) on a set of unquantised Fourier values. */

@@ -57,9 +57,10 @@ static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); 
 // error bound of the FP32 projection per unit row norm: any accumulation
 // order of n_pad products (each exact or rounded once) plus the rounding of
 // the basis to FP32 stays within (n_pad + 4) u * sum|x_t b_t|, and
-// sum|x_t b_t| <= ||x|| ||b|| with ||b|| = 1/sqrt(2) for every pool value.
-static double eta_per_norm_for(int n_pad) {
-  return (double)(n_pad + 4) * 0x1p-24 * 1.01 * 0.70711;
+// sum|x_t b_t| <= ||x|| ||b|| with ||b|| = 1/sqrt(2) for every DFT pool
+// value and 1 for a PAA row.
+static double eta_per_norm_for(int n_pad, int summary) {
+  return (double)(n_pad + 4) * 0x1p-24 * 1.01 * (summary == 1 ? 1.0 : 0.70711);
 }
 
 }  // namespace sofa
@@ -74,6 +75,12 @@ static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
   if (p->l < 1 || p->l > kMaxL) return set_error(SOFA_EINVAL, "l=%d outside [1,16]", p->l);
   if (p->alpha < 1 || p->alpha > kAlphaMax)
     return set_error(SOFA_EINVAL, "alpha=%d outside [1,256]", p->alpha);
+  if (p->summary != 0 && p->summary != 1) return set_error(SOFA_EINVAL, "summary must be 0 (SFA) or 1 (iSAX)");
+  if (p->summary == 1) {
+    if (n < 4 || n > kMaxN || (n & 3)) return set_error(SOFA_EINVAL, "n=%d must be a multiple of 4 in [4,%d]", n, kMaxN);
+    if (n % p->l) return set_error(SOFA_EINVAL, "iSAX needs l=%d to divide n=%d", p->l, n);
+    return SOFA_OK;
+  }
   if (p->pool < 1 || p->pool > 32) return set_error(SOFA_EINVAL, "pool=%d outside [1,32]", p->pool);
   if (p->l > 2 * p->pool) return set_error(SOFA_EINVAL, "l=%d exceeds the pool's %d values", p->l, 2 * p->pool);
   if (p->binning != 0 && p->binning != 1) return set_error(SOFA_EINVAL, "binning must be 0 or 1");
@@ -82,10 +89,13 @@ static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
   return SOFA_OK;
 }
 
+// iSAX: the pool is the l segment values (one zero column when l is odd)
+static int pool_for(const sofa_bin_params* p) { return p->summary == 1 ? (p->l + 1) / 2 : p->pool; }
+
 static sofa_status bins_finish(sofa_bins* b, hipStream_t st) {
   b->n_pad = pad_len(b->n);
   b->ncol_pool = ((2 * b->pool + 15) / 16) * 16;
-  b->eta_per_norm = eta_per_norm_for(b->n_pad);
+  b->eta_per_norm = eta_per_norm_for(b->n_pad, b->summary);
   return launch_bins_tables(b, st);
 }
 
@@ -100,12 +110,13 @@ extern "C" sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t
   b->n = n;
   b->l = params->l;
   b->alpha = params->alpha;
-  b->pool = params->pool;
-  b->binning = params->binning;
+  b->summary = params->summary;
+  b->pool = pool_for(params);
+  b->binning = params->summary == 1 ? 0 : params->binning;
   b->var.assign(2 * b->pool, 0.0);
   b->beta.assign((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 0), 0.0);
   std::vector<double> beta_tmp((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 1));
-  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, S(stream),
+  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, b->summary, S(stream),
                                b->var.data(), b->sel, beta_tmp.data());
   if (s == SOFA_OK) {
     if (b->alpha > 1) std::copy(beta_tmp.begin(), beta_tmp.begin() + b->beta.size(), b->beta.begin());
@@ -129,8 +140,9 @@ extern "C" sofa_status sofa_bins_create(int32_t n, const sofa_bin_params* params
   b->n = n;
   b->l = params->l;
   b->alpha = params->alpha;
-  b->pool = params->pool;
-  b->binning = params->binning;
+  b->summary = params->summary;
+  b->pool = pool_for(params);
+  b->binning = params->summary == 1 ? 0 : params->binning;
   for (int j = 0; j < 16; j++) b->sel[j] = j < b->l ? sel[j] : 0;
   for (int j = 0; j < b->l; j++)
     if (sel[j] < 0 || sel[j] >= 2 * b->pool) {
@@ -164,6 +176,7 @@ extern "C" sofa_status sofa_bins_get(const sofa_bins* b, sofa_bin_params* params
     params->alpha = b->alpha;
     params->pool = b->pool;
     params->binning = b->binning;
+    params->summary = b->summary;
   }
   if (n) *n = b->n;
   if (sel) memcpy(sel, b->sel, sizeof(int32_t) * b->l);
@@ -223,6 +236,7 @@ static sofa_status clone_bins(const sofa_bins* src, sofa_bins* dst) {
   dst->alpha = src->alpha;
   dst->pool = src->pool;
   dst->binning = src->binning;
+  dst->summary = src->summary;
   memcpy(dst->sel, src->sel, sizeof dst->sel);
   dst->beta = src->beta;
   dst->var = src->var;

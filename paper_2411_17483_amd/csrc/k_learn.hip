@@ -7,13 +7,24 @@
 // order statistics or equi-width steps, Section IV-C).
 #include "kernels.h"
 
+#include <cmath>
+
 namespace sofa {
 
 static constexpr double kPi = 3.14159265358979323846;
 
-// Orthonormal DFT basis value of pool entry p at time t: p = 2(k-1) is Re X_k
-// (cos), p = 2(k-1)+1 is Im X_k (-sin); the angle uses (k*t mod n).
-__device__ __forceinline__ double basis64(int p, int t, int n) {
+// Basis value of pool entry p at time t.
+// SFA (summary 0): orthonormal DFT, p = 2(k-1) is Re X_k (cos), p = 2(k-1)+1
+// is Im X_k (-sin); the angle uses (k*t mod n).
+// iSAX (summary 1, Section IV-D): entry p < l is the mean of segment p of l
+// equal segments, scaled to an orthonormal row: (n/l)^-1/2 on the segment,
+// so that the coefficient is sqrt(n/l) times the PAA mean; entries p >= l
+// are zero.
+__device__ __forceinline__ double basis64(int p, int t, int n, int summary, int l) {
+  if (summary == 1) {
+    const int seg = n / l;
+    return (p < l && t / seg == p) ? 1.0 / sqrt((double)seg) : 0.0;
+  }
   int k = p / 2 + 1;
   long long kt = ((long long)k * t) % n;
   double ang = 2.0 * kPi * (double)kt / (double)n;
@@ -21,23 +32,23 @@ __device__ __forceinline__ double basis64(int p, int t, int n) {
   return (p & 1) ? -sin(ang) * s : cos(ang) * s;
 }
 
-__global__ void k_basis64(double* __restrict__ b64, int n, int np) {
+__global__ void k_basis64(double* __restrict__ b64, int n, int np, int summary, int l) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)np * n) return;
   int p = (int)(i / n), t = (int)(i % n);
-  b64[i] = basis64(p, t, n);
+  b64[i] = basis64(p, t, n, summary, l);
 }
 
 // Transposed FP32 basis for the MFMA projection: bt[r][t] for r < nrows,
 // t < n_pad.  Row r holds pool entry cols[r] (or r when cols is null); rows
 // >= nvalid and columns >= n are zero.
 __global__ void k_basis32_t(float* __restrict__ bt, int nrows, int nvalid, int n, int n_pad,
-                            const int* __restrict__ cols) {
+                            const int* __restrict__ cols, int summary, int l) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nrows * n_pad) return;
   int r = (int)(i / n_pad), t = (int)(i % n_pad);
   float v = 0.0f;
-  if (r < nvalid && t < n) v = (float)basis64(cols ? cols[r] : r, t, n);
+  if (r < nvalid && t < n) v = (float)basis64(cols ? cols[r] : r, t, n, summary, l);
   bt[i] = v;
 }
 
@@ -167,8 +178,33 @@ __global__ void k_beta32(const double* __restrict__ beta64, int l, int alpha,
 // ----------------------------------------------------------------------------
 static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
 
+// Phi^-1(p) of the standard normal: bisection on Phi(x) = erfc(-x / sqrt 2) / 2,
+// which is monotone, down to adjacent doubles
+static double normal_quantile(double p) {
+  double lo = -40.0, hi = 40.0;
+  for (int i = 0; i < 2000; i++) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (0.5 * std::erfc(-mid / std::sqrt(2.0)) < p) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// iSAX breakpoints (Section IV-D): the alpha - 1 equal-depth quantiles of
+// N(0,1), the same for every segment, scaled by sqrt(n/l) to the orthonormal
+// PAA coefficients
+void isax_breakpoints(int n, int l, int alpha, double* beta) {
+  const double s = std::sqrt((double)(n / l));
+  for (int a = 1; a < alpha; a++) {
+    const double b = normal_quantile((double)a / (double)alpha) * s;
+    for (int j = 0; j < l; j++) beta[(size_t)j * (alpha - 1) + a - 1] = b;
+  }
+}
+
 sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, int l, int alpha,
-                         int binning, hipStream_t st, double* h_var, int* h_sel, double* h_beta) {
+                         int binning, int summary, hipStream_t st, double* h_var, int* h_sel,
+                         double* h_beta) {
   int np = 2 * pool;
   int64_t mpad = 1;
   while (mpad < m) mpad <<= 1;
@@ -179,9 +215,19 @@ sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, 
   SOFA_TRY(sel.alloc(sizeof(int) * 16));
   SOFA_TRY(cols.alloc(sizeof(double) * l * mpad));
   SOFA_TRY(beta.alloc(sizeof(double) * l * (alpha > 1 ? alpha - 1 : 1)));
-  k_basis64<<<nblk((int64_t)np * n, 256), 256, 0, st>>>(b64.as<double>(), n, np);
+  k_basis64<<<nblk((int64_t)np * n, 256), 256, 0, st>>>(b64.as<double>(), n, np, summary, l);
   k_sample_dft<<<nblk(m, 4), 256, 0, st>>>(X, N, n, m, b64.as<double>(), np, F.as<double>());
   k_col_stats<<<np, 256, 0, st>>>(F.as<double>(), m, np, var.as<double>());
+  if (summary == 1) {
+    // iSAX keeps the l segments in time order and fixed breakpoints; the
+    // sample only reports the variance of each PAA coefficient
+    SOFA_HIP(hipGetLastError());
+    SOFA_HIP(hipMemcpyAsync(h_var, var.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    SOFA_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < 16; j++) h_sel[j] = j < l ? j : 0;
+    if (alpha > 1) isax_breakpoints(n, l, alpha, h_beta);
+    return SOFA_OK;
+  }
   k_select<<<1, 64, 0, st>>>(var.as<double>(), np, l, sel.as<int>());
   if (alpha > 1) {
     k_gather_cols<<<nblk((int64_t)l * mpad, 256), 256, 0, st>>>(F.as<double>(), m, np, sel.as<int>(),
@@ -209,9 +255,9 @@ sofa_status launch_bins_tables(sofa_bins* b, hipStream_t st) {
   SOFA_TRY(b->d_bt_pool.alloc(sizeof(float) * b->ncol_pool * n_pad));
   SOFA_TRY(b->d_beta32.alloc(sizeof(float) * kTable));
   k_basis32_t<<<nblk((int64_t)16 * n_pad, 256), 256, 0, st>>>(b->d_bt_sel.as<float>(), 16, b->l, n,
-                                                                n_pad, b->d_sel.as<int>());
+                                                                n_pad, b->d_sel.as<int>(), b->summary, b->l);
   k_basis32_t<<<nblk((int64_t)b->ncol_pool * n_pad, 256), 256, 0, st>>>(
-      b->d_bt_pool.as<float>(), b->ncol_pool, 2 * b->pool, n, n_pad, nullptr);
+      b->d_bt_pool.as<float>(), b->ncol_pool, 2 * b->pool, n, n_pad, nullptr, b->summary, b->l);
   DevBuf beta64;
   int nb = b->l * (b->alpha > 1 ? b->alpha - 1 : 1);
   SOFA_TRY(beta64.alloc(sizeof(double) * nb));

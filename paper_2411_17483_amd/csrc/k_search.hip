@@ -3,7 +3,8 @@
 //
 // Per batch of B queries:
 //  1. k_tables   per query: lower-bound table T[j][s] = w_j * mind_j(s, v_j)^2
-//                (Eq. 3, widened by the projection error bounds, rounded down),
+//                (Eq. 3, widened by the projection error bounds, rounded down;
+//                w = 2 for SFA, 1 for the iSAX summary of Section IV-D),
 //                the query's own symbols, in HBM (16 KB per query).
 //  2. k_leaf_lb  every (query, leaf): envelope bound sum_j T[j][clamp(s_q,lo,hi)]
 //                (valid because each table row is unimodal with its zero at the
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
                                                 const double* __restrict__ qnorm2,
                                                 const int* __restrict__ sel, int l,
                                                 const float* __restrict__ beta32,
-                                                double eta_x, double eta_per_norm,
+                                                double eta_x, double eta_per_norm, double weight,
                                                 float* __restrict__ tables,
                                                 uint4* __restrict__ sq) {
   __shared__ float v[16];
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
       double gap = 0.0;
       if (lo - vj > gap) gap = lo - vj;
       if (vj - hi > gap) gap = vj - hi;
-      double T = 2.0 * gap * gap * (1.0 - 0x1p-40);
+      double T = weight * gap * gap * (1.0 - 0x1p-40);
       out = __double2float_rd(T);
     }
     tables[(int64_t)q * kTable + i] = out;
@@ -623,8 +624,10 @@ sofa_status launch_prepare(const SearchArgs& a, const float* Q, const float* rad
                                                          const_cast<float*>(a.U0), bad);
   SOFA_TRY(launch_project(a.Qp, B, a.n_pad, a.n_pad, bins.d_bt_pool.as<float>(), bins.ncol_pool / 16,
                           a.n_pad, pool, bins.ncol_pool, nullptr, 0, nullptr, qnorm2, nullptr, st));
+  // Eq. 2 weighs each kept DFT value by 2 (a conjugate pair); PAA rows weigh 1
+  const double weight = bins.summary == 1 ? 1.0 : 2.0;
   k_tables<<<(unsigned)B, 256, 0, st>>>(pool, bins.ncol_pool, qnorm2, bins.d_sel.as<int>(), bins.l,
-                                        bins.d_beta32.as<float>(), a.eta_x, bins.eta_per_norm,
+                                        bins.d_beta32.as<float>(), a.eta_x, bins.eta_per_norm, weight,
                                         const_cast<float*>(a.tables), const_cast<uint4*>(a.sq));
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;

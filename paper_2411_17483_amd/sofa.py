@@ -39,7 +39,7 @@ class SofaError(RuntimeError):
 
 
 class BinParams(ctypes.Structure):
-    _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32)]
+    _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32), ("summary", _i32)]
 
 
 class BuildParams(ctypes.Structure):
@@ -173,29 +173,30 @@ def _dev(t, dtype=None):
 
 # --------------------------------------------------------------------------- #
 class Bins:
-    """Learned SFA quantisation (sofa_learn_bins / sofa_bins_create)."""
+    """Word quantisation (sofa_learn_bins / sofa_bins_create): learned SFA
+    (summary 0) or iSAX (summary 1: PAA means, N(0,1) breakpoints)."""
 
     def __init__(self, handle):
         self._h = _vp(handle)
 
     @classmethod
-    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0):
+    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0, summary=0):
         import torch
         L = load()
         N, n = X.shape
         h = _vp()
-        p = BinParams(l, alpha, pool, binning)
+        p = BinParams(l, alpha, pool, binning, summary)
         _check(L.sofa_learn_bins(_dev(X, torch.float32), N, n, m, ctypes.byref(p), _stream(),
                                  ctypes.byref(h)))
         return cls(h.value)
 
     @classmethod
-    def create(cls, n, sel, beta, var=None, pool=16, binning=0):
+    def create(cls, n, sel, beta, var=None, pool=16, binning=0, summary=0):
         L = load()
         sel = np.ascontiguousarray(sel, dtype=np.int32)
         beta = np.ascontiguousarray(beta, dtype=np.float64)
         l, am1 = beta.shape
-        p = BinParams(l, am1 + 1, pool, binning)
+        p = BinParams(l, am1 + 1, pool, binning, summary)
         v = None if var is None else np.ascontiguousarray(var, dtype=np.float64)
         h = _vp()
         _check(L.sofa_bins_create(n, ctypes.byref(p), sel.ctypes.data, beta.ctypes.data,
@@ -213,7 +214,7 @@ class Bins:
         _check(L.sofa_bins_get(self._h, None, None, sel.ctypes.data,
                                beta.ctypes.data if beta.size else None, var.ctypes.data))
         return {"n": n.value, "l": p.l, "alpha": p.alpha, "pool": p.pool, "binning": p.binning,
-                "sel": sel, "beta": beta, "var": var}
+                "summary": p.summary, "sel": sel, "beta": beta, "var": var}
 
     @property
     def eta_per_norm(self):

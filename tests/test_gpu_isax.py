@@ -1,0 +1,123 @@
+"""GPU tests of the iSAX summary (Section IV-D) through the same path as SFA:
+PAA means scaled to orthonormal basis rows, fixed N(0,1) breakpoints, the
+same tables, envelopes, scans and prune tiers.  Compared with the oracle's
+own PAA / iSAX definitions (pinned on the CPU in test_oracle_pins.py)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _isax(gpu_lib, X, m, l=16, alpha=256):
+    return gpu_lib.Bins.learn(_t(X), m, l=l, alpha=alpha, summary=1)
+
+
+@pytest.mark.parametrize("n,l,alpha", [(256, 16, 256), (64, 8, 4), (100, 4, 16)])
+def test_isax_bins_match_oracle(gpu_lib, n, l, alpha):
+    N, m = 6000, 1500
+    X = synth.collection(N, n, "mix", seed=n + alpha)
+    info = _isax(gpu_lib, X, m, l, alpha).get()
+    assert info["summary"] == 1 and info["l"] == l and info["pool"] == (l + 1) // 2
+    assert info["sel"].tolist() == list(range(l))
+    ref = np.sqrt(n // l) * oracle.isax_breakpoints(alpha)
+    assert info["beta"].shape == (l, alpha - 1)
+    assert np.max(np.abs(info["beta"] - ref[None, :])) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    # the variance of each scaled PAA value over the stride sample
+    rows = (np.arange(m, dtype=np.int64) * N) // m
+    P = np.array([oracle.paa(X[r], l) for r in rows]) * np.sqrt(n // l)
+    var = np.mean((P - P.mean(axis=0)) ** 2, axis=0)
+    assert np.allclose(info["var"][:l], var, rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_isax_transform_within_projection_bound(gpu_lib, n):
+    l, alpha = 16, 256
+    X = synth.collection(2001, n, "mix", seed=23 + n)
+    bins = _isax(gpu_lib, X, 2001, l, alpha)
+    info = bins.get()
+    pool, selv, words = bins.transform(_t(X))
+    pool, words = pool.cpu().numpy().astype(np.float64), words.cpu().numpy()
+    s = np.sqrt(n // l)
+    W, M = oracle.isax_words(X, l, alpha)
+    ref = M * s
+    eta = bins.eta_per_norm * np.sqrt(np.sum(X.astype(np.float64) ** 2, axis=1)) + 1e-30
+    err = np.abs(pool[:, :l] - ref)
+    assert np.all(err <= eta[:, None]), float(np.max(err / eta[:, None]))
+    beta = info["beta"][0]
+    gap = np.min(np.abs(ref[:, :, None] - beta[None, None, :]), axis=2)
+    clear = gap > eta[:, None] + 2.0 ** -23 * np.max(np.abs(beta)) + 1e-12
+    assert np.mean(clear) > 0.5
+    assert np.array_equal(words[:, :l][clear], W[clear])
+
+
+def test_isax_lower_bounds_never_exceed_distance(gpu_lib):
+    N, n, B = 3000, 256, 24
+    X = synth.collection(N, n, "mix", seed=31)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=32)
+    Q[:4] = synth.collection(4, n, "hf", seed=33)
+    bins = _isax(gpu_lib, X, N)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=64)
+    T, LB = ix.lower_bounds(_t(Q))
+    LB = LB.cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    ids = ids.cpu().numpy()
+    Xd = X.astype(np.float64)
+    W, _ = oracle.isax_words(X, 16, 256)
+    _, QM = oracle.isax_words(Q, 16, 256)
+    for b in range(B):
+        d2 = np.sum((Xd[ids] - Q[b].astype(np.float64)) ** 2, axis=1)
+        assert np.all(LB[b] <= d2 * (1 + 1e-12)), b
+    # and close to the oracle's iSAX bound where the symbols agree: the GPU
+    # bound is that bound shrunk by the projection error margins only
+    lb_ref = np.array([[oracle.isax_lb2(QM[b], W[ids[i]], n, 256) for i in range(0, N, 97)]
+                       for b in range(4, 8)])
+    got = LB[4:8, ::97]
+    assert np.all(got <= lb_ref * (1 + 1e-6) + 1e-6)
+    assert np.mean(got >= 0.9 * lb_ref - 1e-3) > 0.9
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_isax_knn_matches_oracle(gpu_lib, k):
+    N, n, B = 30000 + 11, 256, 40
+    X = synth.collection(N, n, "mix", seed=41)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=42)
+    bins = _isax(gpu_lib, X, 3000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=1)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    for prune in (0, 1):
+        ids, d = ix.knn(_t(Q), k, prune=prune)
+        ids, d = ids.cpu().numpy(), d.cpu().numpy()
+        assert np.array_equal(ids, ref_ids), (k, prune)
+        ref = np.sqrt(ref_d2)
+        assert np.all(np.abs(d.astype(np.float64) - ref) <= 1e-6 * np.maximum(ref, 1e-30))
+
+
+def test_sfa_prunes_more_than_isax(gpu_lib):
+    """The paper's comparison on synthetic data: with the same word length
+    and alphabet, the same leaves and the same scan, the series each summary
+    leaves to the exact distance.  On random walks SFA leaves fewer.  On the
+    high-frequency recipe (8 sinusoids with frequencies up to n/2) neither
+    summary prunes at k = 10: the energy lies above both the 16 segment means
+    and the k <= 16 DFT pool, and the distances concentrate."""
+    N, n, B, k = 40000, 256, 48, 10
+    res = {}
+    for kind in ("rw", "hf", "mix"):
+        X = synth.collection(N, n, kind, seed=51)
+        Q, _ = synth.queries(X, B, sigma=0.1, seed=52)
+        for summary in (0, 1):
+            bins = gpu_lib.Bins.learn(_t(X), 4000, summary=summary)
+            ix = gpu_lib.Index(bins, _t(X), leaf_size=256)
+            ix.knn(_t(Q), k)
+            st = ix.stats()
+            res[(kind, summary)] = (st["series_refined"], st["leaves_visited"], st["series_lb_checked"])
+    print(res)
+    assert res[("rw", 0)][0] < res[("rw", 1)][0], res
+    assert res[("hf", 0)][0] == res[("hf", 1)][0] == N * B, res

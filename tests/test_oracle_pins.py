@@ -348,3 +348,68 @@ def test_tlb_range_diagnostic():
                 ds.append(oracle.dist2(X[a], X[b]))
     t = oracle.tlb(np.array(lbs), np.array(ds))
     assert 0.0 < t <= 1.0
+
+
+# --------------------------------------------------------------------------- #
+# iSAX (Section IV-D): PAA means, N(0,1) equal-depth breakpoints, mindist.
+
+@pytest.mark.parametrize("alpha", [2, 3, 4, 8, 64, 256])
+def test_isax_breakpoints_are_normal_quantiles(alpha):
+    """Equal-depth bins of N(0,1): breakpoint a is the a/alpha quantile.
+    Pinned to scipy's inverse normal CDF and to symmetry about 0."""
+    from scipy.special import ndtri
+    b = oracle.isax_breakpoints(alpha)
+    assert b.shape == (alpha - 1,)
+    assert np.all(np.diff(b) > 0)
+    assert np.allclose(b, ndtri(np.arange(1, alpha) / alpha), rtol=0, atol=1e-12)
+    assert np.allclose(b, -b[::-1], rtol=0, atol=1e-12)
+
+
+def test_isax_quartiles_textbook_value():
+    """alpha = 4: the quartiles of N(0,1) are 0 and +-0.6744897501960817."""
+    b = oracle.isax_breakpoints(4)
+    assert abs(b[1]) < 1e-12
+    assert abs(b[2] - 0.6744897501960817) < 1e-12 and abs(b[0] + 0.6744897501960817) < 1e-12
+
+
+@pytest.mark.parametrize("n,l", [(16, 4), (64, 8), (256, 16), (256, 1)])
+def test_paa_exact_on_piecewise_constant_series(n, l):
+    """A series constant on each of the l segments is its own PAA, and the PAA
+    distance of two such series equals their Euclidean distance."""
+    rng = np.random.default_rng(n + l)
+    seg = n // l
+    a = np.repeat(rng.standard_normal(l), seg).astype(np.float32)
+    b = np.repeat(rng.standard_normal(l), seg).astype(np.float32)
+    assert np.array_equal(oracle.paa(a, l), a[::seg].astype(np.float64))
+    d = oracle.dist2(a, b)
+    assert abs(oracle.paa_dist2(a, b, l) - d) <= 1e-12 * d
+
+
+@pytest.mark.parametrize("n,l", [(64, 8), (256, 16)])
+@pytest.mark.parametrize("alpha", [4, 256])
+def test_isax_lb_below_paa_below_distance_every_pair(n, l, alpha):
+    """On every pair of a small z-normalised mix set: the quantised iSAX bound
+    <= the PAA distance <= the Euclidean distance."""
+    X = synth.collection(48, n, "mix", seed=7 * n + alpha)
+    W, M = oracle.isax_words(X, l, alpha)
+    for i in range(48):
+        for j in range(48):
+            lb = oracle.isax_lb2(M[i], W[j], n, alpha)
+            pd = oracle.paa_dist2(X[i], X[j], l)
+            d = oracle.dist2(X[i], X[j])
+            assert lb <= pd * (1 + 1e-12) + 1e-12, (i, j)
+            assert pd <= d * (1 + 1e-12) + 1e-12, (i, j)
+
+
+def test_isax_words_half_open_and_single_symbol():
+    """A PAA mean on a breakpoint takes the upper bin; one symbol gives the
+    all-zero word and a zero bound."""
+    b = oracle.isax_breakpoints(4)
+    x = np.repeat(np.array([b[2], b[0] - 1.0, 0.1, 2.0]), 4).astype(np.float32)
+    beta_f32 = oracle.isax_breakpoints(4)
+    W, M = oracle.isax_words(x, 4, 4)
+    expect = [oracle.symbol(m, beta_f32) for m in M[0]]
+    assert list(W[0]) == expect and W[0][1] == 0 and W[0][3] == 3
+    W1, M1 = oracle.isax_words(x, 4, 1)
+    assert np.all(W1 == 0)
+    assert oracle.isax_lb2(M1[0] + 5.0, W1[0], 16, 1) == 0.0
