@@ -74,6 +74,10 @@ typedef struct {
    * SFA's 2.  The whole path (tables, envelopes, scans, prune tiers) is the
    * same for both. */
   int32_t summary;
+  /* SFA only: 0 (default) keeps the l pool values of largest variance
+   * (Algorithm 1); 1 keeps the first l pool values (Re/Im of k = 1, 2, ...),
+   * the variant without variance selection of the TLB ablation (Section V-E) */
+  int32_t selection;
 } sofa_bin_params;
 
 /* Learns bins from the stride sample of m rows of d_series (rows

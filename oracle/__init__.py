@@ -62,7 +62,7 @@ def _load():
         L.orc_breakpoints.argtypes = [_vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, _vp]
         L.orc_select.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
         L.orc_learn_bins.argtypes = [_vp, ctypes.c_long, ctypes.c_int, ctypes.c_long, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
         L.orc_symbol.argtypes = [ctypes.c_double, _vp, ctypes.c_int]
         L.orc_symbol.restype = ctypes.c_int
         L.orc_sfa_word.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -170,15 +170,16 @@ def select(var, l):
     return sel
 
 
-def learn_bins(X, m, P=16, l=16, alpha=256, binning=0):
-    """Algorithm 1 on the stride sample of m rows: returns (var, sel, beta[l, alpha-1])."""
+def learn_bins(X, m, P=16, l=16, alpha=256, binning=0, selection=0):
+    """Algorithm 1 on the stride sample of m rows: returns (var, sel, beta[l, alpha-1]).
+    selection=1 keeps the first l pool values instead of the l of largest variance."""
     X = _f32(X)
     N, n = X.shape
     var = np.empty(2 * P, dtype=np.float64)
     sel = np.empty(l, dtype=np.int32)
     beta = np.empty((l, alpha - 1), dtype=np.float64)
-    _load().orc_learn_bins(X.ctypes.data, N, n, m, P, l, alpha, binning, var.ctypes.data,
-                           sel.ctypes.data, beta.ctypes.data)
+    _load().orc_learn_bins(X.ctypes.data, N, n, m, P, l, alpha, binning, int(selection),
+                           var.ctypes.data, sel.ctypes.data, beta.ctypes.data)
     return var, sel, beta
 
 

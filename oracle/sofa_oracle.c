@@ -154,8 +154,10 @@ void orc_select(const double* var, int npool, int l, int* sel) {
 /* MCB (Algorithm 1): stride sample of m rows (row floor(i*N/m)), DFT pool of
  * each sampled row, variance per pool value, top-l selection, then alpha
  * bins per selected value.  Outputs: var[2P], sel[l], beta[l][alpha-1]. */
+/* first != 0: keep the first l pool values instead of the l of largest
+ * variance (the ablation's variant without variance selection, Section V-E). */
 void orc_learn_bins(const float* X, long N, int n, long m, int P, int l, int alpha,
-                    int binning, double* var, int* sel, double* beta) {
+                    int binning, int first, double* var, int* sel, double* beta) {
   int np = 2 * P;
   double* F = (double*)malloc(sizeof(double) * m * np);
   for (long i = 0; i < m; i++) {
@@ -173,7 +175,10 @@ void orc_learn_bins(const float* X, long N, int n, long m, int P, int l, int alp
     }
     var[p] = s / (double)m;
   }
-  orc_select(var, np, l, sel);
+  if (first)
+    for (int j = 0; j < l; j++) sel[j] = j;
+  else
+    orc_select(var, np, l, sel);
   double* col = (double*)malloc(sizeof(double) * m);
   for (int j = 0; j < l; j++) {
     for (long i = 0; i < m; i++) col[i] = F[(size_t)i * np + sel[j]];

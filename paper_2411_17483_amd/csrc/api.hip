@@ -76,6 +76,7 @@ static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
   if (p->alpha < 1 || p->alpha > kAlphaMax)
     return set_error(SOFA_EINVAL, "alpha=%d outside [1,256]", p->alpha);
   if (p->summary != 0 && p->summary != 1) return set_error(SOFA_EINVAL, "summary must be 0 (SFA) or 1 (iSAX)");
+  if (p->selection != 0 && p->selection != 1) return set_error(SOFA_EINVAL, "selection must be 0 or 1");
   if (p->summary == 1) {
     if (n < 4 || n > kMaxN || (n & 3)) return set_error(SOFA_EINVAL, "n=%d must be a multiple of 4 in [4,%d]", n, kMaxN);
     if (n % p->l) return set_error(SOFA_EINVAL, "iSAX needs l=%d to divide n=%d", p->l, n);
@@ -111,13 +112,14 @@ extern "C" sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t
   b->l = params->l;
   b->alpha = params->alpha;
   b->summary = params->summary;
+  b->selection = params->summary == 1 ? 0 : params->selection;
   b->pool = pool_for(params);
   b->binning = params->summary == 1 ? 0 : params->binning;
   b->var.assign(2 * b->pool, 0.0);
   b->beta.assign((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 0), 0.0);
   std::vector<double> beta_tmp((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 1));
-  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, b->summary, S(stream),
-                               b->var.data(), b->sel, beta_tmp.data());
+  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, b->summary,
+                               b->selection, S(stream), b->var.data(), b->sel, beta_tmp.data());
   if (s == SOFA_OK) {
     if (b->alpha > 1) std::copy(beta_tmp.begin(), beta_tmp.begin() + b->beta.size(), b->beta.begin());
     s = bins_finish(b, S(stream));
@@ -177,6 +179,7 @@ extern "C" sofa_status sofa_bins_get(const sofa_bins* b, sofa_bin_params* params
     params->pool = b->pool;
     params->binning = b->binning;
     params->summary = b->summary;
+    params->selection = b->selection;
   }
   if (n) *n = b->n;
   if (sel) memcpy(sel, b->sel, sizeof(int32_t) * b->l);
@@ -237,6 +240,7 @@ static sofa_status clone_bins(const sofa_bins* src, sofa_bins* dst) {
   dst->pool = src->pool;
   dst->binning = src->binning;
   dst->summary = src->summary;
+  dst->selection = src->selection;
   memcpy(dst->sel, src->sel, sizeof dst->sel);
   dst->beta = src->beta;
   dst->var = src->var;

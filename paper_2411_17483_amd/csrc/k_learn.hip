@@ -203,8 +203,8 @@ void isax_breakpoints(int n, int l, int alpha, double* beta) {
 }
 
 sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, int l, int alpha,
-                         int binning, int summary, hipStream_t st, double* h_var, int* h_sel,
-                         double* h_beta) {
+                         int binning, int summary, int selection, hipStream_t st, double* h_var,
+                         int* h_sel, double* h_beta) {
   int np = 2 * pool;
   int64_t mpad = 1;
   while (mpad < m) mpad <<= 1;
@@ -228,7 +228,14 @@ sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, 
     if (alpha > 1) isax_breakpoints(n, l, alpha, h_beta);
     return SOFA_OK;
   }
-  k_select<<<1, 64, 0, st>>>(var.as<double>(), np, l, sel.as<int>());
+  if (selection == 1) {
+    // the first l pool values, in pool order
+    int first[16];
+    for (int j = 0; j < 16; j++) first[j] = j < l ? j : 0;
+    SOFA_HIP(hipMemcpyAsync(sel.p, first, sizeof(first), hipMemcpyHostToDevice, st));
+  } else {
+    k_select<<<1, 64, 0, st>>>(var.as<double>(), np, l, sel.as<int>());
+  }
   if (alpha > 1) {
     k_gather_cols<<<nblk((int64_t)l * mpad, 256), 256, 0, st>>>(F.as<double>(), m, np, sel.as<int>(),
                                                                   l, cols.as<double>(), mpad);

@@ -7,8 +7,8 @@ namespace sofa {
 
 // MCB learning (k_learn.hip): fills h_var[2*pool], h_sel[16], h_beta[l*(alpha-1)].
 sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, int l, int alpha,
-                         int binning, int summary, hipStream_t st, double* h_var, int* h_sel,
-                         double* h_beta);
+                         int binning, int summary, int selection, hipStream_t st, double* h_var,
+                         int* h_sel, double* h_beta);
 // the fixed iSAX breakpoints, l x (alpha - 1) row-major
 void isax_breakpoints(int n, int l, int alpha, double* beta);
 // Device tables of a bins object (basis rows, FP32 breakpoints, selection).

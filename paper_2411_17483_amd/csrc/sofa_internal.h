@@ -64,6 +64,7 @@ struct DevBuf {
 struct sofa_bins {
   int32_t n = 0, n_pad = 0, l = 16, alpha = 256, pool = 16, binning = 0;
   int32_t summary = 0;        // 0 SFA, 1 iSAX (PAA means, N(0,1) breakpoints)
+  int32_t selection = 0;      // SFA: 0 largest variance, 1 first l pool values
   int32_t sel[16] = {0};
   std::vector<double> beta;  // l x (alpha-1)
   std::vector<double> var;   // 2*pool

@@ -39,7 +39,8 @@ class SofaError(RuntimeError):
 
 
 class BinParams(ctypes.Structure):
-    _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32), ("summary", _i32)]
+    _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32), ("summary", _i32),
+                ("selection", _i32)]
 
 
 class BuildParams(ctypes.Structure):
@@ -180,12 +181,12 @@ class Bins:
         self._h = _vp(handle)
 
     @classmethod
-    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0, summary=0):
+    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0, summary=0, selection=0):
         import torch
         L = load()
         N, n = X.shape
         h = _vp()
-        p = BinParams(l, alpha, pool, binning, summary)
+        p = BinParams(l, alpha, pool, binning, summary, selection)
         _check(L.sofa_learn_bins(_dev(X, torch.float32), N, n, m, ctypes.byref(p), _stream(),
                                  ctypes.byref(h)))
         return cls(h.value)
@@ -214,7 +215,7 @@ class Bins:
         _check(L.sofa_bins_get(self._h, None, None, sel.ctypes.data,
                                beta.ctypes.data if beta.size else None, var.ctypes.data))
         return {"n": n.value, "l": p.l, "alpha": p.alpha, "pool": p.pool, "binning": p.binning,
-                "summary": p.summary, "sel": sel, "beta": beta, "var": var}
+                "summary": p.summary, "selection": p.selection, "sel": sel, "beta": beta, "var": var}
 
     @property
     def eta_per_norm(self):

@@ -40,6 +40,17 @@ def test_learn_bins_matches_oracle(gpu_lib, binning, alpha):
     assert np.max(np.abs(b["beta"] - beta)) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("binning", [0, 1])
+def test_learn_bins_first_values_matches_oracle(gpu_lib, binning):
+    """selection = 1: the first l pool values, with breakpoints learned on them."""
+    X = synth.collection(20000, 256, "mix", seed=103)
+    b = _bins(gpu_lib, X, 3000, alpha=64, binning=binning, selection=1).get()
+    var, sel, beta = oracle.learn_bins(X, 3000, P=16, l=16, alpha=64, binning=binning, selection=1)
+    assert b["selection"] == 1 and b["sel"].tolist() == list(range(16)) == sel.tolist()
+    assert np.allclose(b["var"], var, rtol=1e-10, atol=0)
+    assert np.max(np.abs(b["beta"] - beta)) <= 1e-12 * np.max(np.abs(beta))
+
+
 def test_learn_bins_small_pool_and_l(gpu_lib):
     X = synth.collection(5000, 64, "hf", seed=5)
     b = _bins(gpu_lib, X, 5000, l=6, alpha=16, pool=8).get()

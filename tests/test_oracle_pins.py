@@ -413,3 +413,18 @@ def test_isax_words_half_open_and_single_symbol():
     W1, M1 = oracle.isax_words(x, 4, 1)
     assert np.all(W1 == 0)
     assert oracle.isax_lb2(M1[0] + 5.0, W1[0], 16, 1) == 0.0
+
+
+@pytest.mark.parametrize("binning", [0, 1])
+def test_learn_bins_first_values(binning):
+    """selection = 1 keeps pool values 0..l-1 and learns their breakpoints
+    exactly as for the same columns chosen by variance: each column's
+    breakpoints equal orc_breakpoints of that column of the stride sample."""
+    X = synth.collection(900, 64, "mix", seed=61)
+    m, P, l, alpha = 300, 8, 6, 16
+    var, sel, beta = oracle.learn_bins(X, m, P=P, l=l, alpha=alpha, binning=binning, selection=1)
+    assert sel.tolist() == list(range(l))
+    rows = (np.arange(m, dtype=np.int64) * X.shape[0]) // m
+    F = oracle.dft_pool(X[rows], P)
+    for j in range(l):
+        assert np.array_equal(beta[j], oracle.breakpoints(F[:, j], alpha, binning))
