@@ -13,7 +13,11 @@ each variant and alphabet size it reports:
   - the plain SFA/iSAX search at k = 10 over 200 queries: queries/s and the
     rows left to the exact distance per query (the pruning the bound buys).
 The sampling sweep (mix, SFA EW + variance, alpha = 256) also times the BF16
-prune.  Prints one JSON line; `--N` shrinks the collections.
+prune.  Then, the analogue of the paper's index-creation and leaf-size
+studies: `sofa_build` throughput on a `--build-N` x n mix collection (GB/s of
+FP32 input, with and without the BF16 + FP8 copies), and queries/s of the
+plain and BF16 paths against the leaf size on the mix collection.  Prints one
+JSON line; `--N` shrinks the collections.
 """
 import argparse
 import json
@@ -50,6 +54,8 @@ def main():
     ap.add_argument("--alphas", default="4,8,16,32,64,128,256")
     ap.add_argument("--kinds", default="rw,hf,mix")
     ap.add_argument("--rates", default="0.001,0.005,0.01,0.05,0.1,0.2")
+    ap.add_argument("--leaves", default="64,128,256,512,1024,2048,4096")
+    ap.add_argument("--build-N", type=int, default=10_000_000)
     args = ap.parse_args()
 
     import torch
@@ -107,6 +113,22 @@ def main():
             log(f"{kind} {name}: TLB " + " ".join(f"{t:.3f}" for t in tl) +
                 f" | rows refined/query at alpha {alphas[-1]}: {pl[-1]['rows_refined_per_query']:.0f}")
         if kind == "mix":
+            out["leaf_size"] = []
+            bins = sofa.Bins.learn(Xd, max(1, N // 100), alpha=256, **VARIANTS["SFA EW+VAR"])
+            for L in [int(x) for x in args.leaves.split(",")]:
+                ix = sofa.Index(bins, Xd, leaf_size=L, precision=1 if L % 256 == 0 else 0)
+                row = {"leaf_size": L}
+                for prune in ((0, 1) if L % 256 == 0 else (0,)):
+                    ix.knn(Qd, k, prune=prune)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ix.knn(Qd, k, prune=prune)
+                    torch.cuda.synchronize()
+                    row[f"prune{prune}_queries_per_s"] = B / (time.perf_counter() - t0)
+                    row[f"prune{prune}_leaves_visited_per_query"] = ix.stats()["leaves_visited"] / B
+                out["leaf_size"].append(row)
+                log(f"leaf {L}: " + ", ".join(f"{a} {b:.0f}" for a, b in row.items() if a.endswith("per_s")))
+                del ix
             for rate in [float(r) for r in args.rates.split(",")]:
                 bins = sofa.Bins.learn(Xd, max(1, int(N * rate)), alpha=256, **VARIANTS["SFA EW+VAR"])
                 r = measure(X, Q, Xd, Qd, bins, prunes=(0, 1))
@@ -114,6 +136,28 @@ def main():
                 log(f"sampling {rate:.3%}: TLB {r['tlb']:.3f}, plain {r['prune0']['queries_per_s']:.0f} q/s, "
                     f"BF16 {r['prune1']['queries_per_s']:.0f} q/s")
         del Xd, Qd
+        torch.cuda.empty_cache()
+    # build throughput at full size
+    if args.build_N > 0:
+        Nb = args.build_N
+        X = synth.collection(Nb, n, "mix", seed=13)
+        Xd = torch.from_numpy(X).to(dev)
+        del X
+        bins = sofa.Bins.learn(Xd, max(1, Nb // 100))
+        torch.cuda.synchronize()
+        out["build"] = {"N": Nb, "n": n, "input_gb": Nb * n * 4 / 1e9}
+        for prec, name in ((0, "sfa_only"), (3, "with_bf16_fp8")):
+            sofa.Index(bins, Xd, leaf_size=256, precision=prec)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ix = sofa.Index(bins, Xd, leaf_size=256, precision=prec)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            out["build"][name] = {"seconds": sec, "input_gb_per_s": Nb * n * 4 / 1e9 / sec,
+                                  "index_gb": ix.info()["device_bytes"] / 1e9}
+            log(f"build {Nb}x{n} ({name}): {sec:.3f} s, {Nb * n * 4 / 1e9 / sec:.0f} GB/s of input")
+            del ix
+        del Xd
         torch.cuda.empty_cache()
     out["alphas"] = alphas
     print(json.dumps(out), flush=True)
