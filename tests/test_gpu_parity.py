@@ -778,3 +778,18 @@ def test_prune_batch_above_1024_queries(gpu_lib, k):
         _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
         st = ix.stats()
         assert 0 < st["series_bf16_needed"] <= st["series_bf16_checked"], (prune, st)
+
+
+@pytest.mark.parametrize("L", [512, 1024])
+def test_prune_large_leaves(gpu_lib, L):
+    """Leaves of several 256-row chunks: every chunk of a leaf runs the leaf's
+    query list; both prune tiers against the oracle, k = 10."""
+    N, n, B = 20000 + 29, 128, 60
+    X = synth.collection(N, n, "mix", seed=361)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L, precision=3)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=362)
+    ref_ids, ref_d2 = oracle.knn(X, Q, 10)
+    for prune in (0, 1, 2):
+        ids, d = ix.knn(_t(Q), 10, prune=prune)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
