@@ -207,19 +207,29 @@ typedef struct {
    * Fourier pool values, computed inside the call. */
   const sofa_radius* radius_model;
   /* 0 (default): seed the bound with the exact distances of the leaf with
-   * the smallest envelope bound (the approximate search of Section IV-A);
-   * 1: skip that seed. */
+   * the smallest envelope bound (the approximate first answer of Section
+   * IV-C); 1: skip that seed. */
   int32_t no_seed_leaf;
   sofa_workspace* ws; /* NULL: the index's own workspace (one caller at a time) */
   /* Candidate slots per query in the workspace (0 = library default).  A
    * smaller value only costs time: when in-band candidates are dropped the
    * query is finished by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
-  /* BF16/FP8 prune only: 0 (default) and 1 run chunk samples of stride 1024
-   * and 32 before the remaining chunks (each pass prunes with the bound the
-   * earlier ones established, which also tightens a loose radius); 2 runs
-   * one pass over all chunks (best when the radius is tight, e.g. k = 1). */
+  /* BF16/FP8 prune only: 0 (default) and 1 run the 256-row chunks in passes
+   * of decreasing stride (1024, 32, 1 for k <= 3; 1024, 128, 16, 2, 1 from
+   * k = 4 on), each selecting candidates with the bound the earlier passes
+   * established, with the (query, leaf) lists rebuilt from that bound before
+   * the last passes; 2 runs one pass over all chunks (best when the radius
+   * is tight, e.g. k = 1). */
   int32_t sampling;
+  /* 0 (default): exact search.  1..64: APPROXIMATE search, no exactness
+   * guarantee: the first answer of Section IV-C (scan the leaf of smallest
+   * lower bound) widened to the approx_leaves leaves of smallest envelope
+   * bound per query, whose rows get exact distances and the FP64 ranking;
+   * the k best of those rows are returned (ids -1 / +inf distances when they
+   * hold fewer than k rows).  prune, radii and fallbacks do not apply.  The
+   * paper names approximate search as future work (Section VI). */
+  int32_t approx_leaves;
 } sofa_knn_params;
 
 /* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 100).

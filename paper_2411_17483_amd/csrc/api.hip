@@ -447,7 +447,7 @@ enum {
   // read back by the host after the call: adjacent, one copy
   W_U, W_U0, W_STAT, W_STATS, W_BAD,
   W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_BSUM, W_BOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
-  W_MLP, W_END
+  W_MLP, W_APPROX, W_END
 };
 
 struct Layout {
@@ -512,6 +512,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_QSCALE] = bf ? (size_t)G * kGroup * 4 : 0;
   sz[W_BCTR] = bf ? 64 : 0;
   sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
+  sz[W_APPROX] = (p && p->approx_leaves > 0) ? (size_t)B * kApproxMax * 4 : 0;
   Layout L;
   static_assert(sizeof(L.off) / sizeof(L.off[0]) == W_END, "one offset per workspace region");
   size_t o = 0;
@@ -554,6 +555,8 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
       return set_error(SOFA_EINVAL, "the radius model takes %d features, the index has %d pool values",
                        m->dims.D, 2 * ix->bins.pool);
   }
+  if (params && (params->approx_leaves < 0 || params->approx_leaves > kApproxMax))
+    return set_error(SOFA_EINVAL, "approx_leaves=%d outside [0,%d]", params->approx_leaves, kApproxMax);
   if (params && params->prune != 0) {
     if (params->prune != 1 && params->prune != 2)
       return set_error(SOFA_EINVAL, "prune must be 0 (off), 1 (BF16) or 2 (FP8)");
@@ -642,16 +645,24 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 16, st));
   hipEvent_t* ev = ws->events();
   if (ev) (void)hipEventRecord(ev[0], st);
-  SOFA_TRY(launch_prepare(a, d_q, p ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
+  // approximate search: no radius, prune or fallback applies
+  const int approx = p ? p->approx_leaves : 0;
+  SOFA_TRY(launch_prepare(a, d_q, (p && !approx) ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
-  const bool use_model = p && p->radius_model && !p->d_radius;
+  const bool use_model = !approx && p && p->radius_model && !p->d_radius;
   if (use_model)
     SOFA_TRY(launch_model_radius(p->radius_model, (const float*)at(W_POOL), ix->bins.ncol_pool, B,
                                  (float*)at(W_MLP), a.U0, st));
-  const bool has_radius = p && (p->d_radius || use_model);
-  const bool bf = p && (p->prune == 1 || p->prune == 2);
+  const bool has_radius = !approx && p && (p->d_radius || use_model);
+  const bool bf = !approx && p && (p->prune == 1 || p->prune == 2);
   int bf_passes = 0;
-  if (!bf) {
+  if (approx > 0) {
+    // no seed: its leaf (chosen on the FP32 bound) need not be among the
+    // scanned ones (chosen on the rounded codes), and its bound would cut them
+    a.seed_leaf = 0;
+    SOFA_TRY(launch_approx(a, approx, (int32_t*)at(W_APPROX), st, ev));
+    SOFA_TRY(launch_finalize(a, d_ids, d_d, status, st, ev));
+  } else if (!bf) {
     SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
   } else {
     uint32_t* cev = (uint32_t*)at(W_CEV);
@@ -762,6 +773,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     if (hst[q] == 4) stats.overflow_bf16_drop++;
     if (hst[q] == 5) stats.overflow_band++;
   }
+  if (approx > 0) return SOFA_OK;  // whatever the scanned leaves hold is the answer
   std::vector<int64_t> redo, tighten;
   std::vector<float> tighten_r;
   for (int64_t q = 0; q < B; q++) {

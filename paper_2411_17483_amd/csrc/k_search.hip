@@ -683,6 +683,120 @@ sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d,
   return SOFA_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Approximate search (no exactness guarantee): the first answer of Section
+// IV-C (descend to the leaf of smallest lower bound and scan it) widened to
+// the M leaves of smallest envelope bound per query.
+
+// the M leaves of smallest envelope bound of query blockIdx.x (ties: lower
+// leaf), from the stored FP16 codes: wave w scans mask blocks w, w + 4, ...
+// and keeps a sorted list of its M smallest (code, leaf) keys; wave 0 merges
+__global__ __launch_bounds__(256) void k_approx_leaves(SearchArgs a, int M, int32_t* __restrict__ out) {
+  __shared__ uint64_t part[4][64];
+  const int q = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  WaveList<1> wl;
+  wl.reset();
+  auto offer = [&](uint64_t key) {
+    uint64_t ins = __ballot(key < wl.at(M - 1));
+    while (ins) {
+      const int l = __builtin_ctzll(ins);
+      ins &= ins - 1;
+      const uint64_t kk = __shfl(key, l);
+      if (kk < wl.at(M - 1)) wl.insert(kk, lane);
+    }
+  };
+  for (int64_t blk = wave; blk < a.n_blocks; blk += 4) {
+    const int64_t leaf = blk * kLeavesPerItem + lane;
+    const uint64_t key = leaf < a.n_leaves
+                             ? ((uint64_t)a.lbh[(blk * a.B + q) * kLeavesPerItem + lane] << 32) | (uint64_t)leaf
+                             : kEmpty;
+    offer(key);
+  }
+  part[wave][lane] = wl.e[0];
+  __syncthreads();
+  if (wave == 0) {
+    for (int w = 1; w < 4; w++) offer(part[w][lane]);
+    if (lane < M) out[(int64_t)q * kApproxMax + lane] = wl.e[0] == kEmpty ? -1 : (int32_t)(uint32_t)wl.e[0];
+  }
+}
+
+// exact FP32 distances to the rows of the selected leaves (waves take leaves
+// round-robin, 16 rows in flight per step), in-band candidates flushed for
+// the final FP64 ranking
+template <int NIT, int R>
+__global__ __launch_bounds__(256) void k_approx_scan(SearchArgs a, int M, const int32_t* __restrict__ leaves) {
+  const int q = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  float4 qr[NIT];
+  load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
+  float Umin = __uint_as_float(__atomic_load_n(a.U + q, __ATOMIC_RELAXED));
+  const float U_in = Umin;
+  WaveList<R> wl;
+  wl.reset();
+  unsigned long long scanned = 0;
+  for (int i = wave; i < M; i += 4) {
+    const int leaf = leaves[(int64_t)q * kApproxMax + i];
+    if (leaf < 0) continue;  // fewer leaves than M
+    const int64_t start = (int64_t)leaf * a.L, end = start + a.L < a.N ? start + a.L : a.N;
+    scanned += (unsigned long long)(end - start);
+    for (int64_t p0 = start; p0 < end; p0 += 4 * kRefRows) {
+      uint32_t pm[kRefRows];
+      bool am[kRefRows];
+#pragma unroll
+      for (int r = 0; r < kRefRows; r++) {
+        const int64_t p = p0 + 4 * r + g;
+        am[r] = p < end;
+        pm[r] = (uint32_t)(am[r] ? p : start);
+      }
+      float d[kRefRows];
+      dist_rows<NIT>(a.X, a.n_pad, pm, am, qr, li, Umin * a.abandon_f, d);
+#pragma unroll
+      for (int r = 0; r < kRefRows; r++)
+#pragma unroll
+        for (int gi = 0; gi < 4; gi++) {
+          const int64_t p = p0 + 4 * r + gi;
+          const float dd = __shfl(d[r], 16 * gi);
+          if (p < end && dd <= Umin * a.band_f) wl.insert(((uint64_t)__float_as_uint(dd) << 32) | (uint64_t)p, lane);
+        }
+      const uint64_t kth = wl.at(a.k - 1);
+      if (kth != kEmpty) {
+        const float uw = key_d(kth) * a.upd_f;
+        Umin = uw < Umin ? uw : Umin;
+      }
+    }
+  }
+  if (lane == 0 && Umin < U_in) atomicMin(a.U + q, __float_as_uint(Umin));
+  flush_wave_list<R>(a, q, wl, Umin, lane);
+  if (lane == 0 && scanned && a.stats) atomicAdd(a.stats + 2, scanned);
+}
+
+template <int NIT, int R>
+static void launch_approx_t(const SearchArgs& a, int M, int32_t* leaves, hipStream_t st) {
+  k_approx_leaves<<<(unsigned)a.B, 256, 0, st>>>(a, M, leaves);
+  k_approx_scan<NIT, R><<<(unsigned)a.B, 256, 0, st>>>(a, M, leaves);
+}
+
+sofa_status launch_approx(const SearchArgs& a, int M, int32_t* leaves, hipStream_t st, hipEvent_t* ev) {
+  if (M < 1 || M > kApproxMax) return set_error(SOFA_EINVAL, "approx_leaves=%d outside [1,%d]", M, kApproxMax);
+  SOFA_TRY(launch_front(a, st, ev));
+  const int R = (a.k + 16 <= 64) ? 1 : 2;
+  switch (a.n_pad / 64) {
+#define SOFA_CASE(NI)                                              \
+  case NI:                                                         \
+    if (R == 1) launch_approx_t<NI, 1>(a, M, leaves, st);          \
+    else launch_approx_t<NI, 2>(a, M, leaves, st);                 \
+    break;
+    SOFA_CASE(1)
+    SOFA_CASE(2)
+    SOFA_CASE(4)
+    SOFA_CASE(8)
+    SOFA_CASE(16)
+#undef SOFA_CASE
+    default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
+  }
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
 sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                           hipStream_t st, hipEvent_t* ev) {
   SOFA_TRY(launch_front(a, st, ev));

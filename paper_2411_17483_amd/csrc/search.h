@@ -49,6 +49,11 @@ sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, i
 sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev);
 // survivor masks from the stored envelope bounds and the current U
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st);
+// approximate search: the front, then the M (<= kApproxMax) leaves of
+// smallest envelope bound per query (B x kApproxMax leaf ids in `leaves`)
+// scanned exactly; launch_finalize ranks what they hold
+constexpr int kApproxMax = 64;
+sofa_status launch_approx(const SearchArgs& a, int M, int32_t* leaves, hipStream_t st, hipEvent_t* ev);
 sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                             hipStream_t st, hipEvent_t* ev);
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -55,7 +55,8 @@ class IndexInfo(ctypes.Structure):
 
 class KnnParams(ctypes.Structure):
     _fields_ = [("prune", _i32), ("d_radius", _vp), ("radius_model", _vp), ("no_seed_leaf", _i32),
-                ("ws", _vp), ("candidate_capacity", _i32), ("sampling", _i32)]
+                ("ws", _vp), ("candidate_capacity", _i32), ("sampling", _i32),
+                ("approx_leaves", _i32)]
 
 
 class RadiusParams(ctypes.Structure):
@@ -289,15 +290,17 @@ class Index:
         return W, ids, env, keys
 
     def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0,
-            model=None, sampling=0):
-        """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors."""
+            model=None, sampling=0, approx_leaves=0):
+        """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors.
+        approx_leaves > 0: approximate search over that many leaves per query."""
         import torch
         B = Q.shape[0]
         ids = torch.empty((B, k), dtype=torch.int64, device=Q.device)
         d = torch.empty((B, k), dtype=torch.float32, device=Q.device)
         p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
                       None if model is None else model._h, 1 if no_seed_leaf else 0,
-                      None if ws is None else ws._h, int(candidate_capacity), int(sampling))
+                      None if ws is None else ws._h, int(candidate_capacity), int(sampling),
+                      int(approx_leaves))
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
         return ids, d

@@ -793,3 +793,37 @@ def test_prune_large_leaves(gpu_lib, L):
     for prune in (0, 1, 2):
         ids, d = ix.knn(_t(Q), 10, prune=prune)
         _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
+def test_approximate_search(gpu_lib):
+    """approx_leaves = M scans the M leaves of smallest envelope bound per
+    query (no exactness guarantee).  With M at least the number of leaves it
+    is the exact search; for any M every returned distance is the true
+    distance of its id, ranked by (distance, id); recall does not fall as M
+    grows; out-of-range M is an error."""
+    N, n, B, k, L = 3000 + 7, 128, 50, 10, 64
+    X = synth.collection(N, n, "mix", seed=371)
+    bins = _bins(gpu_lib, X, N)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=L)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=372)
+    ref_ids, ref_d2 = oracle.knn(X, Q, k)
+    n_leaves = ix.info()["n_leaves"]
+    assert n_leaves <= 64
+    ids, d = ix.knn(_t(Q), k, approx_leaves=64)
+    _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    recalls = []
+    for M in (1, 2, 4, 8, 16):
+        ids, d = ix.knn(_t(Q), k, approx_leaves=M)
+        ids, d = ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)
+        for b in range(B):
+            got = ids[b][ids[b] >= 0]
+            assert got.size == min(k, M * L)
+            d2 = oracle.dist2_rows(X, Q[b], got)
+            assert np.all(np.abs(d[b][:got.size] - np.sqrt(d2)) <= 1e-6 * np.maximum(np.sqrt(d2), 1e-30))
+            key = list(zip(d2.tolist(), got.tolist()))
+            assert key == sorted(key)
+        recalls.append(np.mean([len(set(ids[b]) & set(ref_ids[b])) / k for b in range(B)]))
+    assert all(r1 <= r2 + 1e-12 for r1, r2 in zip(recalls, recalls[1:])), recalls
+    assert recalls[-1] > recalls[0], recalls
+    with pytest.raises(gpu_lib.SofaError):
+        ix.knn(_t(Q), k, approx_leaves=65)
