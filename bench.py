@@ -306,6 +306,26 @@ def main():
         del iix, ibins
         torch.cuda.empty_cache()
 
+    # approximate search (opt-in, no exactness guarantee): the M leaves of
+    # smallest envelope bound per query; recall@k against the exact answer
+    approx = None
+    if not args.headline_only:
+        approx = []
+        exact = ids_by_path[headline]
+        for M in (1, 4, 16, 64):
+            ix.knn(Qd, k, approx_leaves=M)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ids_a, _ = ix.knn(Qd, k, approx_leaves=M)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            ids_a = ids_a.cpu().numpy()
+            rec = float(np.mean([len(set(ids_a[b].tolist()) & set(exact[b].tolist())) / k for b in range(B)]))
+            approx.append({"approx_leaves": M, "recall_at_k": rec, "queries_per_s": B / sec,
+                           "ms_per_step": sec * 1e3})
+            log(f"approximate, {M} leaves: recall@{k} {rec:.3f}, {B / sec:.0f} q/s")
+
     h = results[headline][f"k{k}"]
     cnt, stg = h["counters"], h["stages_ms"]
     if headline == "plain":
@@ -369,6 +389,7 @@ def main():
         "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "k": k, "queries": int(len(lat)), "path": headline},
         "paths": results, "paths_ids_identical": agree, "word_scan": word_scan, "isax_summary": isax,
+        "approximate": approx,
         "parity_sample": parity,
         "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
         "radius_models": model_info,
