@@ -736,20 +736,91 @@ __device__ __forceinline__ void col_epilogue(const SearchArgs& a, const Bf16Args
   }
 }
 
+// chunk of work item it; skip > 0 enumerates the chunks that are not
+// multiples of skip
+__device__ __forceinline__ int64_t item_chunk(const Bf16Args& b, uint32_t it) {
+  return b.chunk_mult * (b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
+                                    : (int64_t)it * b.chunk_stride + b.chunk_first);
+}
+
+// A operand of one wave: row blocks rb and rb + 1 (32 rows each), all K steps
+template <int PREC, int KS>
+__device__ __forceinline__ void load_a(const u4v* xv, int64_t rb, int lane,
+                                       typename TileTraits<PREC>::frag (&av)[2][KS]) {
+  constexpr int H = TileTraits<PREC>::kHalves;
+#pragma unroll
+  for (int r = 0; r < 2; r++)
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) av[r][ks] = load_frag<PREC>(xv + ((rb + r) * KS + ks) * 64 * H + lane);
+}
+
+// raw buffer descriptor (fourth word for gfx9 raw, untyped access) over
+// bytes [base, base + bytes); reads past the end return zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+
+// fragment at byte offset voff + soff of a buffer (the halves of an FP8
+// fragment 1 KB apart, as in load_frag)
+template <int PREC>
+__device__ __forceinline__ typename TileTraits<PREC>::frag load_frag_buf(__amdgpu_buffer_rsrc_t r, int voff,
+                                                                         int soff) {
+  if constexpr (PREC == 1) {
+    return __builtin_bit_cast(bf8v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  } else {
+    const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 1024, 0);
+    return __builtin_bit_cast(v8i, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+  }
+}
+
+// the MFMAs of one 32-query column block over the wave's two row blocks.  B
+// fragments are read from LDS two K steps ahead of their MFMAs (one for the
+// widest FP8 rows, which leave too few registers); the scheduling barriers
+// keep the compiler from sinking the reads back to their use.  RELOAD: each
+// A fragment is replaced from buffer ra (the next chunk's two row blocks) as
+// soon as its two MFMAs have issued, so the next chunk's HBM reads overlap
+// this block's matrix work in the registers they will occupy.
+template <int PREC, int KS, bool RELOAD>
+__device__ __forceinline__ void col_mfma(typename TileTraits<PREC>::frag (&av)[2][KS], const u4v* bcol,
+                                         __amdgpu_buffer_rsrc_t ra, int lane, f16v& acc0, f16v& acc1) {
+  constexpr int H = TileTraits<PREC>::kHalves;
+  constexpr int kAhead = (PREC == 2 && KS >= 8) ? 1 : 2;
+  constexpr int kBlockBytes = KS * 64 * H * 16;
+#pragma unroll
+  for (int e = 0; e < 16; e++) acc0[e] = acc1[e] = 0.0f;
+  typename TileTraits<PREC>::frag bq[KS];
+#pragma unroll
+  for (int ks = 0; ks < kAhead && ks < KS; ks++) bq[ks] = load_frag<PREC>(bcol + ks * 64 * H + lane);
+#pragma unroll
+  for (int ks = 0; ks < KS; ks++) {
+    if (ks + kAhead < KS) bq[ks + kAhead] = load_frag<PREC>(bcol + (ks + kAhead) * 64 * H + lane);
+    __builtin_amdgcn_sched_barrier(0);
+    acc0 = mma<PREC>(av[0][ks], bq[ks], acc0);
+    acc1 = mma<PREC>(av[1][ks], bq[ks], acc1);
+    if (RELOAD) {
+      av[0][ks] = load_frag_buf<PREC>(ra, lane * 16, ks * 64 * H * 16);
+      av[1][ks] = load_frag_buf<PREC>(ra, lane * 16, kBlockBytes + ks * 64 * H * 16);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // one group: thresholds from the terms loaded one group ahead, the DMA and
 // terms of the next group (when there is one), the slots of the group after
-// it, the column blocks, and the barrier that publishes the next buffer.
-// JOINT: both column blocks' MFMAs interleaved (4 per pair of fragment
-// reads, 64 accumulators), for one wave per SIMD; otherwise one block after
-// the other.
-template <int PREC, int KS, bool DUMP, bool JOINT>
+// it, the two column blocks one after the other, and the barrier that
+// publishes the next buffer.  LAST (the chunk's last group): column block 1
+// runs first, then block 0, which always runs (its lane 0 is a listed entry)
+// and reloads the A registers from ra, the next chunk's rows (an empty
+// buffer when there is none: the loads return zero).
+template <int PREC, int KS, bool DUMP, bool LAST>
 __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& b,
                                            const ChunkState& cs,
-                                           const typename TileTraits<PREC>::frag (&av)[2][KS],
-                                           const float* xn2s, const GroupSlots& gcur, bool has_next,
-                                           const GroupSlots& gnext, bool has_next2, GroupSlots& gnext2,
-                                           int64_t off, uint32_t cnt, int g2, ColTerms& cols,
-                                           const u4v* cur, u4v* nxt, unsigned long long& st_pairs) {
+                                           typename TileTraits<PREC>::frag (&av)[2][KS],
+                                           const float* xn2s, const GroupSlots& gcur, const GroupSlots& gnext,
+                                           bool has_next2, GroupSlots& gnext2, int64_t off, uint32_t cnt,
+                                           int g2, ColTerms& cols, const u4v* cur, u4v* nxt,
+                                           __amdgpu_buffer_rsrc_t ra, unsigned long long& st_pairs) {
   constexpr int H = TileTraits<PREC>::kHalves;
   const int wave = cs.wave, lane = cs.lane;
   const int q0 = cols.v0 ? __float_as_int(cols.c0.w) : -1;
@@ -760,63 +831,29 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
   const bool mb0 = q0 >= 0, mb1 = q1 >= 0;
   const float f0 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s0;
   const float f1 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s1;
-  if (has_next) {
+  if (!LAST) {
     stage_group<PREC, KS>(b, gnext, wave, lane, nxt);
     load_cols<PREC>(b, gnext, cols);
+    if (has_next2) gnext2 = group_slots(b, off, cnt, g2, lane);
   }
-  if (has_next2) gnext2 = group_slots(b, off, cnt, g2, lane);
-  const bool act0 = DUMP || __ballot(mb0), act1 = DUMP || __ballot(mb1);
-  if (JOINT && act0 && act1) {
-    f16v acc[2][2];
+  const bool act0 = LAST || DUMP || __ballot(mb0), act1 = DUMP || __ballot(mb1);
 #pragma unroll
-    for (int r = 0; r < 2; r++)
-#pragma unroll
-      for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int e = 0; e < 16; e++) acc[r][c][e] = 0.0f;
-#pragma unroll
-    for (int ks = 0; ks < KS; ks++) {
-      const auto b0 = load_frag<PREC>(cur + (0 * KS + ks) * 64 * H + lane);
-      const auto b1 = load_frag<PREC>(cur + (1 * KS + ks) * 64 * H + lane);
-      acc[0][0] = mma<PREC>(av[0][ks], b0, acc[0][0]);
-      acc[1][0] = mma<PREC>(av[1][ks], b0, acc[1][0]);
-      acc[0][1] = mma<PREC>(av[0][ks], b1, acc[0][1]);
-      acc[1][1] = mma<PREC>(av[1][ks], b1, acc[1][1]);
-    }
-    st_pairs += 64 * 64;
-    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, gcur.s0, q0, cq0, mb0, f0, acc[0][0], acc[1][0]);
-    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, gcur.s1, q1, cq1, mb1, f1, acc[0][1], acc[1][1]);
-  } else {
-#pragma unroll
-    for (int cb = 0; cb < 2; cb++) {
-      if (!(cb ? act1 : act0)) continue;
-      st_pairs += 64 * 32;
-      f16v acc[2];
-#pragma unroll
-      for (int r = 0; r < 2; r++)
-#pragma unroll
-        for (int e = 0; e < 16; e++) acc[r][e] = 0.0f;
-      // B fragments read from LDS two K steps ahead of their MFMAs (one for
-      // the widest FP8 rows, which leave too few registers); the scheduling
-      // barriers keep the compiler from sinking the reads back to their use
-      constexpr int kAhead = (PREC == 2 && KS >= 8) ? 1 : 2;
-      typename TileTraits<PREC>::frag bq[KS];
-#pragma unroll
-      for (int ks = 0; ks < kAhead && ks < KS; ks++) bq[ks] = load_frag<PREC>(cur + (cb * KS + ks) * 64 * H + lane);
-#pragma unroll
-      for (int ks = 0; ks < KS; ks++) {
-        if (ks + kAhead < KS) bq[ks + kAhead] = load_frag<PREC>(cur + (cb * KS + ks + kAhead) * 64 * H + lane);
-        __builtin_amdgcn_sched_barrier(0);
-        acc[0] = mma<PREC>(av[0][ks], bq[ks], acc[0]);
-        acc[1] = mma<PREC>(av[1][ks], bq[ks], acc[1]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      col_epilogue<PREC, DUMP>(a, b, cs, xn2s, cb ? gcur.s1 : gcur.s0, cb ? q1 : q0, cb ? cq1 : cq0,
-                               cb ? mb1 : mb0, cb ? f1 : f0, acc[0], acc[1]);
-    }
+  for (int i = 0; i < 2; i++) {
+    const int cb = LAST ? 1 - i : i;
+    if (!(cb ? act1 : act0)) continue;
+    st_pairs += 64 * 32;
+    f16v acc[2];
+    const u4v* bcol = cur + cb * KS * 64 * H;
+    if (LAST && cb == 0)
+      col_mfma<PREC, KS, true>(av, bcol, ra, lane, acc[0], acc[1]);
+    else
+      col_mfma<PREC, KS, false>(av, bcol, ra, lane, acc[0], acc[1]);
+    col_epilogue<PREC, DUMP>(a, b, cs, xn2s, cb ? gcur.s1 : gcur.s0, cb ? q1 : q0, cb ? cq1 : cq0,
+                             cb ? mb1 : mb0, cb ? f1 : f0, acc[0], acc[1]);
   }
-  // the next group's fragments and terms have landed; every wave is done with cur
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  // the next group's fragments and terms have landed (LAST: the reload of A
+  // may still be in flight); every wave is done with cur
+  if (!LAST) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
 }
 
@@ -824,28 +861,35 @@ template <int PREC, int KS, bool DUMP, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES)))
 void k_bf16_tiles(SearchArgs a, Bf16Args b) {
   typedef typename TileTraits<PREC>::frag frag;
-  constexpr int H = TileTraits<PREC>::kHalves;
   __shared__ __attribute__((aligned(16))) u4v Bs0[group_units<PREC, KS>()];
   __shared__ __attribute__((aligned(16))) u4v Bs1[group_units<PREC, KS>()];
   __shared__ float xn2s[256];
   __shared__ uint32_t item_sh;
   ChunkState cs;
-  cs.wave = threadIdx.x >> 6;
+  // uniform within the wave: the branches on the reload row block stay scalar
+  cs.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   cs.lane = threadIdx.x & 63;
   cs.gam = (float)(KS * TileTraits<PREC>::kStep + TileTraits<PREC>::kStep) * 0x1p-23f;
   const int wave = cs.wave, lane = cs.lane;
   const u4v* xv = reinterpret_cast<const u4v*>(b.xb);
   unsigned long long st_pairs = 0, st_needed = 0;
+  // work items are fetched one ahead, so that a chunk's last group can load
+  // the next chunk's A operand; thread 0 writes item_sh between the barriers
+  // that separate it from every thread's reads
+  uint32_t it_next = 0;
+  if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
+  __syncthreads();
+  it_next = __builtin_amdgcn_readfirstlane(item_sh);
+  int64_t a_chunk = -1;  // the chunk whose A operand av holds (or is loading)
+  frag av[2][KS];
   for (;;) {
+    const uint32_t it = it_next;
+    if ((int64_t)it >= b.n_items) break;
+    __syncthreads();
     if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1u);
     __syncthreads();
-    const uint32_t it = item_sh;
-    __syncthreads();
-    if ((int64_t)it >= b.n_items) break;
-    // skip > 0: enumerate the chunks that are not multiples of skip
-    const int64_t chunk =
-        b.chunk_mult * (b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
-                                   : (int64_t)it * b.chunk_stride + b.chunk_first);
+    it_next = __builtin_amdgcn_readfirstlane(item_sh);
+    const int64_t chunk = item_chunk(b, it);
     cs.c0 = chunk * 256;
     const int64_t leaf = cs.c0 / a.L;
     cs.blk = leaf / kLeavesPerItem;
@@ -862,13 +906,9 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     load_cols<PREC>(b, gcur, cols);
     GroupSlots gnext = gcur;
     if (ng > 1) gnext = group_slots(b, off, cnt, 1, lane);
-    // A operand: this wave's 64 rows, all K steps, in registers
-    const int64_t rb0 = (cs.c0 + 64 * wave) / 32;
-    frag av[2][KS];
-#pragma unroll
-    for (int r = 0; r < 2; r++)
-#pragma unroll
-      for (int ks = 0; ks < KS; ks++) av[r][ks] = load_frag<PREC>(xv + ((rb0 + r) * KS + ks) * 64 * H + lane);
+    // A operand: this wave's 64 rows, all K steps, in registers (already
+    // loading when the previous chunk's last group reloaded them)
+    if (a_chunk != chunk) load_a<PREC, KS>(xv, (cs.c0 + 64 * wave) / 32, lane, av);
     {
       // rows past N (zero in the copy) get a NaN |x|^2: no compare passes
       const int64_t row = cs.c0 + threadIdx.x;
@@ -879,6 +919,12 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     cs.sc = PREC == 2 ? b.cscale[chunk] : 1.0f;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first group's fragments
     __syncthreads();
+    // the next chunk's rows for the last group's reload of A
+    const bool has_following = (int64_t)it_next < b.n_items;
+    const int64_t next_chunk = has_following ? item_chunk(b, it_next) : (int64_t)0;
+    constexpr int kABytes = 2 * KS * 64 * TileTraits<PREC>::kHalves * 16;
+    const __amdgpu_buffer_rsrc_t ra =
+        raw_rsrc(xv + (next_chunk * 256 + 64 * wave) / 32 * (kABytes / 32), has_following ? kABytes : 0);
     // smallest |x|^2 over the 16 rows of this lane's fragment, per row block
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -891,28 +937,28 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
       cs.xmin[r] = m;
     }
     // groups alternate between the two buffers
-    for (int g = 0; g < ng; g += 2) {
+    for (int g = 0; g + 1 < ng; g++) {
       GroupSlots gnext2 = gnext;
-      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, gcur, g + 1 < ng, gnext, g + 2 < ng,
-                                             gnext2, off, cnt, g + 2, cols, Bs0, Bs1, st_pairs);
-      if (g + 1 >= ng) break;
+      group_step<PREC, KS, DUMP, false>(a, b, cs, av, xn2s, gcur, gnext, g + 2 < ng, gnext2, off, cnt, g + 2,
+                                        cols, (g & 1) ? Bs1 : Bs0, (g & 1) ? Bs0 : Bs1, ra, st_pairs);
       gcur = gnext;
       gnext = gnext2;
-      GroupSlots gnext3 = gnext;
-      group_step<PREC, KS, DUMP, WAVES == 1>(a, b, cs, av, xn2s, gcur, g + 2 < ng, gnext, g + 3 < ng,
-                                             gnext3, off, cnt, g + 3, cols, Bs1, Bs0, st_pairs);
-      gcur = gnext;
-      gnext = gnext3;
     }
+    {
+      const int g = ng - 1;
+      GroupSlots unused = gnext;
+      group_step<PREC, KS, DUMP, true>(a, b, cs, av, xn2s, gcur, gnext, false, unused, off, cnt, 0, cols,
+                                       (g & 1) ? Bs1 : Bs0, (g & 1) ? Bs0 : Bs1, ra, st_pairs);
+    }
+    a_chunk = has_following ? next_chunk : (int64_t)-1;
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
   if (threadIdx.x == 0 && st_needed && a.stats) atomicAdd(a.stats + 5, st_needed);
 }
 
-// waves per SIMD of the tile kernel: 2 (one column block after the other;
-// the two waves of a SIMD hide each other's epilogues and LDS waits).  1
-// runs both column blocks of a group together with 512 registers per wave;
-// measured slower on 10M x 256 (the lone wave cannot hide its own stalls).
+// waves per SIMD of the tile kernel: the two waves of a SIMD hide each
+// other's epilogues and LDS waits (one wave running both column blocks of a
+// group together, with 512 registers, measured slower on 10M x 256)
 constexpr int kTileWaves = 2;
 
 // launch over the supported (precision, K steps) pairs
