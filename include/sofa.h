@@ -83,8 +83,9 @@ typedef struct {
 /* Learns bins from the stride sample of m rows of d_series (rows
  * floor(i*N/m), i < m), all arithmetic in FP64 on the device: DFT of the
  * sample, variance per pool value, top-l selection, sort and breakpoints.
- * d_series: N x n FP32 device array.  Requires 1 <= m <= N, n >= 2*pool+2,
- * n % 4 == 0, n <= 4096.  Synchronous (returns when *out is complete). */
+ * d_series: N x n FP32 device array.  Requires 1 <= m <= N, m <= 2^25,
+ * n >= 2*pool+2, n % 4 == 0, n <= 4096.  Synchronous (returns when *out is
+ * complete). */
 sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t n, int64_t m,
                             const sofa_bin_params* params, void* stream, sofa_bins** out);
 

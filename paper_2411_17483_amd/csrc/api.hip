@@ -106,6 +106,7 @@ extern "C" sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t
   *out = nullptr;
   SOFA_TRY(check_bin_params(n, params));
   if (!d_series || N < 1 || m < 1 || m > N) return set_error(SOFA_EINVAL, "need 1 <= m <= N and a series array");
+  if (m > (1ll << 25)) return set_error(SOFA_EINVAL, "the sample holds at most 2^25 rows (asked for %lld)", (long long)m);
   if (N >= (1ll << 31)) return set_error(SOFA_EINVAL, "N must be < 2^31");
   sofa_bins* b = new sofa_bins();
   b->n = n;

@@ -92,8 +92,9 @@ __device__ __forceinline__ uint4 fp8_pack16(const float* __restrict__ p, float i
 __global__ void k_bf16_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
                             uint4* __restrict__ xb) {
   const int KS = n_pad / 16;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrb * KS * 64) return;
+  const int64_t total = nrb * KS * 64;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
   const int lane = (int)(i % 64);
   const int64_t t = i / 64;
   const int ks = (int)(t % KS);
@@ -110,6 +111,7 @@ __global__ void k_bf16_copy(const float* __restrict__ X, int64_t N, int n_pad, i
     w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
   }
   xb[i] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 }
 
 // per row: |x|^2 rounded down, r_x = |x - xh| up, |xh| up (one wave per row)
@@ -166,11 +168,11 @@ __device__ __forceinline__ void norms_of_fp8(const float* __restrict__ row, int 
 __global__ __launch_bounds__(256) void k_bf16_meta(const float* __restrict__ X, int64_t N, int n_pad,
                                                    float4* __restrict__ meta) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= N) return;
-  float4 m;
-  norms_of(X + row * n_pad, n_pad, lane, m);
-  if (lane == 0) meta[row] = m;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < N; row += (int64_t)gridDim.x * 4) {
+    float4 m;
+    norms_of(X + row * n_pad, n_pad, lane, m);
+    if (lane == 0) meta[row] = m;
+  }
 }
 
 // per leaf: (max |xh|, max r_x, max |x|^2)
@@ -223,8 +225,9 @@ __global__ __launch_bounds__(256) void k_fp8_chunk_scale(const float* __restrict
 __global__ void k_fp8_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
                            const float* __restrict__ cscale, uint4* __restrict__ xf) {
   const int KS = n_pad / 64;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrb * KS * 128) return;
+  const int64_t total = nrb * KS * 128;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
   const int lane = (int)(i % 64);
   const int h = (int)((i / 64) % 2);
   const int64_t t = i / 128;
@@ -235,17 +238,18 @@ __global__ void k_fp8_copy(const float* __restrict__ X, int64_t N, int n_pad, in
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
   if (row < N) w = fp8_pack16(X + row * n_pad + k0, 1.0f / cscale[row / 256]);
   xf[i] = w;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fp8_meta(const float* __restrict__ X, int64_t N, int n_pad,
                                                   const float* __restrict__ cscale,
                                                   float4* __restrict__ meta) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= N) return;
-  float4 m;
-  norms_of_fp8(X + row * n_pad, n_pad, lane, cscale[row / 256], m);
-  if (lane == 0) meta[row] = m;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < N; row += (int64_t)gridDim.x * 4) {
+    float4 m;
+    norms_of_fp8(X + row * n_pad, n_pad, lane, cscale[row / 256], m);
+    if (lane == 0) meta[row] = m;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -296,11 +300,12 @@ __global__ __launch_bounds__(256) void k_qsort(const uint32_t* __restrict__ cnt,
 // smask[blk][s]: the survivor mask of the query in sorted slot s (0 past B)
 __global__ void k_smask(const uint64_t* __restrict__ masks, int64_t n_blocks, int B, int Spad,
                         const int32_t* __restrict__ perm, uint64_t* __restrict__ smask) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_blocks * Spad) return;
-  int64_t b = i / Spad;
-  int s = (int)(i % Spad);
-  smask[i] = s < B ? masks[b * B + perm[s]] : 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_blocks * Spad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / Spad;
+    const int s = (int)(i % Spad);
+    smask[i] = s < B ? masks[b * B + perm[s]] : 0ull;
+  }
 }
 
 // per leaf, the sorted slots of the queries whose (query, leaf) pair
@@ -1077,8 +1082,8 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
                               uint4* xb, float4* meta, float4* leafmeta, hipStream_t st) {
   const int64_t nrb = ((N + 255) / 256) * 8;  // 32-row blocks, padded to whole 256-row chunks
   const int KS = n_pad / 16;
-  k_bf16_copy<<<nblk(nrb * KS * 64, 256), 256, 0, st>>>(X, N, n_pad, nrb, xb);
-  k_bf16_meta<<<nblk(N, 4), 256, 0, st>>>(X, N, n_pad, meta);
+  k_bf16_copy<<<grid_blocks(nrb * KS * 64, 256), 256, 0, st>>>(X, N, n_pad, nrb, xb);
+  k_bf16_meta<<<grid_blocks(N, 4), 256, 0, st>>>(X, N, n_pad, meta);
   k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
@@ -1090,8 +1095,8 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
   const int64_t nrb = n_chunks * 8;  // 32-row blocks, padded to whole 256-row chunks
   const int KS = n_pad / 64;
   k_fp8_chunk_scale<<<(unsigned)n_chunks, 256, 0, st>>>(X, N, n_pad, cscale);
-  k_fp8_copy<<<nblk(nrb * KS * 128, 256), 256, 0, st>>>(X, N, n_pad, nrb, cscale, xf);
-  k_fp8_meta<<<nblk(N, 4), 256, 0, st>>>(X, N, n_pad, cscale, meta);
+  k_fp8_copy<<<grid_blocks(nrb * KS * 128, 256), 256, 0, st>>>(X, N, n_pad, nrb, cscale, xf);
+  k_fp8_meta<<<grid_blocks(N, 4), 256, 0, st>>>(X, N, n_pad, cscale, meta);
   k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
@@ -1102,7 +1107,7 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
 static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
   const int Spad = b.G * kGroup;
   const int64_t n_sub = a.n_blocks * kSubPerBlock;
-  k_smask<<<nblk(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
+  k_smask<<<grid_blocks(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
   k_leaf_lists<0><<<(unsigned)n_sub, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, b.bsum, nullptr, nullptr,
                                                    nullptr);
   k_scan_counts<<<1, 1024, 0, st>>>(b.bsum, n_sub, b.boff);

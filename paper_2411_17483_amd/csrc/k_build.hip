@@ -276,19 +276,19 @@ __global__ __launch_bounds__(256) void k_permute(const float* __restrict__ X, in
                                                  double* __restrict__ nout,
                                                  int32_t* __restrict__ ids) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int64_t p = (int64_t)blockIdx.x * 4 + wave;
-  if (p >= N) return;
-  int64_t src = perm[p];
-  for (int c = lane * 4; c < n_pad; c += 256) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c < n) v = *reinterpret_cast<const float4*>(X + src * n + c);
-    *reinterpret_cast<float4*>(Xo + p * n_pad + c) = v;
-  }
-  if (lane == 0) {
-    *reinterpret_cast<uint4*>(wout + p * kWordBytes) =
-        *reinterpret_cast<const uint4*>(win + src * kWordBytes);
-    nout[p] = nin[src];
-    ids[p] = (int32_t)src;
+  for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < N; p += (int64_t)gridDim.x * 4) {
+    const int64_t src = perm[p];
+    for (int c = lane * 4; c < n_pad; c += 256) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c < n) v = *reinterpret_cast<const float4*>(X + src * n + c);
+      *reinterpret_cast<float4*>(Xo + p * n_pad + c) = v;
+    }
+    if (lane == 0) {
+      *reinterpret_cast<uint4*>(wout + p * kWordBytes) =
+          *reinterpret_cast<const uint4*>(win + src * kWordBytes);
+      nout[p] = nin[src];
+      ids[p] = (int32_t)src;
+    }
   }
 }
 
@@ -375,7 +375,7 @@ sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_i
   SOFA_TRY(ix->ids.alloc(4 * N));
   SOFA_TRY(ix->norm2.alloc(8 * N));
   SOFA_TRY(ix->env.alloc(32 * ix->n_leaves));
-  k_permute<<<nblk(N, 4), 256, 0, st>>>(X, n, va, N, n_pad, ix->X.as<float>(), words_in,
+  k_permute<<<grid_blocks(N, 4), 256, 0, st>>>(X, n, va, N, n_pad, ix->X.as<float>(), words_in,
                                         ix->words.as<uint8_t>(), norm2_in, ix->norm2.as<double>(),
                                         ix->ids.as<int32_t>());
   k_envelope<<<nblk(ix->n_leaves, 4), 256, 0, st>>>(ix->words.as<uint8_t>(), N, ix->L, ix->n_leaves,

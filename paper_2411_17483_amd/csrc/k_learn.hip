@@ -60,16 +60,21 @@ __global__ __launch_bounds__(256) void k_sample_dft(const float* __restrict__ X,
 #pragma clang fp contract(off)
   __shared__ float xs[4][kMaxN];
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int64_t i = (int64_t)blockIdx.x * 4 + wave;
-  bool ok = i < m;
-  int64_t row = ok ? (int64_t)((i * N) / m) : 0;
-  for (int t = lane; t < n; t += 64) xs[wave][t] = ok ? X[row * n + t] : 0.0f;
-  __syncthreads();
-  if (!ok || lane >= np) return;
-  const double* b = b64 + (int64_t)lane * n;
-  double s = 0.0;
-  for (int t = 0; t < n; t++) s = s + (double)xs[wave][t] * b[t];
-  F[i * np + lane] = s;
+  // the loop bound is uniform across the workgroup (the barriers inside)
+  for (int64_t i0 = (int64_t)blockIdx.x * 4; i0 < m; i0 += (int64_t)gridDim.x * 4) {
+    const int64_t i = i0 + wave;
+    const bool ok = i < m;
+    const int64_t row = ok ? (int64_t)((i * N) / m) : 0;
+    for (int t = lane; t < n; t += 64) xs[wave][t] = ok ? X[row * n + t] : 0.0f;
+    __syncthreads();
+    if (ok && lane < np) {
+      const double* b = b64 + (int64_t)lane * n;
+      double s = 0.0;
+      for (int t = 0; t < n; t++) s = s + (double)xs[wave][t] * b[t];
+      F[i * np + lane] = s;
+    }
+    __syncthreads();
+  }
 }
 
 // Mean and population variance of column p of F (m x np), one block per column.
@@ -216,7 +221,7 @@ sofa_status launch_learn(const float* X, int64_t N, int n, int64_t m, int pool, 
   SOFA_TRY(cols.alloc(sizeof(double) * l * mpad));
   SOFA_TRY(beta.alloc(sizeof(double) * l * (alpha > 1 ? alpha - 1 : 1)));
   k_basis64<<<nblk((int64_t)np * n, 256), 256, 0, st>>>(b64.as<double>(), n, np, summary, l);
-  k_sample_dft<<<nblk(m, 4), 256, 0, st>>>(X, N, n, m, b64.as<double>(), np, F.as<double>());
+  k_sample_dft<<<grid_blocks(m, 4), 256, 0, st>>>(X, N, n, m, b64.as<double>(), np, F.as<double>());
   k_col_stats<<<np, 256, 0, st>>>(F.as<double>(), m, np, var.as<double>());
   if (summary == 1) {
     // iSAX keeps the l segments in time order and fixed breakpoints; the

@@ -38,6 +38,16 @@ constexpr int kLeavesPerItem = 64;         // leaves per refinement work item (o
 constexpr int kMaxK = 100;
 constexpr int kMaxN = 1024;
 
+// A dispatch counts the work-items of each grid dimension in 32 bits, so a
+// grid of 2^32 threads or more wraps and silently skips its tail.  Kernels
+// whose size grows with the collection take at most kMaxGridBlocks
+// workgroups and stride over the rest.
+constexpr int64_t kMaxGridBlocks = 1 << 16;
+static inline unsigned grid_blocks(int64_t items, int64_t per_block) {
+  const int64_t b = (items + per_block - 1) / per_block;
+  return (unsigned)(b < 1 ? 1 : (b > kMaxGridBlocks ? kMaxGridBlocks : b));
+}
+
 // n_pad: row length of the permuted copy, a power-of-two multiple of 64 so that
 // 16 lanes x float4 cover a row in n_pad/64 steps
 int pad_len(int n);
