@@ -3,10 +3,9 @@
 
 Collections (z-normalised FP32, even rows random walk, odd rows 8-sinusoid
 high-frequency, generated on the host in chunks and streamed to the GPU):
-100M x 128 (BF16 prune), 20M x 512 (FP8 prune), 5M x 1024 (plain SFA
-search; the batched-distance tiers stop at n = 512).  Requests carry one
-noisy-copy query (sigma 0.1) of a uniformly chosen collection with k
-uniform in {1, 10, 100}; arrivals are Poisson at a fixed offered rate.  For
+100M x 128 (BF16 prune), 20M x 512 and 5M x 1024 (FP8 prune).  Requests
+carry one noisy-copy query (sigma 0.1) of a uniformly chosen collection with
+k uniform in {1, 10, 100}; arrivals are Poisson at a fixed offered rate.  For
 each rate the run reports the achieved queries/s and the p50/p99 latency
 from submission to result (measured by the server's own clock), plus the
 batch sizes the loop formed.  A subset of requests is also answered one at
@@ -120,7 +119,7 @@ def main():
     import torch
     from paper_2411_17483_amd import sofa
     sofa.load()
-    specs = [(100_000_000, 128, 6, 1, 1), (20_000_000, 512, 7, 2, 2), (5_000_000, 1024, 8, 0, 0)]
+    specs = [(100_000_000, 128, 6, 1, 1), (20_000_000, 512, 7, 2, 2), (5_000_000, 1024, 8, 2, 2)]
     colls, build = [], []
     for N, n, seed, prec, prune in specs:
         N = max(4096, int(N * args.scale))

@@ -84,7 +84,7 @@ typedef struct {
  * floor(i*N/m), i < m), all arithmetic in FP64 on the device: DFT of the
  * sample, variance per pool value, top-l selection, sort and breakpoints.
  * d_series: N x n FP32 device array.  Requires 1 <= m <= N, m <= 2^25,
- * n >= 2*pool+2, n % 4 == 0, n <= 4096.  Synchronous (returns when *out is
+ * n >= 2*pool+2, n % 4 == 0, n <= 1024.  Synchronous (returns when *out is
  * complete). */
 sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t n, int64_t m,
                             const sofa_bin_params* params, void* stream, sofa_bins** out);
@@ -132,7 +132,7 @@ double sofa_bins_eta_per_norm(const sofa_bins* bins);
 typedef struct {
   int32_t leaf_size; /* rows per leaf, a multiple of 64 in [64, 4096] (default 256) */
   /* bit 0: keep a BF16 copy for the batched-distance prune (n <= 256);
-   * bit 1: keep an FP8 (OCP e4m3) copy (n <= 512), scaled by a power of two
+   * bit 1: keep an FP8 (OCP e4m3) copy (n <= 1024), scaled by a power of two
    * per 256-row chunk so that every value fits the e4m3 range.  Both need
    * leaf_size to be a multiple of 256. */
   int32_t precision;
@@ -212,9 +212,14 @@ typedef struct {
    * IV-C); 1: skip that seed. */
   int32_t no_seed_leaf;
   sofa_workspace* ws; /* NULL: the index's own workspace (one caller at a time) */
-  /* Candidate slots per query in the workspace (0 = library default).  A
-   * smaller value only costs time: when in-band candidates are dropped the
-   * query is finished by an exhaustive pass, so results stay exact. */
+  /* Candidate slots per query in the workspace, and the length of each
+   * query's list of refined rows (0 = library defaults: candidates for the
+   * BF16 prune 32768, or 2^18 for k > 16 within 1 GiB per batch; for the
+   * FP8 prune 2^18, or 2^20 for k > 16 within 2 GiB per batch; never below
+   * 32768.  Refined rows: 32768, or 2^18 for k > 16 within 1 GiB per batch,
+   * never below 65536).  A smaller value only costs time: when in-band candidates are
+   * dropped the query is searched again with its tightened bound, or finished
+   * by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
   /* BF16/FP8 prune only: 0 (default) and 1 run the 256-row chunks in passes
    * of decreasing stride (1024, 32, 1 for k <= 3; 1024, 128, 16, 2, 1 from
@@ -262,8 +267,10 @@ typedef struct {
   /* queries whose batched-distance candidates overflowed, by cause: a
    * candidate inside the final band was evicted or dropped; a BF16/FP8
    * candidate was dropped; the final band held more rows than the ranking
-   * buffer.  max_candidates: the largest BF16/FP8 candidate count of one
-   * query in one pass. */
+   * buffer (1,024 rows; without a radius such a band is ranked in FP64 from
+   * the query's list of refined rows, with no exhaustive pass).
+   * max_candidates: the largest BF16/FP8 candidate count of one query in
+   * one pass. */
   int64_t overflow_evicted, overflow_bf16_drop, overflow_band, max_candidates;
   /* queries whose BF16/FP8 candidates overflowed and that were searched once
    * more with their tightened bound as the radius (on the BF16 tier when the

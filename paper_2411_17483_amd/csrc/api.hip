@@ -313,8 +313,8 @@ extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, 
       }
     }
     if (s == SOFA_OK && params && (params->precision & 2)) {
-      if (ix->n_pad > 512)
-        s = set_error(SOFA_EINVAL, "the FP8 copy supports n <= 512 (padded length %d)", ix->n_pad);
+      if (ix->n_pad > 1024)
+        s = set_error(SOFA_EINVAL, "the FP8 copy supports n <= 1024 (padded length %d)", ix->n_pad);
       else if (ix->L % 256)
         s = set_error(SOFA_EINVAL, "the FP8 copy needs leaf_size to be a multiple of 256");
       else {
@@ -437,9 +437,15 @@ namespace {
 
 constexpr uint32_t kExhCap = 1u << 20;
 
-int cap_for(int k, const sofa_knn_params* p) {
+// Result keys per query (refined rows inside the band when they were
+// refined).  A query whose list fills while a dropped row lies in the final
+// band is finished by the exhaustive pass, so large k (more rows refined)
+// gets a longer list, within a byte budget per batch.
+constexpr int64_t kResListBytes = 1ll << 30;
+int cap_for(int k, const sofa_knn_params* p, int64_t B) {
   if (p && p->candidate_capacity > 0) return p->candidate_capacity;
-  return k <= 16 ? 32768 : 65536;
+  if (k <= 16) return 32768;
+  return (int)std::max<int64_t>(65536, std::min<int64_t>(1 << 18, kResListBytes / 8 / std::max<int64_t>(B, 1)));
 }
 
 // workspace regions of one batch
@@ -456,21 +462,21 @@ struct Layout {
   size_t total;
 };
 
-// Candidate slots per query and pass of the batched-distance prune.  The
-// FP8 bound is looser (3 fraction bits), so its lists are longer: sized so
-// that a pass rarely overflows into the retry and exhaustive paths.
-// The FP8 lists of a batch are kept within 2 GiB (never below the BF16 size).
-constexpr int kBf16Cap = 32768;
+// Candidate slots per query and pass of the batched-distance prune, sized
+// so that a pass rarely overflows into the retry pass (a whole pass over the
+// prune copy) or the exhaustive pass.  A larger k leaves more rows inside
+// the bound, and the FP8 bound is looser (3 fraction bits), so both get
+// longer lists, kept within a byte budget per batch and never below the
+// BF16 base size.
+constexpr int kBf16Cap = 32768, kBf16CapLargeK = 1 << 18;
 constexpr int kFp8Cap = 1 << 18, kFp8CapLargeK = 1 << 20;
-constexpr int64_t kFp8ListBytes = 1ll << 31;
+constexpr int64_t kBf16ListBytes = 1ll << 30, kFp8ListBytes = 1ll << 31;
 int bf16_cap(const sofa_knn_params* p, int k, int64_t B) {
   if (p && p->candidate_capacity > 0) return p->candidate_capacity;
-  if (p && p->prune == 2) {
-    const int64_t want = k > 16 ? kFp8CapLargeK : kFp8Cap;
-    const int64_t fit = kFp8ListBytes / 4 / std::max<int64_t>(B, 1);
-    return (int)std::max<int64_t>(kBf16Cap, std::min(want, fit));
-  }
-  return kBf16Cap;
+  const bool fp8 = p && p->prune == 2;
+  const int64_t want = fp8 ? (k > 16 ? kFp8CapLargeK : kFp8Cap) : (k > 16 ? kBf16CapLargeK : kBf16Cap);
+  const int64_t fit = (fp8 ? kFp8ListBytes : kBf16ListBytes) / 4 / std::max<int64_t>(B, 1);
+  return (int)std::max<int64_t>(kBf16Cap, std::min(want, fit));
 }
 
 Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
@@ -488,7 +494,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_MASK] = (size_t)ix->n_blocks * B * 8;
   sz[W_LBH] = (size_t)ix->n_blocks * kLeavesPerItem * B * 2;
   sz[W_CTR] = 64;
-  sz[W_RES] = (size_t)B * cap_for(k, p) * 8;
+  sz[W_RES] = (size_t)B * cap_for(k, p, B) * 8;
   sz[W_RCNT] = (size_t)B * 4;
   sz[W_FLAG] = (size_t)B * 8;
   sz[W_STAT] = (size_t)B * 4;
@@ -614,7 +620,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   a.n_blocks = ix->n_blocks;
   a.B = (int)B;
   a.k = k;
-  a.cap = cap_for(k, p);
+  a.cap = cap_for(k, p, B);
   a.seed_leaf = (p && p->no_seed_leaf) ? 0 : 1;
   a.Qp = (float*)at(W_QP);
   a.tables = (float*)at(W_TAB);
@@ -792,7 +798,6 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     } else if (st_q == 1 || (st_q >= 2 && has_radius)) {
       redo.push_back(q);
     } else if (st_q >= 2) {
-      // exhaustive pass with the query's valid bound
       if (ws->exh.bytes == 0) SOFA_TRY(ws->exh.alloc((size_t)kExhCap * (4 + 8 + 8) + 256));
       char* eb = ws->exh.as<char>();
       uint32_t* pos = (uint32_t*)eb;
@@ -800,8 +805,16 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       int64_t* id = (int64_t*)(eb + (size_t)kExhCap * 12);
       uint32_t* cnt = (uint32_t*)(eb + (size_t)kExhCap * 20);
       uint32_t s_found = 0;
-      SOFA_TRY(launch_exhaustive(a, (int)q, pos, cnt, kExhCap, d64, id, d_ids, d_d, st, &s_found));
-      stats.overflow_fallbacks++;
+      if (st_q == 5) {
+        // more in-band rows than the finalize ranks in one workgroup, none
+        // evicted or dropped: all of them are in the query's list of
+        // refined rows, which is ranked in FP64 on its own
+        SOFA_TRY(launch_band_rank(a, (int)q, pos, cnt, kExhCap, d64, id, d_ids, d_d, st, &s_found));
+      } else {
+        // exhaustive pass with the query's valid bound
+        SOFA_TRY(launch_exhaustive(a, (int)q, pos, cnt, kExhCap, d64, id, d_ids, d_d, st, &s_found));
+        stats.overflow_fallbacks++;
+      }
     }
   }
   // search a subset of the queries again (exactness does not depend on the

@@ -966,7 +966,9 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
 // group together, with 512 registers, measured slower on 10M x 256)
 constexpr int kTileWaves = 2;
 
-// launch over the supported (precision, K steps) pairs
+// launch over the supported (precision, K steps) pairs.  FP8 rows of 1024
+// values: the A operand alone takes 256 VGPRs and the two B buffers 128 KB
+// of LDS, so one workgroup per CU, one wave per SIMD (512 registers).
 template <bool DUMP>
 static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, hipStream_t st) {
 #define SOFA_TILE(P, K) k_bf16_tiles<P, K, DUMP, kTileWaves><<<grid, 256, 0, st>>>(a, b)
@@ -983,7 +985,8 @@ static sofa_status launch_tiles(const SearchArgs& a, const Bf16Args& b, unsigned
       case 2: SOFA_TILE(2, 2); break;
       case 4: SOFA_TILE(2, 4); break;
       case 8: SOFA_TILE(2, 8); break;
-      default: return set_error(SOFA_EINVAL, "the FP8 prune supports n <= 512 (padded %d)", a.n_pad);
+      case 16: k_bf16_tiles<2, 16, DUMP, 1><<<grid < 256u ? grid : 256u, 256, 0, st>>>(a, b); break;
+      default: return set_error(SOFA_EINVAL, "the FP8 prune supports n <= 1024 (padded %d)", a.n_pad);
     }
   } else {
     return set_error(SOFA_EINVAL, "unknown prune precision %d", b.prec);
@@ -1211,7 +1214,8 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
     SOFA_RC(2)
     SOFA_RC(4)
     SOFA_RC(8)
-    default: return set_error(SOFA_EINVAL, "the batched-distance prune supports n <= 512");
+    SOFA_RC(16)
+    default: return set_error(SOFA_EINVAL, "the batched-distance prune supports n <= 1024");
   }
 #undef SOFA_RC
   if (ev) (void)hipEventRecord(ev[2], st);

@@ -469,6 +469,23 @@ __global__ __launch_bounds__(256) void k_exhaustive(SearchArgs a, int q, uint32_
   }
 }
 
+// rows of query q's list of refined rows inside the final FP32 band.  When
+// no row of the band was evicted or dropped, the list holds all of them:
+// the band only shrinks, so each was inside it when it was refined.
+__global__ void k_band_collect(SearchArgs a, int q, uint32_t* __restrict__ pos_out,
+                               uint32_t* __restrict__ cnt, uint32_t cap) {
+  const float band = __uint_as_float(a.U[q]) * a.band_f;
+  const uint32_t c = a.rescnt[q];
+  const uint32_t lim = c < (uint32_t)a.cap ? c : (uint32_t)a.cap;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += gridDim.x * blockDim.x) {
+    const uint64_t key = a.res[(int64_t)q * a.cap + i];
+    if (key_d(key) <= band) {
+      const uint32_t slot = atomicAdd(cnt, 1u);
+      if (slot < cap) pos_out[slot] = (uint32_t)key;
+    }
+  }
+}
+
 // FP64 distances of the exhaustive survivors
 __global__ void k_exh_exact(SearchArgs a, int q, const uint32_t* __restrict__ pos, uint32_t s,
                             double* __restrict__ d, int64_t* __restrict__ id) {
@@ -824,6 +841,24 @@ sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, i
   return launch_finalize(a, out_ids, out_d, status, st, ev);
 }
 
+// FP64 ranking of the s rows collected in pos: the query's k nearest
+static sofa_status rank_collected(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt, uint32_t cap,
+                                  double* d, int64_t* id, int64_t* out_ids, float* out_d, hipStream_t st,
+                                  uint32_t* s_out, const char* what) {
+  uint32_t s = 0;
+  SOFA_HIP(hipMemcpyAsync(&s, cnt, 4, hipMemcpyDeviceToHost, st));
+  SOFA_HIP(hipStreamSynchronize(st));
+  if (s > cap)
+    return set_error(SOFA_EINTERNAL, "query %d: %u series tie within the FP32 error band "
+                                     "(limit %u)", q, s, cap);
+  if (s < (uint32_t)a.k) return set_error(SOFA_EINTERNAL, "query %d: %s found %u < k rows", q, what, s);
+  k_exh_exact<<<nblk(s, 256), 256, 0, st>>>(a, q, pos, s, d, id);
+  k_exh_rank<<<nblk(s, 256), 256, 0, st>>>(a.k, q, s, d, id, out_ids, out_d);
+  SOFA_HIP(hipGetLastError());
+  *s_out = s;
+  return SOFA_OK;
+}
+
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,
                               uint32_t cap, double* d, int64_t* id, int64_t* out_ids, float* out_d,
                               hipStream_t st, uint32_t* s_out) {
@@ -836,18 +871,15 @@ sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_
     case 16: launch_exh_t<16>(a, q, pos, cnt, cap, st); break;
     default: return set_error(SOFA_EINTERNAL, "unsupported padded length %d", a.n_pad);
   }
-  uint32_t s = 0;
-  SOFA_HIP(hipMemcpyAsync(&s, cnt, 4, hipMemcpyDeviceToHost, st));
-  SOFA_HIP(hipStreamSynchronize(st));
-  if (s > cap)
-    return set_error(SOFA_EINTERNAL, "query %d: %u series tie within the FP32 error band "
-                                     "(limit %u)", q, s, cap);
-  if (s < (uint32_t)a.k) return set_error(SOFA_EINTERNAL, "query %d: exhaustive pass found %u < k rows", q, s);
-  k_exh_exact<<<nblk(s, 256), 256, 0, st>>>(a, q, pos, s, d, id);
-  k_exh_rank<<<nblk(s, 256), 256, 0, st>>>(a.k, q, s, d, id, out_ids, out_d);
-  SOFA_HIP(hipGetLastError());
-  *s_out = s;
-  return SOFA_OK;
+  return rank_collected(a, q, pos, cnt, cap, d, id, out_ids, out_d, st, s_out, "exhaustive pass");
+}
+
+sofa_status launch_band_rank(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt, uint32_t cap,
+                             double* d, int64_t* id, int64_t* out_ids, float* out_d, hipStream_t st,
+                             uint32_t* s_out) {
+  k_fill_u32<<<1, 64, 0, st>>>(cnt, 0u, 1);
+  k_band_collect<<<64, 256, 0, st>>>(a, q, pos, cnt, cap);
+  return rank_collected(a, q, pos, cnt, cap, d, id, out_ids, out_d, st, s_out, "band ranking");
 }
 
 }  // namespace sofa

@@ -61,5 +61,10 @@ sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,
                               uint32_t cap, double* d, int64_t* id, int64_t* out_ids, float* out_d,
                               hipStream_t st, uint32_t* s_out);
+// the final band of query q ranked in FP64 from its list of refined rows
+// (valid when no row of the band was evicted or dropped)
+sofa_status launch_band_rank(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt, uint32_t cap,
+                             double* d, int64_t* id, int64_t* out_ids, float* out_d, hipStream_t st,
+                             uint32_t* s_out);
 
 }  // namespace sofa

@@ -278,6 +278,32 @@ def test_knn_many_exact_ties_take_exhaustive_pass(gpu_lib):
         _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
 
 
+def test_knn_band_overflow_ranked_from_refined_rows(gpu_lib):
+    """1,500 copies of one row: more rows tie inside the final band than the
+    finalize ranks in one workgroup (1,024).  The BF16 path keeps every
+    in-band candidate in the query's list of refined rows, so the band is
+    ranked in FP64 from that list, with no exhaustive pass.  The plain
+    path's per-wave lists evict tied rows, and the eviction sends the query
+    to the exhaustive pass.  Both answers are the oracle's."""
+    N, n = 12000, 128
+    X = synth.collection(N, n, "rw", seed=53)
+    dup = np.sort(np.random.default_rng(1).choice(np.arange(1, N), 1500, replace=False))
+    X[dup] = X[0]
+    Q = np.stack([X[0], X[7]])
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=1)
+    for prune in (0, 1):
+        for k in (1, 10, 100):
+            ids, d = ix.knn(_t(Q), k, prune=prune)
+            ref_ids, ref_d2 = oracle.knn(X, Q, k)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+            st = ix.stats()
+            if prune == 1:
+                assert st["overflow_band"] == 1 and st["overflow_fallbacks"] == 0, (k, st)
+            else:
+                assert st["overflow_evicted"] == 1 and st["overflow_fallbacks"] == 1, (k, st)
+
+
 def test_knn_tiny_candidate_capacity_stays_exact(gpu_lib):
     N, n, B = 20000, 256, 24
     X = synth.collection(N, n, "mix", seed=81)
@@ -559,8 +585,26 @@ def test_fp8_knn_radius_and_capacity_paths(gpu_lib):
     assert ix.stats()["overflow_fallbacks"] > 0
 
 
-def test_fp8_lengths_64_to_512(gpu_lib):
-    for n, N in ((64, 9000 + 7), (128, 7000 + 3), (512, 6000 + 5)):
+def test_fp8_lower_bounds_never_exceed_distance_1024(gpu_lib):
+    """Rows of 1024 values (16 K steps, one wave per SIMD): the FP8 bound
+    stays below the FP64 distance on every pair."""
+    N, n, B = 2048 + 9, 1024, 24
+    X = synth.collection(N, n, "mix", seed=255)
+    X[5] *= np.float32(200.0)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=256)
+    Q[0] = X[3]
+    Q[1] = X[5] * np.float32(1.0001)
+    bins, ix = _fp8_index(gpu_lib, X)
+    LB = ix.fp8_lower_bounds(_t(Q)).cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    Xd = X.astype(np.float64)[ids.cpu().numpy()]
+    for b in range(B):
+        d2 = np.sum((Xd - Q[b].astype(np.float64)) ** 2, axis=1)
+        assert np.all(LB[b] <= d2 * (1 + 1e-12) + 1e-30), (b, float(np.max(LB[b] - d2)))
+
+
+def test_fp8_lengths_64_to_1024(gpu_lib):
+    for n, N in ((64, 9000 + 7), (128, 7000 + 3), (512, 6000 + 5), (1024, 5000 + 3)):
         X = synth.collection(N, n, "mix", seed=281 + n)
         Q, _ = synth.queries(X, 20, sigma=0.1, seed=282)
         bins = _bins(gpu_lib, X, 2000, pool=min(16, n // 2 - 1))
@@ -583,10 +627,11 @@ def test_fp8_argument_errors(gpu_lib):
         bf.knn(_t(X[:2]), 1, prune=3)
     with pytest.raises(gpu_lib.SofaError):
         gpu_lib.Index(bins, _t(X), leaf_size=64, precision=2)
-    X10 = synth.collection(2000, 1024, "rw", seed=292)
-    b10 = _bins(gpu_lib, X10, 1000)
+    # every supported length (n <= 1024) has the FP8 tier; longer series
+    # are rejected when the bins are learned
+    X20 = synth.collection(1000, 2048, "rw", seed=292)
     with pytest.raises(gpu_lib.SofaError):
-        gpu_lib.Index(b10, _t(X10), precision=2)
+        _bins(gpu_lib, X20, 500)
 
 
 # --------------------------------------------------------------------------- #

@@ -27,8 +27,8 @@ odd rows eight sinusoids plus noise; queries are noisy copies, sigma 0.1):
   row would exceed the 2^32 work-items a dispatch can count (every row must
   reach the index: the exported ids form a permutation);
 - three HBM-resident collections served together (100M x 128 on the BF16
-  tier, 20M x 512 on the FP8 tier, 5M x 1024 on the plain scan), requests of
-  k in {1, 10, 100}, each answer the same alone and in the mix.
+  tier, 20M x 512 and 5M x 1024 on the FP8 tier), requests of k in
+  {1, 10, 100}, each answer the same alone and in the mix.
 """
 import gc
 import sys
@@ -246,7 +246,7 @@ def test_serving_three_collections(gpu_lib):
     specs = [  # (N, n, collection seed, copies built, prune tier served)
         (100_000_000, 128, 6, 1, 1),
         (20_000_000, 512, 7, 2, 2),
-        (5_000_000, 1024, 8, 0, 0),
+        (5_000_000, 1024, 8, 2, 2),
     ]
     pool, s = 64, 3
     colls = []
