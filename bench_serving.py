@@ -106,7 +106,7 @@ def run_level(srv, cids, pools, qps, duration, seed, ks=(1, 10, 100)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--qps", default="100,400,1500,4000")
+    ap.add_argument("--qps", default="100,400,1500,4000,8000,16000")
     ap.add_argument("--duration", type=float, default=6.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=256)
