@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--headline", default="learned_bf16",
                     help="path whose k-NN rate is the reported value")
     ap.add_argument("--no-isax", action="store_true", help="skip the iSAX summary comparison")
+    ap.add_argument("--eval-queries", type=int, default=10_000,
+                    help="held-out queries for the radius networks' fallback rate and error")
     ap.add_argument("--no-radius", action="store_true",
                     help="skip the radius networks and the learned paths (short profiling runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -306,6 +308,37 @@ def main():
         del iix, ibins
         torch.cuda.empty_cache()
 
+    # the radius networks on held-out queries (own seed): one learned-radius
+    # BF16 search of the whole set per k; the fallback rate and the error of
+    # the predicted ln d_k against the exact k-th distance the search returns
+    radius_eval = None
+    if models and not args.headline_only and args.eval_queries > 0:
+        radius_eval = {}
+        Qev, _ = synth.queries(X, args.eval_queries, sigma=0.1, seed=args.seed + 3)
+        Qev_d = torch.from_numpy(Qev).to(dev)
+        feat_ev, _, _ = bins.transform(Qev_d, sel=False, words=False)
+        for kk, m in models.items():
+            ix.knn(Qev_d, kk, prune=1, model=m, sampling=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, dd = ix.knn(Qev_d, kk, prune=1, model=m, sampling=1)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            st = ix.stats()
+            resid = (torch.log(dd[:, -1].double()) - m.forward(feat_ev.contiguous()).double()).cpu().numpy()
+            margin = m.get()["margin"]
+            radius_eval[f"k{kk}"] = {
+                "queries": args.eval_queries, "queries_per_s": args.eval_queries / sec,
+                "radius_fallbacks": st["radius_fallbacks"],
+                "fallback_rate": st["radius_fallbacks"] / args.eval_queries,
+                "resid_ln_dk": {"rmse": float(np.sqrt(np.mean(resid ** 2))),
+                                "mean": float(np.mean(resid)),
+                                "p1": float(np.percentile(resid, 1)), "p99": float(np.percentile(resid, 99))},
+                "margin": margin, "resid_above_margin": int(np.sum(resid > margin))}
+            log(f"radius eval k={kk}: {st['radius_fallbacks']} fallbacks of {args.eval_queries}, "
+                f"rmse {radius_eval[f'k{kk}']['resid_ln_dk']['rmse']:.4f}")
+        del Qev_d, feat_ev
+
     # approximate search (opt-in, no exactness guarantee): the M leaves of
     # smallest envelope bound per query; recall@k against the exact answer
     approx = None
@@ -389,7 +422,7 @@ def main():
         "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "k": k, "queries": int(len(lat)), "path": headline},
         "paths": results, "paths_ids_identical": agree, "word_scan": word_scan, "isax_summary": isax,
-        "approximate": approx,
+        "approximate": approx, "radius_eval": radius_eval,
         "parity_sample": parity,
         "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
         "radius_models": model_info,
