@@ -748,7 +748,19 @@ __device__ __forceinline__ int64_t item_chunk(const Bf16Args& b, uint32_t it) {
                                     : (int64_t)it * b.chunk_stride + b.chunk_first);
 }
 
-// A operand of one wave: row blocks rb and rb + 1 (32 rows each), all K steps
+// A operand of one wave: row blocks rb and rb + 1 (32 rows each), all K
+// steps.  The rows stream through once per pass: non-temporal loads keep
+// them from evicting the query rows the B gathers reuse.
+template <int PREC>
+__device__ __forceinline__ typename TileTraits<PREC>::frag load_frag_nt(const u4v* p) {
+  if constexpr (PREC == 1) {
+    return __builtin_bit_cast(bf8v, __builtin_nontemporal_load(p));
+  } else {
+    const u4v lo = __builtin_nontemporal_load(p), hi = __builtin_nontemporal_load(p + 64);
+    return __builtin_bit_cast(v8i, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+  }
+}
+
 template <int PREC, int KS>
 __device__ __forceinline__ void load_a(const u4v* xv, int64_t rb, int lane,
                                        typename TileTraits<PREC>::frag (&av)[2][KS]) {
@@ -756,7 +768,7 @@ __device__ __forceinline__ void load_a(const u4v* xv, int64_t rb, int lane,
 #pragma unroll
   for (int r = 0; r < 2; r++)
 #pragma unroll
-    for (int ks = 0; ks < KS; ks++) av[r][ks] = load_frag<PREC>(xv + ((rb + r) * KS + ks) * 64 * H + lane);
+    for (int ks = 0; ks < KS; ks++) av[r][ks] = load_frag_nt<PREC>(xv + ((rb + r) * KS + ks) * 64 * H + lane);
 }
 
 // raw buffer descriptor (fourth word for gfx9 raw, untyped access) over
@@ -770,11 +782,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int
 template <int PREC>
 __device__ __forceinline__ typename TileTraits<PREC>::frag load_frag_buf(__amdgpu_buffer_rsrc_t r, int voff,
                                                                          int soff) {
+  // cache policy 2: non-temporal (streamed once)
   if constexpr (PREC == 1) {
-    return __builtin_bit_cast(bf8v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(bf8v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 2));
   } else {
-    const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
-    const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 1024, 0);
+    const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 2);
+    const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 1024, 2);
     return __builtin_bit_cast(v8i, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
   }
 }
