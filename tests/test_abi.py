@@ -41,6 +41,14 @@ def test_errors_without_device_work():
     assert b"l=0" in lib.sofa_last_error()
     st = lib.sofa_knn(None, None, 1, 1, None, None, None, None)
     assert st == sofa.SOFA_EINVAL
+    # valid parameters, but a sample beyond 2^25 rows or series longer than
+    # 1024 values: rejected before the (never dereferenced) array is used
+    p = sofa.BinParams(16, 256, 16, 0, 0, 0)
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.sofa_learn_bins(fake, 1 << 26, 256, (1 << 25) + 1, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == sofa.SOFA_EINVAL and b"2^25" in lib.sofa_last_error()
+    st = lib.sofa_learn_bins(fake, 100, 2048, 10, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == sofa.SOFA_EINVAL and b"n=2048" in lib.sofa_last_error()
 
 
 # public struct name in include/sofa.h -> ctypes structure in the binding
