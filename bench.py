@@ -244,19 +244,28 @@ def main():
         results[name] = res
     agree = all(np.array_equal(v, ids_by_path[headline]) for v in ids_by_path.values())
 
-    # batch-1 latency of the headline path
-    kw = dict(paths[headline])
-    if kw.get("model") == "learned":
-        kw["model"] = models[k]
-    lat = []
-    for i in range(min(args.latency_queries, B)):
-        q = Qd[i:i + 1]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ix.knn(q, k, **kw)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-    lat = np.array(lat) if lat else np.zeros(1)
+    # batch-1 latency of the headline path (and of the plain path beside it)
+    def batch1_latency(kw):
+        kw = dict(kw)
+        if kw.get("model") == "learned":
+            kw["model"] = models[k]
+        out = []
+        for i in range(min(args.latency_queries, B)):
+            q = Qd[i:i + 1]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ix.knn(q, k, **kw)
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t0) * 1e3)
+        return np.array(out) if out else np.zeros(1)
+
+    lat = batch1_latency(paths[headline])
+    lat_plain = None
+    if not args.headline_only and args.latency_queries > 0:
+        lp = batch1_latency(paths["plain"])
+        lat_plain = {"p50": float(np.percentile(lp, 50)), "p99": float(np.percentile(lp, 99)), "k": k,
+                     "queries": int(len(lp)), "path": "plain"}
+        log(f"batch-1 latency, plain path: p50 {lat_plain['p50']:.2f} ms, p99 {lat_plain['p99']:.2f} ms")
 
     # the iSAX summary (PAA means, N(0,1) breakpoints) through the same path
     # on the same data: rows left to the exact distance, tile pairs, queries/s,
@@ -421,6 +430,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "latency_ms_batch1": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "k": k, "queries": int(len(lat)), "path": headline},
+        "latency_ms_batch1_plain": lat_plain,
         "paths": results, "paths_ids_identical": agree, "word_scan": word_scan, "isax_summary": isax,
         "approximate": approx, "radius_eval": radius_eval,
         "parity_sample": parity,
