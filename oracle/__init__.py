@@ -21,7 +21,7 @@ Functions and the passages they follow (arXiv 2411.17483):
                      learned-radius network (not in the paper): FP64 forward,
                      chain-rule gradients and Adam (Kingma & Ba 2015)
   to_bf16 / to_e4m3  round-to-nearest-even onto the BF16 and OCP E4M3 grids
-  tlb                Section V-E tightness of lower bound (parity unpinned)
+  tlb                Section V-E tightness of lower bound (a diagnostic)
 """
 import ctypes
 import os

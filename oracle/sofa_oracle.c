@@ -17,9 +17,8 @@
  * brute-force k-NN against numpy lexsort, equi-depth/equi-width breakpoints on
  * constructed samples, MLP gradients against central finite differences,
  * Adam's first step, iSAX breakpoints against an independent normal quantile,
- * PAA bound == distance on piecewise-constant series.  The TLB diagnostic
- * (orc_tlb) is "parity unpinned": the
- * paper reports TLB only on datasets that are not available.
+ * PAA bound == distance on piecewise-constant series, the TLB on pairs worked
+ * by hand and on equal bounds and distances (where it is one).
  */
 #include <math.h>
 #include <stdint.h>
@@ -358,8 +357,8 @@ void orc_dist2_rows(const float* X, int n, const float* q, const long long* rows
 }
 
 /* Tightness of the lower bound (Section V-E): mean over (query, series)
- * pairs with nonzero distance of LB / distance.  Diagnostic; parity
- * unpinned (the paper measures it only on unavailable datasets). */
+ * pairs with nonzero distance of LB / distance (distances, not squares).
+ * A diagnostic: the paper's values are for datasets not available here. */
 double orc_tlb(const double* lb2, const double* dist2, long cnt) {
   double s = 0.0;
   long c = 0;

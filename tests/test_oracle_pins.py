@@ -335,8 +335,27 @@ def test_e4m3_rounding_grid():
     assert np.array_equal(oracle.to_e4m3(v.astype(np.float64)), ref)
 
 
-def test_tlb_range_diagnostic():
-    """TLB is a diagnostic (parity unpinned): only its range is checked."""
+def test_tlb_hand_computed_and_equality():
+    """Section V-E: TLB is the bound over the true distance (distances, not
+    their squares), averaged over the pairs, and it is one where the two are
+    equal.  The pairs at distance zero have no ratio and are left out.  The
+    values below are worked by hand: a squared ratio would give 0.4375, a
+    count that kept the zero pair 0.5."""
+    lb2 = np.array([1.0, 4.0, 0.0, 9.0, 2.0])
+    d2 = np.array([4.0, 16.0, 0.0, 9.0, 8.0])
+    # ratios 1/2, 2/4, (none), 3/3, sqrt(2)/sqrt(8) = 1/2
+    assert oracle.tlb(lb2, d2) == pytest.approx(0.625, abs=1e-15)
+    d = np.random.default_rng(5).uniform(0.1, 40.0, 1000)
+    assert oracle.tlb(d, d) == pytest.approx(1.0, abs=1e-15)
+    assert oracle.tlb(np.zeros(1000), d) == 0.0
+    # linear in the bound's distance: four times the squared bound doubles it
+    assert oracle.tlb(d / 16.0, d) == pytest.approx(0.25, abs=1e-15)
+    assert oracle.tlb(d / 4.0, d) == pytest.approx(0.5, abs=1e-15)
+    assert oracle.tlb(np.zeros(3), np.zeros(3)) == 0.0
+
+
+def test_tlb_range_on_sfa_bounds():
+    """On SFA bounds of real pairs the TLB lies in (0, 1]."""
     X = synth.collection(200, 128, "mix", seed=8)
     var, sel, beta = oracle.learn_bins(X, 200, P=16, l=16, alpha=256)
     W, C = oracle.words(X, sel, beta)
