@@ -603,6 +603,41 @@ def test_fp8_lower_bounds_never_exceed_distance_1024(gpu_lib):
         assert np.all(LB[b] <= d2 * (1 + 1e-12) + 1e-30), (b, float(np.max(LB[b] - d2)))
 
 
+def test_prune_bounds_fuzz_ten_million_pairs(gpu_lib):
+    """Both batched-distance bounds (BF16 and FP8, one index holding both
+    copies) stay below the FP64 distance on 12.6M pairs: 262,157 rows, one
+    in 509 of them scaled by 1e-4 to 316 (log-uniform), so that FP8 chunk
+    scales vary and small rows fall into the e4m3 subnormal range, rows on
+    BF16 ties, and 48 queries: noisy copies, near and exact copies (also of
+    scaled rows) and unrelated series."""
+    N, n = (1 << 18) + 13, 256
+    X = synth.collection(N, n, "mix", seed=271)
+    rng = np.random.default_rng(272)
+    scaled = np.arange(0, N, 509)
+    X[scaled] *= (10.0 ** rng.uniform(-4.0, 2.5, scaled.size)).astype(np.float32)[:, None]
+    X[3:7] = (np.round(X[3:7] * 128) / 128 + 2.0 ** -9).astype(np.float32)
+    Q = np.empty((48, n), dtype=np.float32)
+    Q[:16], _ = synth.queries(X, 16, sigma=0.1, seed=273)
+    near = rng.integers(0, N, 8)
+    Q[16:24] = X[near] + np.float32(1e-4) * rng.standard_normal((8, n)).astype(np.float32)
+    Q[24:28] = X[rng.integers(0, N, 4)]                       # exact copies
+    Q[28:32] = X[scaled[rng.integers(0, scaled.size, 4)]]     # exact copies of scaled rows
+    Q[32:40] = X[scaled[rng.integers(0, scaled.size, 8)]] * np.float32(1.0001)
+    Q[40:44] = X[3:7]                                         # rows on BF16 ties
+    Q[44:48] = synth.collection(4, n, "mix", seed=274)        # unrelated series
+    bins, ix = _fp8_index(gpu_lib, X, m=4000, precision=3)
+    Qd = _t(Q)
+    LBb = ix.bf16_lower_bounds(Qd).cpu().numpy().astype(np.float64)
+    LBf = ix.fp8_lower_bounds(Qd).cpu().numpy().astype(np.float64)
+    _, ids, _, _ = ix.export()
+    Xd = X.astype(np.float64)[ids.cpu().numpy()]
+    for b in range(Q.shape[0]):
+        d2 = np.sum((Xd - Q[b].astype(np.float64)) ** 2, axis=1)
+        lim = d2 * (1 + 1e-12) + 1e-30
+        assert np.all(LBb[b] <= lim), ("bf16", b, float(np.max(LBb[b] - d2)))
+        assert np.all(LBf[b] <= lim), ("fp8", b, float(np.max(LBf[b] - d2)))
+
+
 def test_fp8_lengths_64_to_1024(gpu_lib):
     for n, N in ((64, 9000 + 7), (128, 7000 + 3), (512, 6000 + 5), (1024, 5000 + 3)):
         X = synth.collection(N, n, "mix", seed=281 + n)
