@@ -245,6 +245,27 @@ def test_knn_ragged_shapes(gpu_lib, n, L, N):
         _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
 
 
+@pytest.mark.parametrize("N", [1, 5, 64, 65, 257])
+def test_knn_degenerate_sizes(gpu_lib, N):
+    """Collections smaller than a leaf or a 256-row chunk, a single row, and
+    k up to N (every row returned): ids equal to the oracle's on the plain
+    scan and on both batched-distance tiers, with bins from all N rows."""
+    n = 64
+    X = synth.collection(N, n, "mix", seed=281 + N)
+    Q = np.empty((6, n), dtype=np.float32)
+    Q[:4], _ = synth.queries(X, 4, sigma=0.1, seed=282)
+    Q[4] = X[N - 1]                                           # exact copy
+    Q[5] = synth.collection(1, n, "hf", seed=283)[0]          # unrelated series
+    bins = _bins(gpu_lib, X, N)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=3)
+    ix64 = gpu_lib.Index(bins, _t(X), leaf_size=64)
+    for k in sorted({1, min(N, 5), min(N, 100)}):
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        for index, prune in ((ix64, 0), (ix, 0), (ix, 1), (ix, 2)):
+            ids, d = index.knn(_t(Q), k, prune=prune)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
 def test_knn_radius_paths_are_exact(gpu_lib):
     import torch
     N, n, B, k = 20000, 256, 32, 10
