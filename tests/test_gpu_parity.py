@@ -266,6 +266,25 @@ def test_knn_degenerate_sizes(gpu_lib, N):
             _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
 
 
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_knn_alphabet_of_one_and_two(gpu_lib, alpha):
+    """Degenerate alphabets: with one symbol every word bound is 0, so the
+    plain scan visits every leaf; with two, one breakpoint per value.  The
+    answer is still the oracle's on the plain scan and both prune tiers."""
+    N, n, B = 3000 + 3, 128, 10
+    X = synth.collection(N, n, "mix", seed=291)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=292)
+    bins = _bins(gpu_lib, X, 1000, alpha=alpha)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=3)
+    ref_ids, ref_d2 = oracle.knn(X, Q, 10)
+    for prune in (0, 1, 2):
+        ids, d = ix.knn(_t(Q), 10, prune=prune)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+        st = ix.stats()  # the last call's counters
+        if alpha == 1 and prune == 0:
+            assert st["leaves_visited"] == st["leaves_total"]
+
+
 def test_knn_radius_paths_are_exact(gpu_lib):
     import torch
     N, n, B, k = 20000, 256, 32, 10
