@@ -285,6 +285,28 @@ def test_knn_alphabet_of_one_and_two(gpu_lib, alpha):
             assert st["leaves_visited"] == st["leaves_total"]
 
 
+def test_knn_constant_series(gpu_lib):
+    """A constant series z-normalises to zeros (population sigma 0).  A zero
+    query is at d^2 = |x|^2 (= n up to the FP32 rounding of each row) from
+    every row, so every row falls inside the FP32 band and the order comes
+    from the FP64 ranking alone; zero rows in the collection sit at |q|^2
+    from every query.  Plain scan and both prune tiers against the oracle."""
+    N, n = 5000 + 3, 64
+    X = synth.collection(N, n, "mix", seed=301)
+    X[[10, 2000, 4999]] = 0.0
+    Q = np.empty((4, n), dtype=np.float32)
+    Q[0] = 0.0
+    Q[1] = X[7]
+    Q[2:], _ = synth.queries(X, 2, sigma=0.1, seed=302)
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=3)
+    for k in (1, 10, 100):
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        for prune in (0, 1, 2):
+            ids, d = ix.knn(_t(Q), k, prune=prune)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
 def test_knn_radius_paths_are_exact(gpu_lib):
     import torch
     N, n, B, k = 20000, 256, 32, 10
