@@ -922,6 +922,24 @@ def test_prune_batch_above_1024_queries(gpu_lib, k):
         assert 0 < st["series_bf16_needed"] <= st["series_bf16_checked"], (prune, st)
 
 
+def test_largest_batch(gpu_lib):
+    """The largest batch a call takes, 65,535 queries (65,536 slots of 64:
+    64 staged pieces of mask rows), on the plain scan and both prune tiers
+    against the oracle; one more query is refused."""
+    N, n, B = 2000 + 3, 64, 65535
+    X = synth.collection(N, n, "mix", seed=351)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=352)
+    bins, ix = _fp8_index(gpu_lib, X, precision=3)
+    ref_ids, ref_d2 = oracle.knn(X, Q, 3)
+    Qd = _t(Q)
+    for prune in (0, 1, 2):
+        ids, d = ix.knn(Qd, 3, prune=prune)
+        _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+    with pytest.raises(gpu_lib.SofaError) as e:
+        ix.knn(_t(np.concatenate([Q, Q[:1]])), 3)
+    assert e.value.status == gpu_lib.SOFA_EINVAL
+
+
 @pytest.mark.parametrize("L", [512, 1024])
 def test_prune_large_leaves(gpu_lib, L):
     """Leaves of several 256-row chunks: every chunk of a leaf runs the leaf's
