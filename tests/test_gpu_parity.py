@@ -922,6 +922,21 @@ def test_prune_batch_above_1024_queries(gpu_lib, k):
         assert 0 < st["series_bf16_needed"] <= st["series_bf16_checked"], (prune, st)
 
 
+@pytest.mark.parametrize("n", [36, 100, 200])
+def test_prune_lengths_with_padding(gpu_lib, n):
+    """Lengths that are not a multiple of 64 (padded to 64, 128 and 256 with
+    zeros in both operands) on both prune tiers against the oracle."""
+    N, B = 3000 + 5, 16
+    X = synth.collection(N, n, "mix", seed=371 + n)
+    Q, _ = synth.queries(X, B, sigma=0.1, seed=372)
+    bins, ix = _fp8_index(gpu_lib, X, precision=3)
+    for k in (1, 10):
+        ref_ids, ref_d2 = oracle.knn(X, Q, k)
+        for prune in (1, 2):
+            ids, d = ix.knn(_t(Q), k, prune=prune)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
 def test_largest_batch(gpu_lib):
     """The largest batch a call takes, 65,535 queries (65,536 slots of 64:
     64 staged pieces of mask rows), on the plain scan and both prune tiers
