@@ -31,6 +31,30 @@ def test_library_exports_every_declared_symbol():
     assert set(sofa.EXPORTED) <= set(_declared())
 
 
+def test_missing_library_raises_without_fallback(monkeypatch, tmp_path):
+    """Without the built library the binding refuses to run: there is no
+    CPU path to fall back on."""
+    from paper_2411_17483_amd import sofa
+    monkeypatch.setattr(sofa, "_lib", None)
+    monkeypatch.setattr(sofa, "LIB_PATH", str(tmp_path / "libsofa.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        sofa.load()
+
+
+def test_product_package_does_not_use_the_oracle():
+    """The oracle is test infrastructure: no module of the package imports
+    it or loads its library."""
+    pkg = os.path.join(ROOT, "paper_2411_17483_amd")
+    offenders = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp", ".c")):
+                text = open(os.path.join(dirpath, f), errors="replace").read()
+                if re.search(r"^\s*(import|from)\s+oracle\b|liboracle|sofa_oracle", text, flags=re.M):
+                    offenders.append(f)
+    assert not offenders, offenders
+
+
 def test_errors_without_device_work():
     from paper_2411_17483_amd import sofa
     lib = sofa.load()
