@@ -55,6 +55,21 @@ def test_product_package_does_not_use_the_oracle():
     assert not offenders, offenders
 
 
+def test_oracle_shares_no_code_with_the_library():
+    """The oracle includes nothing from the library's sources or headers, and
+    the library nothing from the oracle."""
+    orc = os.path.join(ROOT, "oracle")
+    for f in os.listdir(orc):
+        if f.endswith((".c", ".h", ".py")):
+            text = open(os.path.join(orc, f)).read()
+            assert not re.search(r"paper_2411_17483_amd|csrc|sofa\.h|sofa_internal", text), f
+    csrc = os.path.join(ROOT, "paper_2411_17483_amd", "csrc")
+    for f in os.listdir(csrc):
+        text = open(os.path.join(csrc, f), errors="replace").read()
+        for inc in re.findall(r'#include\s+"([^"]+)"', text):
+            assert "oracle" not in inc, (f, inc)
+
+
 def test_errors_without_device_work():
     from paper_2411_17483_amd import sofa
     lib = sofa.load()
