@@ -101,6 +101,7 @@ sofa_status sofa_bins_create(int32_t n, const sofa_bin_params* params, const int
 sofa_status sofa_bins_get(const sofa_bins* bins, sofa_bin_params* params, int32_t* n,
                           int32_t* sel, double* beta, double* var);
 
+/* Releases the handle and the device memory it holds.  NULL does nothing. */
 void sofa_bins_free(sofa_bins* bins);
 
 /* Projection onto the Fourier pool (Algorithm 2, step 1) and quantisation
@@ -158,6 +159,8 @@ typedef struct {
   int32_t has_fp8;
 } sofa_index_info;
 
+/* Fills *info from the index on the host, with no device work.  SOFA_EINVAL
+ * if either pointer is NULL. */
 sofa_status sofa_index_get_info(const sofa_index* index, sofa_index_info* info);
 
 /* Copies the index layout to caller device arrays (any may be NULL):
@@ -167,6 +170,8 @@ sofa_status sofa_index_get_info(const sofa_index* index, sofa_index_info* info);
 sofa_status sofa_index_export(const sofa_index* index, uint8_t* d_words, int32_t* d_ids,
                               uint8_t* d_env, uint64_t* d_keys, void* stream);
 
+/* Releases the index, its device arrays and its own workspace.  Work queued
+ * on it must have finished.  NULL does nothing. */
 void sofa_index_free(sofa_index* index);
 
 /* ------------------------------------------------------------------------ */
@@ -284,6 +289,9 @@ typedef struct {
   int64_t prune_passes;
 } sofa_knn_stats;
 
+/* Copies the counters of the last call on ws (or, with ws NULL, on the
+ * index's own workspace) to *out; all zero when no call has run there.
+ * SOFA_EINVAL if out is NULL. */
 sofa_status sofa_knn_get_stats(const sofa_workspace* ws, const sofa_index* index,
                                sofa_knn_stats* out);
 
@@ -322,8 +330,15 @@ typedef struct {
   uint64_t seed;    /* initial weights: Philox4x32-10 normal draws, He scaling */
 } sofa_radius_params;
 
+/* Creates a network of the given sizes (0 takes the default; D in [1, 64],
+ * H1 and H2 in [1, 4096], 1 <= k <= 100, else SOFA_EINVAL), its weights
+ * drawn from seed, standardisation mu = 0 and sd = 1, Adam moments zero.
+ * Allocates device memory (SOFA_ENOMEM or SOFA_EDEVICE on failure, with
+ * *out NULL) and synchronises the device. */
 sofa_status sofa_radius_create(const sofa_radius_params* params, sofa_radius** out);
+/* Releases the network and its device memory.  NULL does nothing. */
 void sofa_radius_free(sofa_radius* model);
+/* The length of the flat parameter vector (0 for NULL). */
 int64_t sofa_radius_num_params(const sofa_radius* model);
 
 /* Host copies in and out: params[num_params] FP32 master, mu[D], sd[D],
