@@ -22,6 +22,17 @@ def test_header_declares_the_boundary():
         assert core in names
 
 
+def test_every_declaration_is_documented():
+    """Each entry point in the header has a comment right above it."""
+    lines = open(os.path.join(ROOT, "include", "sofa.h")).read().split("\n")
+    bare = []
+    for i, line in enumerate(lines):
+        m = re.match(r"^[A-Za-z_][A-Za-z_0-9 ]*\**\s*\**(sofa_[a-z_0-9]+)\s*\(", line)
+        if m and not any("*/" in p or "//" in p for p in lines[max(0, i - 3):i]):
+            bare.append(m.group(1))
+    assert not bare, bare
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2411_17483_amd import sofa
     lib = sofa.load()
