@@ -14,7 +14,10 @@ and k = 1 with the same steps, and the headline path's batch-1 latency
 Prints one JSON line.  `value` is queries per second of the headline step
 with the inputs resident in HBM.  `roofline` describes the headline path's
 dominant kernel from its live HIP-event duration; `cpu_baseline` times the
-FP64 oracle brute force on a bounded sample of the same queries.
+FP64 oracle brute force over the same batch, and that run checks every
+query's answer: ids identical, distances within 1e-5 relative.  Any
+disagreement (with the oracle, or between the paths) nulls `value` and exits
+with status 1.
 """
 import argparse
 import json
@@ -73,7 +76,9 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--latency-queries", type=int, default=200)
-    ap.add_argument("--cpu-queries", type=int, default=160)
+    ap.add_argument("--cpu-queries", type=int, default=1000,
+                    help="queries checked against the FP64 oracle brute force (and timed as "
+                         "the CPU baseline); default: the whole batch")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path at k (for profiling runs)")
@@ -208,9 +213,12 @@ def main():
             ids, d = ix.knn(Qd, kk, **kw)
             stats.append(ix.stats())
         torch.cuda.synchronize()
+        run_dists[0] = d
         return (time.perf_counter() - t0) / steps, stats, ids
 
-    results, ids_by_path = {}, {}
+    run_dists = [None]
+
+    results, ids_by_path, d_by_path, ids_k1 = {}, {}, {}, {}
     for name, kw in paths.items():
         if args.headline_only and name != headline:
             continue
@@ -240,9 +248,13 @@ def main():
                     res[f"k{kk}"]["tiles_peak_tflops"] = peak / 1e12
             if kk == k:
                 ids_by_path[name] = ids.cpu().numpy()
+                d_by_path[name] = run_dists[0].cpu().numpy()
+            elif kk == 1:
+                ids_k1[name] = ids.cpu().numpy()
             log(f"{name} k={kk}: {sec * 1e3:.2f} ms/step ({B / sec:.0f} q/s)")
         results[name] = res
     agree = all(np.array_equal(v, ids_by_path[headline]) for v in ids_by_path.values())
+    agree_k1 = all(np.array_equal(v, ids_k1[headline]) for v in ids_k1.values()) if ids_k1 else True
 
     # batch-1 latency of the headline path (and of the plain path beside it)
     def batch1_latency(kw):
@@ -402,8 +414,13 @@ def main():
                     "work_per_launch": {"flop": flops / launches, "pairs_needed": pairs / launches,
                                         "pairs_computed": cnt["series_bf16_checked"] / launches}}
 
+    # exactness of the timed answers: every query of the batch against the
+    # FP64 oracle brute force over all N rows (ids identical, distances within
+    # 1e-5 relative; the k = 1 answer must be the first column, the ranking
+    # being a total order on (distance, id)); a disagreement voids the figure
     cpu = None
     parity = None
+    parity_ok = agree and agree_k1
     if not args.no_cpu and args.cpu_queries > 0:
         import oracle
         m = min(args.cpu_queries, B)
@@ -412,11 +429,22 @@ def main():
         ref_ids, ref_d2 = oracle.knn(X, Q[:m], k, nthreads=threads)
         dt = time.perf_counter() - t0
         cpu = {"value": m / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {m} of the {B} queries, k={k}, FP64 brute force over all "
-                         f"{N} rows ({dt:.1f} s)"}
+               "sample": f"{'all' if m == B else 'first'} {m} of the {B} queries, k={k}, FP64 brute force "
+                         f"over all {N} rows ({dt:.1f} s)"}
         got = ids_by_path[headline][:m]
-        parity = f"{int(np.sum(np.all(got == ref_ids, axis=1)))}/{m} queries with ids identical to the oracle"
-        log(parity)
+        ids_ok = np.all(got == ref_ids, axis=1)
+        ref_d = np.sqrt(ref_d2)
+        d_ok = np.all(np.abs(d_by_path[headline][:m].astype(np.float64) - ref_d) <= 1e-5 * ref_d, axis=1)
+        k1_ok = np.ones(m, dtype=bool)
+        if headline in ids_k1:
+            k1_ok = ids_k1[headline][:m, 0] == ref_ids[:, 0]
+        good = ids_ok & d_ok & k1_ok
+        parity = {"checked": f"{int(good.sum())}/{m}", "ids_identical": int(ids_ok.sum()),
+                  "dists_within_1e-5": int(d_ok.sum()), "k1_first_column": int(k1_ok.sum()),
+                  "max_rel_dist_err": float(np.max(np.abs(d_by_path[headline][:m] - ref_d) /
+                                                   np.maximum(ref_d, 1e-300)))}
+        parity_ok = parity_ok and bool(good.all())
+        log(f"parity against the oracle: {parity}")
 
     out = {
         "metric": "exact k-NN queries/s @10M x 256: learned-radius + BF16 vs plain GPU; p99 ms",
@@ -433,14 +461,21 @@ def main():
         "latency_ms_batch1_plain": lat_plain,
         "paths": results, "paths_ids_identical": agree, "word_scan": word_scan, "isax_summary": isax,
         "approximate": approx, "radius_eval": radius_eval,
-        "parity_sample": parity,
+        "parity_sample": parity, "parity_ok": parity_ok,
+        "paths_ids_identical_k1": agree_k1,
         "build_s": {"bins": t_bins, "index": t_build, "radius_training": t_train},
         "radius_models": model_info,
         "speedup_vs_plain": {f"k{kk}": results[headline][f"k{kk}"]["queries_per_s"] /
                              results["plain"][f"k{kk}"]["queries_per_s"]
                              for kk in (k, 1) if "plain" in results and f"k{kk}" in results[headline]},
     }
+    if not parity_ok:
+        # a figure for answers that are not the exact ones is not reported
+        out["value"] = None
+        out["parity_failed"] = True
     print(json.dumps(out), flush=True)
+    if not parity_ok:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -50,12 +50,13 @@ typedef struct sofa_workspace sofa_workspace;
 typedef struct sofa_radius sofa_radius;
 
 /* ------------------------------------------------------------------------ */
-/* Learned SFA quantisation (Section IV-C; Algorithm 1, MCB).
+/* Learned SFA quantisation (Section IV-E, transformation and learned
+ * quantisation and feature selection; Algorithm 1, MCB).
  *
  * The pool holds the real and imaginary parts of the orthonormal DFT
  * coefficients k = 1..pool (DC omitted: it is zero for z-normalised series,
- * Section IV-D); pool value 2(k-1) is Re X_k, 2(k-1)+1 is Im X_k.  MCB keeps
- * the l pool values of largest variance over the sample (ties: lower pool
+ * Section IV-E, Eq. 1); pool value 2(k-1) is Re X_k, 2(k-1)+1 is Im X_k.
+ * MCB keeps the l pool values of largest variance over the sample (ties: lower pool
  * index first), in decreasing-variance order, and learns alpha-1 breakpoints
  * per kept value: equi-depth beta(a) = v_(floor(a*m/alpha)) of the sorted
  * sample, or equi-width beta(a) = min + a*(max-min)/alpha.  Bins are
@@ -120,12 +121,12 @@ sofa_status sofa_transform(const sofa_bins* bins, const float* d_x, int64_t m,
 double sofa_bins_eta_per_norm(const sofa_bins* bins);
 
 /* ------------------------------------------------------------------------ */
-/* Index (Section IV-E, SOFA index; the MESSI tree of Section IV-A is
+/* Index (Section IV-G, SOFA index; the MESSI tree of Sections IV-A and IV-B is
  * replaced by fixed-size leaves over a sorted flat array).
  *
  * sofa_build SFA-transforms every row, sorts the rows by a key that
  * interleaves the symbols' leading bits (most significant bit first, values
- * in word order, like the iSAX-style refinement of Section IV-A), cuts the
+ * in word order, like the iSAX-style refinement of Section IV-B), cuts the
  * sorted order into leaves of leaf_size rows, and stores per leaf the
  * smallest and largest symbol of each word position (its envelope).  It
  * keeps its own permuted copy of the rows, so d_series may be freed after

@@ -9,13 +9,13 @@ shares no code with the GPU path.
 Functions and the passages they follow (arXiv 2411.17483):
   znorm              Section II, z-normalised Euclidean distance (population sigma)
   dist2              Section II, squared distance, sequential FP64 sum
-  dft_pool           Section IV-D, orthonormal DFT; pool = Re/Im of k = 1..P
+  dft_pool           Section IV-E, orthonormal DFT; pool = Re/Im of k = 1..P
   learn_bins         Algorithm 1 (MCB): stride sample, variance selection,
                      equi-depth or equi-width breakpoints
   words              Algorithm 2 (SFA transform), quantisation into half-open bins
   sfa_lb2            Eq. 2 and Eq. 3 (SFA lower bound, DC term omitted)
   dft_lb2            Eq. 1 (DFT lower bound)
-  knn                Section II similarity search, k-NN extension (Section IV-A);
+  knn                Section II similarity search, k-NN extension (Section IV-C);
                      ranking key (FP64 distance, row id)
   mlp_forward / mlp_backward / adam
                      learned-radius network (not in the paper): FP64 forward,

@@ -60,7 +60,7 @@ double orc_dist2(const float* q, const float* x, int n) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Orthonormal DFT coefficient k of one series (Section IV-D, Eq. 1 context):
+/* Orthonormal DFT coefficient k of one series (Section IV-E, Eq. 1 context):
  * X_k = n^{-1/2} sum_t x_t exp(-2 pi i k t / n).  The angle uses the integer
  * reduction (k*t mod n) so that large k*t products do not lose accuracy.  A
  * direct O(n) sum per coefficient, not an FFT. */
@@ -79,7 +79,7 @@ void orc_dft_coef(const float* x, int n, int k, double* re, double* im) {
 
 /* The candidate pool of one series: real and imaginary parts of the DFT
  * coefficients k = 1..P (the DC term is omitted because it is zero after
- * z-normalisation, Section IV-D).  Pool index 2(k-1) is Re X_k and 2(k-1)+1
+ * z-normalisation, Section IV-E, Eq. 1).  Pool index 2(k-1) is Re X_k and 2(k-1)+1
  * is Im X_k.  out has 2P entries. */
 void orc_dft_pool(const float* x, int n, int P, double* out) {
   for (int k = 1; k <= P; k++) {
@@ -110,7 +110,7 @@ static void orc_msort(double* a, double* tmp, long lo, long hi) {
 }
 
 /* Breakpoints of one Fourier value from its sample (Algorithm 1, step 3;
- * Section IV-C).  alpha symbols give alpha-1 finite breakpoints; the outer
+ * Section IV-E, transformation and learned quantisation).  alpha symbols give alpha-1 finite breakpoints; the outer
  * bins are open to -inf / +inf.
  *  equi-depth (binning 0): beta(a) = v_(floor(a*m/alpha)), the order
  *    statistic of the sorted sample, a = 1..alpha-1.
@@ -132,7 +132,7 @@ void orc_breakpoints(const double* vals, long m, int alpha, int binning, double*
   free(tmp);
 }
 
-/* Variance-based selection (Section IV-C, feature selection; Algorithm 1,
+/* Variance-based selection (Section IV-E, feature selection; Algorithm 1,
  * step 2): population variance of each pool value over the sample, then the
  * l values with the largest variance.  Ties go to the lower pool index.  The
  * word keeps the selected values in decreasing-variance order. */
@@ -187,7 +187,7 @@ void orc_learn_bins(const float* X, long N, int n, long m, int P, int l, int alp
   free(F);
 }
 
-/* Quantisation (Algorithm 2, step 2; Section IV-C bins): the symbol of a
+/* Quantisation (Algorithm 2, step 2; Section IV-E bins): the symbol of a
  * value c for selected value j is the number of finite breakpoints that are
  * <= c, i.e. the index of the half-open bin [beta(a-1), beta(a)) holding c. */
 int orc_symbol(double c, const double* beta_j, int alpha) {
@@ -312,7 +312,7 @@ double orc_dft_lb2(const double* a, const double* b, const double* w, int cnt) {
 
 /* ------------------------------------------------------------------------ */
 /* Exact k-NN by brute force (Section II, similarity search; the k-NN
- * extension of Section IV-A): every series is ranked by the key
+ * extension of Section IV-C): every series is ranked by the key
  * (squared FP64 distance, original row id), ascending, and the first k are
  * returned.  Queries run in parallel; each one scans the collection in row
  * order and keeps a sorted list of its k best keys. */

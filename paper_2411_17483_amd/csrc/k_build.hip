@@ -9,7 +9,7 @@
 // layout.  Quantisation (Algorithm 2, step 2) is fused into the epilogue: a
 // binary search over the FP32 breakpoints held in LDS.
 //
-// Layout: the MESSI tree of Section IV-A is replaced by a flat array sorted
+// Layout: the MESSI tree of Sections IV-A and IV-B is replaced by a flat array sorted
 // by a key that interleaves the leading bits of the symbols (most significant
 // first, positions in word order), cut into fixed-size leaves; each leaf
 // keeps a per-position [min, max] symbol envelope.

@@ -4,7 +4,7 @@
 // of the pool values of each sampled row, population variance of every pool
 // value, the l values of largest variance (ties: lower pool index), then per
 // kept value a sort of its sample and the alpha-1 breakpoints (equi-depth
-// order statistics or equi-width steps, Section IV-C).
+// order statistics or equi-width steps, Section IV-E).
 #include "kernels.h"
 
 #include <cmath>

@@ -1,5 +1,5 @@
 // k_search.hip -- exact k-NN under the GEMINI filter-and-refine scheme with
-// the SFA lower bound (Section II-A; Eq. 2 and Eq. 3; Section IV-A search).
+// the SFA lower bound (Section II-A; Eq. 2 and Eq. 3; Section IV-C search).
 //
 // Per batch of B queries:
 //  1. k_tables   per query: lower-bound table T[j][s] = w_j * mind_j(s, v_j)^2
@@ -13,7 +13,7 @@
 //                down; after the seed, k_leaf_mask turns the codes into a
 //                64-leaf survivor mask per (leaf block, query).
 //  3. k_seed     exact distances to the best leaf's rows (the approximate search
-//                of Section IV-A) give the first best-so-far bound.
+//                of Section IV-C) give the first best-so-far bound.
 //  4. k_refine   persistent kernel over (leaf block, query) items, leaf-block
 //                major so that concurrent queries share the same rows in L2:
 //                table in LDS, word lower bounds (16-byte coalesced loads),

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import mlp_bound
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -767,23 +768,32 @@ def _mlp_data(seed, B, D=32):
 
 
 def test_mlp_forward_matches_oracle(gpu_lib):
+    """Forward pass against the FP64 oracle, element by element, within the
+    FP32 error bound of tests/mlp_bound.py (8 sigma of the rounding-error
+    model, propagated through both layers)."""
     flat = _mlp_params(1)
     m = gpu_lib.RadiusModel(k=10)
     m.set(params=flat, mu=np.zeros(32), sd=np.ones(32), margin=0.0)
     x, _ = _mlp_data(2, 300)
     y = m.forward(_t(x)).cpu().numpy().astype(np.float64)
     ref = oracle.mlp_forward(_unflat(flat), x)
-    assert np.max(np.abs(y - ref) / (1 + np.abs(ref))) < 1e-4
-    # standardisation: (x - mu) / sd applied to the inputs
+    _, bound, _ = mlp_bound.forward_bound(_unflat(flat), x)
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+    # standardisation: (x - mu) / sd applied to the inputs (formed in FP32 on
+    # both sides; the bound allows each input four roundings)
     mu = np.linspace(-1, 1, 32).astype(np.float32)
     sd = np.linspace(0.5, 2, 32).astype(np.float32)
     m.set(mu=mu, sd=sd)
     y2 = m.forward(_t(x)).cpu().numpy().astype(np.float64)
-    ref2 = oracle.mlp_forward(_unflat(flat), ((x - mu) / sd).astype(np.float32))
-    assert np.max(np.abs(y2 - ref2) / (1 + np.abs(ref2))) < 1e-4
+    xs = ((x - mu) / sd).astype(np.float32)
+    ref2 = oracle.mlp_forward(_unflat(flat), xs)
+    _, bound2, _ = mlp_bound.forward_bound(_unflat(flat), xs, xs_rounded=True)
+    assert np.all(np.abs(y2 - ref2) <= bound2), np.max(np.abs(y2 - ref2) / bound2)
 
 
 def test_mlp_gradients_match_oracle(gpu_lib):
+    """Every gradient element and the loss against the FP64 oracle, within
+    the element-wise FP32 error bound of tests/mlp_bound.py."""
     flat = _mlp_params(3)
     m = gpu_lib.RadiusModel(k=10)
     m.set(params=flat, mu=np.zeros(32), sd=np.ones(32))
@@ -791,12 +801,11 @@ def test_mlp_gradients_match_oracle(gpu_lib):
     g, loss = m.gradients(_t(x), _t(t))
     g = g.cpu().numpy().astype(np.float64)
     ref_loss, rg = oracle.mlp_backward(_unflat(flat), x, t)
-    assert abs(float(loss.cpu()[0]) - ref_loss) <= 1e-4 * ref_loss
     ref = np.concatenate([rg["W1"].ravel(), rg["b1"], rg["W2"].ravel(), rg["b2"], rg["W3"], rg["b3"]])
-    bounds = np.cumsum([0, 256 * 32, 256, 256 * 256, 256, 256, 1])
-    for a, b in zip(bounds[:-1], bounds[1:]):
-        scale = np.max(np.abs(ref[a:b]))
-        assert np.max(np.abs(g[a:b] - ref[a:b])) <= 1e-3 * scale + 1e-9, (a, b)
+    _, bound, _, loss_bound = mlp_bound.gradient_bound(_unflat(flat), x, t)
+    assert abs(float(loss.cpu()[0]) - ref_loss) <= loss_bound
+    bad = np.abs(g - ref) > bound
+    assert not bad.any(), (np.flatnonzero(bad)[:10], np.max(np.abs(g - ref) / bound))
 
 
 def test_mlp_adam_steps_match_oracle(gpu_lib):

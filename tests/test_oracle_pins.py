@@ -16,7 +16,7 @@ pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
 
 # --------------------------------------------------------------------------- #
-# DFT (Section IV-D): Parseval, closed forms, numpy.fft special case
+# DFT (Section IV-E, Eq. 1): Parseval, closed forms, numpy.fft special case
 @pytest.mark.parametrize("n", [8, 64, 256, 1024])
 def test_parseval_full_spectrum(n):
     rng = np.random.default_rng(n)
@@ -306,6 +306,53 @@ def test_adam_first_step():
     m, v = np.zeros(50), np.zeros(50)
     oracle.adam(p, g, m, v, 1, lr=1e-3)
     assert np.allclose(p - p0, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+
+
+def test_adam_constant_gradient_many_steps():
+    """Kingma & Ba, Algorithm 1, with the same gradient g at every step: the
+    moments are m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    bias-corrected ratio is g / (|g| + eps) at every t and the parameter moves
+    by the same amount each step.  Resetting the moments between steps, or a
+    wrong power in either correction, makes the steps unequal."""
+    rng = np.random.default_rng(19)
+    g = rng.standard_normal(40) * np.logspace(-6, 2, 40)
+    p = rng.standard_normal(40)
+    p0 = p.copy()
+    m, v = np.zeros(40), np.zeros(40)
+    lr, eps = 2e-3, 1e-8
+    step = -lr * g / (np.abs(g) + eps)
+    for t in range(1, 31):
+        prev = p.copy()
+        oracle.adam(p, g, m, v, t, lr=lr, eps=eps)
+        assert np.allclose(p - prev, step, rtol=1e-9, atol=1e-20), t
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+    assert np.allclose(p - p0, 30 * step, rtol=1e-9, atol=1e-20)
+
+
+def test_adam_two_steps_worked_by_hand():
+    """Kingma & Ba, Algorithm 1, b1 = 0.9, b2 = 0.999, two steps worked by
+    hand with different gradients.
+
+    g1 = 2, g2 = 1:  m2 = 0.9*0.1*2 + 0.1*1 = 0.28, v2 = 0.999*0.001*4 +
+    0.001*1 = 0.004996; the corrections are 1 - 0.9^2 = 0.19 and
+    1 - 0.999^2 = 0.001999, so the second step is
+    -lr * (28/19) / (sqrt(4996/1999) + eps).
+
+    g1 = 1, g2 = -1: m2 = 0.09 - 0.1 = -0.01 and v2 = 0.000999 + 0.001 =
+    0.001999, so m2/0.19 = -1/19 and v2/0.001999 = 1: the second step is
+    +lr / (19 (1 + eps)), against -lr/(1 + eps) for the first."""
+    lr, eps = 1e-3, 1e-8
+    p = np.zeros(2)
+    m, v = np.zeros(2), np.zeros(2)
+    oracle.adam(p, np.array([2.0, 1.0]), m, v, 1, lr=lr, eps=eps)
+    first = p.copy()
+    assert np.allclose(first, [-lr * 2 / (2 + eps), -lr / (1 + eps)], rtol=1e-13, atol=0)
+    oracle.adam(p, np.array([1.0, -1.0]), m, v, 2, lr=lr, eps=eps)
+    assert np.allclose(m, [0.28, -0.01], rtol=1e-12, atol=0)
+    assert np.allclose(v, [0.004996, 0.001999], rtol=1e-12, atol=0)
+    expect = [-lr * (28 / 19) / (np.sqrt(4996 / 1999) + eps), lr / (19 * (1 + eps))]
+    assert np.allclose(p - first, expect, rtol=1e-11, atol=0)
 
 
 # --------------------------------------------------------------------------- #
