@@ -43,6 +43,42 @@ typedef enum {
 /* Thread-local message describing the last non-OK status of this thread. */
 const char* sofa_last_error(void);
 
+/* ------------------------------------------------------------------------ */
+/* Device memory.  By default the library takes device memory with hipMalloc
+ * and returns it with hipFree.  sofa_set_allocator installs the caller's
+ * functions instead (for example backed by PyTorch's caching allocator, so
+ * that one pool owns all device memory); both NULL restore the default.
+ *
+ *  alloc(bytes, stream, ctx) returns device memory of at least `bytes`
+ *    bytes on the current device, aligned to 256 bytes, or NULL (the call
+ *    that needed it then fails with SOFA_ENOMEM).  `stream` is the
+ *    hipStream_t of the call the memory is for, or NULL for memory that
+ *    outlives one call (index arrays, bins, networks).
+ *  free(p, stream, ctx) takes back a pointer that alloc returned, with the
+ *    same stream.  Before calling it the library synchronises that stream
+ *    (the device, for NULL), so no queued kernel still uses the memory.
+ *
+ * Process-wide and thread-safe.  Memory keeps the allocator it came from: a
+ * buffer taken before a change is returned to the functions that gave it.
+ * The functions must stay callable until every object (bins, index,
+ * workspace, network, server) created while they were installed is freed.
+ * They may be called from the serving threads.  Pinned host staging memory
+ * is not routed through them.  SOFA_EINVAL if exactly one of the two
+ * functions is NULL. */
+typedef void* (*sofa_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*sofa_free_fn)(void* p, void* stream, void* ctx);
+sofa_status sofa_set_allocator(sofa_alloc_fn alloc, sofa_free_fn free, void* ctx);
+
+/* z-normalisation (Section II, the z-normalised Euclidean distance): each of
+ * the m rows of d_in (m x n FP32, device) becomes (x - mean) / sd in d_out
+ * (m x n FP32, device; may equal d_in), with the mean and the population
+ * standard deviation sd = sqrt(mean((x - mean)^2)) taken in FP64 and the
+ * quotient formed in FP64 and rounded to FP32 once.  A row with sd = 0 (a
+ * constant row) becomes all zeros.  Non-finite input gives non-finite
+ * output (the build and the search then reject it).  1 <= n <= 2^20.
+ * Asynchronous on `stream`. */
+sofa_status sofa_znormalise(const float* d_in, int64_t m, int32_t n, float* d_out, void* stream);
+
 /* Opaque handles (defined with their entry points below). */
 typedef struct sofa_bins sofa_bins;
 typedef struct sofa_index sofa_index;
@@ -79,6 +115,10 @@ typedef struct {
    * (Algorithm 1); 1 keeps the first l pool values (Re/Im of k = 1, 2, ...),
    * the variant without variance selection of the TLB ablation (Section V-E) */
   int32_t selection;
+  /* sofa_learn_bins only: 0 (default) the rows are z-normalised already;
+   * 1 z-normalises each sampled row on the device first (as
+   * sofa_znormalise), for bins that match an index built with znormalise */
+  int32_t znormalise;
 } sofa_bin_params;
 
 /* Learns bins from the stride sample of m rows of d_series (rows
@@ -142,10 +182,15 @@ typedef struct {
    * positions 0-3, 4-7, 8-15 (positions are in decreasing-variance order),
    * interleaved most significant first; 1 spends 4 bits on every position */
   int32_t key_scheme;
+  /* 0 (default): the rows are z-normalised already and are used as given.
+   * 1: the build z-normalises every row on the device first (as
+   * sofa_znormalise, into a temporary N x n copy, so the build briefly needs
+   * that much more device memory); the index then holds the normalised rows. */
+  int32_t znormalise;
 } sofa_build_params;
 
-/* d_series: N x n FP32 device array (z-normalised; the library does not
- * re-normalise).  Non-finite values give SOFA_EINVAL.  N must be < 2^31.
+/* d_series: N x n FP32 device array, z-normalised (or raw with znormalise
+ * set).  Non-finite values give SOFA_EINVAL.  N must be < 2^31.
  * Synchronous (returns when the index is complete). */
 sofa_status sofa_build(const sofa_bins* bins, const float* d_series, int64_t N, int32_t n,
                        const sofa_build_params* params, void* stream, sofa_index** out);
@@ -242,6 +287,10 @@ typedef struct {
    * hold fewer than k rows).  prune, radii and fallbacks do not apply.  The
    * paper names approximate search as future work (Section VI). */
   int32_t approx_leaves;
+  /* 0 (default): the queries are z-normalised already.  1: each query is
+   * z-normalised on the device first (as sofa_znormalise, into the
+   * workspace); the caller's array is left unchanged. */
+  int32_t znormalise;
 } sofa_knn_params;
 
 /* d_queries: B x n FP32 device array, z-normalised.  1 <= k <= min(N, 100).

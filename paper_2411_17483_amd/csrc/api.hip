@@ -34,22 +34,55 @@ int pad_len(int n) {
   return p;
 }
 
-sofa_status DevBuf::alloc(size_t b) {
+static std::mutex g_alloc_mu;
+static Allocator g_alloc;
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+sofa_status DevBuf::alloc(size_t b, hipStream_t st) {
   release();
   if (b == 0) return SOFA_OK;
-  hipError_t e = hipMalloc(&p, b);
-  if (e != hipSuccess) {
-    p = nullptr;
-    (void)hipGetLastError();
-    return set_error(SOFA_ENOMEM, "device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+  from = current_allocator();
+  stream = st;
+  if (from.alloc) {
+    p = from.alloc(b, (void*)st, from.ctx);
+    if (!p) return set_error(SOFA_ENOMEM, "the caller's allocator returned no memory for %zu bytes", b);
+  } else {
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return set_error(SOFA_ENOMEM, "device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+    }
   }
   bytes = b;
   return SOFA_OK;
 }
 
-sofa_status DevBuf::reserve(size_t b) {
+void DevBuf::release() {
+  if (p) {
+    if (from.free) {
+      // the caller's allocator may hand the memory out again at once: no
+      // queued kernel may still use it (hipFree waits the same way)
+      if (stream) (void)hipStreamSynchronize(stream);
+      else (void)hipDeviceSynchronize();
+      from.free(p, (void*)stream, from.ctx);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+  p = nullptr;
+  bytes = 0;
+  from = Allocator{};
+  stream = nullptr;
+}
+
+sofa_status DevBuf::reserve(size_t b, hipStream_t st) {
   if (b <= bytes) return SOFA_OK;
-  return alloc(b);
+  return alloc(b, st);
 }
 
 static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -70,6 +103,16 @@ using namespace sofa;
 // ============================================================================
 extern "C" const char* sofa_last_error(void) { return g_err.c_str(); }
 
+extern "C" sofa_status sofa_set_allocator(sofa_alloc_fn alloc, sofa_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return set_error(SOFA_EINVAL, "give both an allocation and a release function, or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free = free_fn;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return SOFA_OK;
+}
+
 static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
   if (!p) return set_error(SOFA_EINVAL, "null bin parameters");
   if (p->l < 1 || p->l > kMaxL) return set_error(SOFA_EINVAL, "l=%d outside [1,16]", p->l);
@@ -77,6 +120,7 @@ static sofa_status check_bin_params(int n, const sofa_bin_params* p) {
     return set_error(SOFA_EINVAL, "alpha=%d outside [1,256]", p->alpha);
   if (p->summary != 0 && p->summary != 1) return set_error(SOFA_EINVAL, "summary must be 0 (SFA) or 1 (iSAX)");
   if (p->selection != 0 && p->selection != 1) return set_error(SOFA_EINVAL, "selection must be 0 or 1");
+  if (p->znormalise != 0 && p->znormalise != 1) return set_error(SOFA_EINVAL, "znormalise must be 0 or 1");
   if (p->summary == 1) {
     if (n < 4 || n > kMaxN || (n & 3)) return set_error(SOFA_EINVAL, "n=%d must be a multiple of 4 in [4,%d]", n, kMaxN);
     if (n % p->l) return set_error(SOFA_EINVAL, "iSAX needs l=%d to divide n=%d", p->l, n);
@@ -119,8 +163,21 @@ extern "C" sofa_status sofa_learn_bins(const float* d_series, int64_t N, int32_t
   b->var.assign(2 * b->pool, 0.0);
   b->beta.assign((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 0), 0.0);
   std::vector<double> beta_tmp((size_t)b->l * (b->alpha > 1 ? b->alpha - 1 : 1));
-  sofa_status s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, b->summary,
-                               b->selection, S(stream), b->var.data(), b->sel, beta_tmp.data());
+  // with znormalise, the stride sample is gathered and normalised first; its
+  // own stride sample (all of its rows) is then the same rows
+  DevBuf zs;
+  sofa_status s = SOFA_OK;
+  if (params->znormalise) {
+    s = zs.alloc((size_t)m * n * 4, S(stream));
+    if (s == SOFA_OK) s = launch_znorm(d_series, m, n, zs.as<float>(), S(stream), N);
+    if (s == SOFA_OK) {
+      d_series = zs.as<float>();
+      N = m;
+    }
+  }
+  if (s == SOFA_OK)
+    s = launch_learn(d_series, N, n, m, b->pool, b->l, b->alpha, b->binning, b->summary, b->selection,
+                     S(stream), b->var.data(), b->sel, beta_tmp.data());
   if (s == SOFA_OK) {
     if (b->alpha > 1) std::copy(beta_tmp.begin(), beta_tmp.begin() + b->beta.size(), b->beta.begin());
     s = bins_finish(b, S(stream));
@@ -204,7 +261,7 @@ extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int6
     } else {
       // the projection writes 16-column groups: go through a padded temporary
       DevBuf tmp;
-      SOFA_TRY(tmp.alloc((size_t)m * b->ncol_pool * 4));
+      SOFA_TRY(tmp.alloc((size_t)m * b->ncol_pool * 4, S(stream)));
       SOFA_TRY(launch_project(d_x, m, b->n, b->n, b->d_bt_pool.as<float>(), b->ncol_pool / 16,
                               b->n_pad, tmp.as<float>(), b->ncol_pool, nullptr, 0, nullptr, nullptr,
                               nullptr, S(stream)));
@@ -217,7 +274,7 @@ extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int6
     DevBuf tmpw;
     uint8_t* w = d_words;
     if (!w) {
-      SOFA_TRY(tmpw.alloc((size_t)m * kWordBytes));
+      SOFA_TRY(tmpw.alloc((size_t)m * kWordBytes, S(stream)));
       w = tmpw.as<uint8_t>();
     }
     SOFA_TRY(launch_project(d_x, m, b->n, b->n, b->d_bt_sel.as<float>(), 1, b->n_pad, d_sel, 16,
@@ -225,6 +282,13 @@ extern "C" sofa_status sofa_transform(const sofa_bins* b, const float* d_x, int6
     if (tmpw.p) SOFA_HIP(hipStreamSynchronize(S(stream)));
   }
   return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_znormalise(const float* d_in, int64_t m, int32_t n, float* d_out, void* stream) {
+  if (m < 0 || n < 1 || n > (1 << 20)) return set_error(SOFA_EINVAL, "need m >= 0 and 1 <= n <= 2^20");
+  if (m == 0) return SOFA_OK;
+  if (!d_in || !d_out) return set_error(SOFA_EINVAL, "null array");
+  return launch_znorm(d_in, m, n, d_out, S(stream));
 }
 
 // ============================================================================
@@ -273,10 +337,22 @@ extern "C" sofa_status sofa_build(const sofa_bins* bins, const float* d_series, 
   }
   ix->n_leaves = (N + L - 1) / L;
   ix->n_blocks = (ix->n_leaves + kLeavesPerItem - 1) / kLeavesPerItem;
+  const int zn = params ? params->znormalise : 0;
+  if (zn != 0 && zn != 1) {
+    delete ix;
+    return set_error(SOFA_EINVAL, "znormalise must be 0 or 1");
+  }
+  // with znormalise, every later step reads the normalised copy
+  DevBuf zcopy;
+  if (s == SOFA_OK && zn) {
+    s = zcopy.alloc((size_t)N * n * 4, st);
+    if (s == SOFA_OK) s = launch_znorm(d_series, N, n, zcopy.as<float>(), st);
+    if (s == SOFA_OK) d_series = zcopy.as<float>();
+  }
   DevBuf words_in, norm_in, bad;
-  if (s == SOFA_OK) s = words_in.alloc((size_t)N * kWordBytes);
-  if (s == SOFA_OK) s = norm_in.alloc((size_t)N * 8);
-  if (s == SOFA_OK) s = bad.alloc(4);
+  if (s == SOFA_OK) s = words_in.alloc((size_t)N * kWordBytes, st);
+  if (s == SOFA_OK) s = norm_in.alloc((size_t)N * 8, st);
+  if (s == SOFA_OK) s = bad.alloc(4, st);
   if (s == SOFA_OK && hipMemsetAsync(bad.p, 0, 4, st) != hipSuccess) s = set_error(SOFA_EDEVICE, "memset failed");
   if (s == SOFA_OK)
     s = launch_project(d_series, N, n, n, ix->bins.d_bt_sel.as<float>(), 1, ix->n_pad, nullptr, 16,
@@ -454,7 +530,7 @@ enum {
   // read back by the host after the call: adjacent, one copy
   W_U, W_U0, W_STAT, W_STATS, W_BAD,
   W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_BSUM, W_BOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
-  W_MLP, W_APPROX, W_END
+  W_MLP, W_APPROX, W_QZ, W_END
 };
 
 struct Layout {
@@ -520,6 +596,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_BCTR] = bf ? 64 : 0;
   sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
   sz[W_APPROX] = (p && p->approx_leaves > 0) ? (size_t)B * kApproxMax * 4 : 0;
+  sz[W_QZ] = (p && p->znormalise) ? (size_t)B * ix->n * 4 : 0;
   Layout L;
   static_assert(sizeof(L.off) / sizeof(L.off[0]) == W_END, "one offset per workspace region");
   size_t o = 0;
@@ -562,6 +639,8 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
       return set_error(SOFA_EINVAL, "the radius model takes %d features, the index has %d pool values",
                        m->dims.D, 2 * ix->bins.pool);
   }
+  if (params && params->znormalise != 0 && params->znormalise != 1)
+    return set_error(SOFA_EINVAL, "znormalise must be 0 or 1");
   if (params && (params->approx_leaves < 0 || params->approx_leaves > kApproxMax))
     return set_error(SOFA_EINVAL, "approx_leaves=%d outside [0,%d]", params->approx_leaves, kApproxMax);
   if (params && params->prune != 0) {
@@ -604,9 +683,14 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   if (ws->max_bytes > 0 && (int64_t)lay.total > ws->max_bytes)
     return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay.total,
                      (long long)ws->max_bytes);
-  SOFA_TRY(ws->buf.reserve(lay.total));
+  SOFA_TRY(ws->buf.reserve(lay.total, st));
   char* base = ws->buf.as<char>();
   auto at = [&](int i) { return (void*)(base + lay.off[i]); };
+  if (p && p->znormalise) {
+    // the search, its fall-backs and their copies all read the normalised queries
+    SOFA_TRY(launch_znorm(d_q, B, ix->n, (float*)at(W_QZ), st));
+    d_q = (const float*)at(W_QZ);
+  }
   SearchArgs a{};
   a.X = ix->X.as<float>();
   a.words = ix->words.as<uint8_t>();
@@ -798,7 +882,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     } else if (st_q == 1 || (st_q >= 2 && has_radius)) {
       redo.push_back(q);
     } else if (st_q >= 2) {
-      if (ws->exh.bytes == 0) SOFA_TRY(ws->exh.alloc((size_t)kExhCap * (4 + 8 + 8) + 256));
+      if (ws->exh.bytes == 0) SOFA_TRY(ws->exh.alloc((size_t)kExhCap * (4 + 8 + 8) + 256, st));
       char* eb = ws->exh.as<char>();
       uint32_t* pos = (uint32_t*)eb;
       double* d64 = (double*)(eb + (size_t)kExhCap * 4);
@@ -823,9 +907,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
                       int sampling) -> sofa_status {
     const int64_t R = (int64_t)list.size();
     DevBuf qb, ib, db, rb;
-    SOFA_TRY(qb.alloc((size_t)R * ix->n * 4));
-    SOFA_TRY(ib.alloc((size_t)R * k * 8));
-    SOFA_TRY(db.alloc((size_t)R * k * 4));
+    SOFA_TRY(qb.alloc((size_t)R * ix->n * 4, st));
+    SOFA_TRY(ib.alloc((size_t)R * k * 8, st));
+    SOFA_TRY(db.alloc((size_t)R * k * 4, st));
     for (int64_t i = 0; i < R; i++)
       SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + list[i] * ix->n, (size_t)ix->n * 4,
                               hipMemcpyDeviceToDevice, st));
@@ -834,7 +918,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     p2.prune = prune;
     p2.sampling = sampling;
     if (radii) {
-      SOFA_TRY(rb.alloc((size_t)R * 4));
+      SOFA_TRY(rb.alloc((size_t)R * 4, st));
       SOFA_HIP(hipMemcpyAsync(rb.p, radii, (size_t)R * 4, hipMemcpyHostToDevice, st));
       p2.d_radius = rb.as<float>();
     }
@@ -897,13 +981,13 @@ extern "C" sofa_status sofa_lower_bounds(const sofa_index* ix, const float* d_qu
   if (B == 0) return SOFA_OK;
   hipStream_t st = S(stream);
   DevBuf qp, pool, qn, tab, sq, u0, bad;
-  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
-  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
-  SOFA_TRY(qn.alloc((size_t)B * 8));
-  SOFA_TRY(tab.alloc((size_t)B * kTable * 4));
-  SOFA_TRY(sq.alloc((size_t)B * 16));
-  SOFA_TRY(u0.alloc((size_t)B * 4));
-  SOFA_TRY(bad.alloc(4));
+  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4, st));
+  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4, st));
+  SOFA_TRY(qn.alloc((size_t)B * 8, st));
+  SOFA_TRY(tab.alloc((size_t)B * kTable * 4, st));
+  SOFA_TRY(sq.alloc((size_t)B * 16, st));
+  SOFA_TRY(u0.alloc((size_t)B * 4, st));
+  SOFA_TRY(bad.alloc(4, st));
   SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
   SearchArgs a{};
   a.X = ix->X.as<float>();
@@ -957,28 +1041,28 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   const int64_t G = (B + kGroup - 1) / kGroup;
   DevBuf qp, pool, qn, tab, sq, u0, bad, masks, lcnt, loff, bsum, boff, lslot, sm, sc, perm, qb, qmeta, qscale,
       ctr, U, stats;
-  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4));
-  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4));
-  SOFA_TRY(qn.alloc((size_t)B * 8));
-  SOFA_TRY(tab.alloc((size_t)B * kTable * 4));
-  SOFA_TRY(sq.alloc((size_t)B * 16));
-  SOFA_TRY(u0.alloc((size_t)B * 4));
-  SOFA_TRY(U.alloc((size_t)B * 4));
-  SOFA_TRY(bad.alloc(4));
-  SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8));
-  SOFA_TRY(lcnt.alloc((size_t)ix->n_leaves * 4));
-  SOFA_TRY(loff.alloc((size_t)ix->n_leaves * 8));
-  SOFA_TRY(bsum.alloc((size_t)ix->n_blocks * 4 * 4));  // per 16-leaf sub-block
-  SOFA_TRY(boff.alloc((size_t)ix->n_blocks * 4 * 8));
-  SOFA_TRY(lslot.alloc((size_t)ix->n_leaves * B * 2));
-  SOFA_TRY(sm.alloc((size_t)ix->n_blocks * G * kGroup * 8));
-  SOFA_TRY(sc.alloc((size_t)G * kGroup * 16));
-  SOFA_TRY(perm.alloc((size_t)B * 4));
-  SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2));
-  SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16));
-  SOFA_TRY(qscale.alloc((size_t)G * kGroup * 4));
-  SOFA_TRY(ctr.alloc(64));
-  SOFA_TRY(stats.alloc(64));
+  SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4, st));
+  SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4, st));
+  SOFA_TRY(qn.alloc((size_t)B * 8, st));
+  SOFA_TRY(tab.alloc((size_t)B * kTable * 4, st));
+  SOFA_TRY(sq.alloc((size_t)B * 16, st));
+  SOFA_TRY(u0.alloc((size_t)B * 4, st));
+  SOFA_TRY(U.alloc((size_t)B * 4, st));
+  SOFA_TRY(bad.alloc(4, st));
+  SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8, st));
+  SOFA_TRY(lcnt.alloc((size_t)ix->n_leaves * 4, st));
+  SOFA_TRY(loff.alloc((size_t)ix->n_leaves * 8, st));
+  SOFA_TRY(bsum.alloc((size_t)ix->n_blocks * 4 * 4, st));  // per 16-leaf sub-block
+  SOFA_TRY(boff.alloc((size_t)ix->n_blocks * 4 * 8, st));
+  SOFA_TRY(lslot.alloc((size_t)ix->n_leaves * B * 2, st));
+  SOFA_TRY(sm.alloc((size_t)ix->n_blocks * G * kGroup * 8, st));
+  SOFA_TRY(sc.alloc((size_t)G * kGroup * 16, st));
+  SOFA_TRY(perm.alloc((size_t)B * 4, st));
+  SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2, st));
+  SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16, st));
+  SOFA_TRY(qscale.alloc((size_t)G * kGroup * 4, st));
+  SOFA_TRY(ctr.alloc(64, st));
+  SOFA_TRY(stats.alloc(64, st));
   SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
   SOFA_TRY(launch_fill_u32(stats.as<uint32_t>(), 0u, 16, st));
   SearchArgs a{};

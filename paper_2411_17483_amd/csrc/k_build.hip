@@ -22,6 +22,49 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 static inline unsigned nblk(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
 
 // ----------------------------------------------------------------------------
+// z-normalisation (Section II): per row, the mean and the population standard
+// deviation in FP64 (lane sums over t = lane, lane + 64, ..., then a
+// butterfly across the wave), and (x - mean) / sd formed in FP64 and rounded
+// to FP32 once; sd = 0 gives zeros.  One wave per row; rows are re-read from
+// L2 for the second moment and the output.
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Output row r reads input row r, or with src_rows > m the stride-sample
+// row floor(r * src_rows / m).  in and out may be the same array when
+// src_rows == m (no __restrict__): each element is read and then written by
+// the same lane.
+__global__ __launch_bounds__(256) void k_znorm(const float* in, int64_t m, int n, float* out,
+                                               int64_t src_rows) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < m; r += (int64_t)gridDim.x * 4) {
+    const int64_t src = src_rows > m ? r * src_rows / m : r;
+    const float* x = in + src * n;
+    double s = 0.0;
+    for (int t = lane; t < n; t += 64) s += (double)x[t];
+    const double mu = wave_sum64(s) / (double)n;
+    double q = 0.0;
+    for (int t = lane; t < n; t += 64) {
+      const double d = (double)x[t] - mu;
+      q += d * d;
+    }
+    const double sd = sqrt(wave_sum64(q) / (double)n);
+    float* o = out + r * n;
+    for (int t = lane; t < n; t += 64) o[t] = sd > 0.0 ? (float)(((double)x[t] - mu) / sd) : 0.0f;
+  }
+}
+
+sofa_status launch_znorm(const float* in, int64_t m, int n, float* out, hipStream_t st, int64_t src_rows) {
+  if (m <= 0) return SOFA_OK;
+  k_znorm<<<grid_blocks(m, 4), 256, 0, st>>>(in, m, n, out, src_rows);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+// ----------------------------------------------------------------------------
 // projection
 constexpr int kPrjCh = 128;            // staged columns per chunk
 constexpr int kPrjRow = kPrjCh + 4;    // padded LDS row (floats), keeps 16-byte alignment

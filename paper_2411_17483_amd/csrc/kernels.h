@@ -14,6 +14,12 @@ void isax_breakpoints(int n, int l, int alpha, double* beta);
 // Device tables of a bins object (basis rows, FP32 breakpoints, selection).
 sofa_status launch_bins_tables(sofa_bins* b, hipStream_t st);
 
+// z-normalisation of m rows of n values (k_build.hip); out may equal in.
+// With src_rows > m, output row r is the normalised input row
+// floor(r * src_rows / m) (the stride sample of a src_rows-row array).
+sofa_status launch_znorm(const float* in, int64_t m, int n, float* out, hipStream_t st,
+                         int64_t src_rows = 0);
+
 // MFMA projection (k_build.hip).  out: m x (16*ng) FP32 (nullable);
 // words: m x 16 u8 quantised with beta32 (nullable, requires ng == 1);
 // norm2: m FP64 squared norms (nullable); bad: set to 1 if any value is not finite.

@@ -52,18 +52,27 @@ static inline unsigned grid_blocks(int64_t items, int64_t per_block) {
 // 16 lanes x float4 cover a row in n_pad/64 steps
 int pad_len(int n);
 
+// Device memory comes from hipMalloc, or from the caller's allocator once
+// sofa_set_allocator installed one.  A buffer remembers where its memory came
+// from and returns it there.
+struct Allocator {
+  sofa_alloc_fn alloc = nullptr;  // null: hipMalloc / hipFree
+  sofa_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+Allocator current_allocator();
+
 // device buffer owned by a host object
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Allocator from;                 // where p came from
+  hipStream_t stream = nullptr;   // the stream it was allocated for (may be null)
   ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  sofa_status alloc(size_t b);      // exact size, drops old contents
-  sofa_status reserve(size_t b);    // grows only
+  void release();
+  // exact size, drops old contents; `st` is passed to the caller's allocator
+  sofa_status alloc(size_t b, hipStream_t st = nullptr);
+  sofa_status reserve(size_t b, hipStream_t st = nullptr);  // grows only
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 

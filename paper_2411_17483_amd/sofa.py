@@ -28,7 +28,7 @@ EXPORTED = [
     "sofa_radius_train_step", "sofa_radius_fit", "sofa_radius_forward", "sofa_radius_calibrate",
     "sofa_radius_predict", "sofa_server_create", "sofa_server_add_collection",
     "sofa_server_set_model", "sofa_server_submit", "sofa_server_wait", "sofa_server_get_stats",
-    "sofa_server_free",
+    "sofa_server_free", "sofa_set_allocator", "sofa_znormalise",
 ]
 
 
@@ -40,11 +40,11 @@ class SofaError(RuntimeError):
 
 class BinParams(ctypes.Structure):
     _fields_ = [("l", _i32), ("alpha", _i32), ("pool", _i32), ("binning", _i32), ("summary", _i32),
-                ("selection", _i32)]
+                ("selection", _i32), ("znormalise", _i32)]
 
 
 class BuildParams(ctypes.Structure):
-    _fields_ = [("leaf_size", _i32), ("precision", _i32), ("key_scheme", _i32)]
+    _fields_ = [("leaf_size", _i32), ("precision", _i32), ("key_scheme", _i32), ("znormalise", _i32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -56,7 +56,7 @@ class IndexInfo(ctypes.Structure):
 class KnnParams(ctypes.Structure):
     _fields_ = [("prune", _i32), ("d_radius", _vp), ("radius_model", _vp), ("no_seed_leaf", _i32),
                 ("ws", _vp), ("candidate_capacity", _i32), ("sampling", _i32),
-                ("approx_leaves", _i32)]
+                ("approx_leaves", _i32), ("znormalise", _i32)]
 
 
 class RadiusParams(ctypes.Structure):
@@ -150,6 +150,8 @@ def load():
     L.sofa_radius_forward.argtypes = [_vp, _vp, _i64, _vp, _vp]
     L.sofa_radius_calibrate.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_double, _vp]
     L.sofa_radius_predict.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.sofa_set_allocator.argtypes = [_vp, _vp, _vp]
+    L.sofa_znormalise.argtypes = [_vp, _i64, _i32, _vp, _vp]
     _lib = L
     return L
 
@@ -173,6 +175,66 @@ def _dev(t, dtype=None):
     return _vp(t.data_ptr())
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+_allocator = None
+
+
+class TorchAllocator:
+    """sofa_set_allocator backed by PyTorch's caching allocator: the library's
+    device memory comes from (and goes back to) torch's pool.  Counts the
+    calls and the bytes outstanding."""
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self.allocs = self.frees = 0
+        self.live = {}
+
+        def alloc(nbytes, stream, ctx):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+            except RuntimeError:
+                return None
+            self.allocs += 1
+            self.live[p] = int(nbytes)
+            return p
+
+        def free(p, stream, ctx):
+            self.frees += 1
+            self.live.pop(p, None)
+            torch.cuda.caching_allocator_delete(p)
+
+        self._alloc, self._free = _ALLOC_FN(alloc), _FREE_FN(free)
+
+    @property
+    def live_bytes(self):
+        return sum(self.live.values())
+
+
+def set_allocator(allocator):
+    """Install a TorchAllocator (or None for hipMalloc/hipFree).  The object
+    is kept alive here while installed; buffers taken from it must be freed
+    before it is dropped."""
+    global _allocator
+    if allocator is None:
+        _check(load().sofa_set_allocator(None, None, None))
+    else:
+        _check(load().sofa_set_allocator(ctypes.cast(allocator._alloc, _vp), ctypes.cast(allocator._free, _vp),
+                                         None))
+    _allocator = allocator
+
+
+def znormalise(X, out=None):
+    """Rows of X (m x n FP32 device tensor) z-normalised on the device
+    (sofa_znormalise); out may be X itself."""
+    import torch
+    out = torch.empty_like(X) if out is None else out
+    m, n = X.shape
+    _check(load().sofa_znormalise(_dev(X, torch.float32), m, n, _dev(out, torch.float32), _stream()))
+    return out
+
+
 # --------------------------------------------------------------------------- #
 class Bins:
     """Word quantisation (sofa_learn_bins / sofa_bins_create): learned SFA
@@ -182,12 +244,12 @@ class Bins:
         self._h = _vp(handle)
 
     @classmethod
-    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0, summary=0, selection=0):
+    def learn(cls, X, m, l=16, alpha=256, pool=16, binning=0, summary=0, selection=0, znormalise=0):
         import torch
         L = load()
         N, n = X.shape
         h = _vp()
-        p = BinParams(l, alpha, pool, binning, summary, selection)
+        p = BinParams(l, alpha, pool, binning, summary, selection, int(znormalise))
         _check(L.sofa_learn_bins(_dev(X, torch.float32), N, n, m, ctypes.byref(p), _stream(),
                                  ctypes.byref(h)))
         return cls(h.value)
@@ -262,12 +324,12 @@ class Workspace:
 class Index:
     """A built index (sofa_build) and exact k-NN queries (sofa_knn)."""
 
-    def __init__(self, bins, X, leaf_size=256, precision=0, key_scheme=0):
+    def __init__(self, bins, X, leaf_size=256, precision=0, key_scheme=0, znormalise=0):
         import torch
         L = load()
         N, n = X.shape
         h = _vp()
-        p = BuildParams(leaf_size, precision, key_scheme)
+        p = BuildParams(leaf_size, precision, key_scheme, int(znormalise))
         _check(L.sofa_build(bins._h, _dev(X, torch.float32), N, n, ctypes.byref(p), _stream(),
                             ctypes.byref(h)))
         self._h = h
@@ -290,7 +352,7 @@ class Index:
         return W, ids, env, keys
 
     def knn(self, Q, k, radius=None, prune=0, no_seed_leaf=False, ws=None, candidate_capacity=0,
-            model=None, sampling=0, approx_leaves=0):
+            model=None, sampling=0, approx_leaves=0, znormalise=False):
         """Exact k-NN of the rows of Q: (ids B x k int64, dists B x k float32) device tensors.
         approx_leaves > 0: approximate search over that many leaves per query."""
         import torch
@@ -300,7 +362,7 @@ class Index:
         p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
                       None if model is None else model._h, 1 if no_seed_leaf else 0,
                       None if ws is None else ws._h, int(candidate_capacity), int(sampling),
-                      int(approx_leaves))
+                      int(approx_leaves), 1 if znormalise else 0)
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
         return ids, d
