@@ -237,7 +237,10 @@ void sofa_index_free(sofa_index* index);
  * limit (the serving layer treats that as "not admitted"). */
 /* max_bytes = 0: no limit (grows on demand). */
 sofa_status sofa_workspace_create(int64_t max_bytes, sofa_workspace** out);
-/* Bytes a batch of B queries with k needs on index (no allocation). */
+/* Bytes a batch of B queries with k needs on index (no allocation): the
+ * batch's regions and its fall-back buffers (the copies of re-searched
+ * queries and the exhaustive pass's lists), which are reserved with it so
+ * that a fall-back never allocates. */
 sofa_status sofa_workspace_bytes_for(const sofa_index* index, int64_t B, int32_t k,
                                      int32_t prune, int64_t* bytes);
 void sofa_workspace_free(sofa_workspace* ws);
@@ -462,10 +465,14 @@ sofa_status sofa_fp8_lower_bounds(const sofa_index* index, const float* d_querie
  * thread, so their kernels overlap on the device.  A free slot takes, among
  * the collections with fewer than per_collection batches in flight, the
  * queue whose oldest request is oldest overall, up to max_batch of its
- * requests, and admits the batch only if its workspace bytes
- * (sofa_workspace_bytes_for) fit in memory_budget beside the batches in
- * flight: otherwise it halves the batch, then waits for memory to free.  A
- * query that alone exceeds the budget fails with SOFA_ENOMEM.  Requests
+ * requests, and admits the batch only if the server's device memory stays
+ * within memory_budget: the slots' staging buffers, plus per slot what its
+ * workspace holds (a workspace keeps the capacity of its largest batch,
+ * fall-back buffers included; a running slot is charged the larger of that
+ * and its batch's bytes, sofa_workspace_bytes_for with the batch's radius
+ * model).  When a batch does not fit, the idle slots free their workspaces;
+ * then the batch is halved; then it waits for memory to free.  A query that
+ * alone exceeds the budget fails with SOFA_ENOMEM.  Requests
  * that arrive while batches run join the next batch of their collection.
  * A batch runs at the largest k of its requests and each request keeps its
  * first k results, which are exactly its own k nearest (the ranking is the
@@ -479,16 +486,15 @@ typedef struct sofa_server sofa_server;
 typedef struct {
   int32_t slots;         /* concurrent batches (default 4, at most 16) */
   int32_t max_batch;     /* queries per batch (default 256) */
-  int64_t memory_budget; /* device bytes for the workspaces of the batches in
-                          * flight (default 8 GiB); each slot's workspace
-                          * keeps the capacity of its largest batch */
+  int64_t memory_budget; /* device bytes of the server: staging buffers and
+                          * the slots' workspaces (default 8 GiB) */
   int32_t per_collection; /* batches of one collection in flight (default 1) */
 } sofa_server_params;
 
 typedef struct {
   int64_t submitted, completed, batches;
   int64_t max_batch;             /* largest batch run */
-  int64_t in_flight_bytes_peak;  /* largest sum of admitted workspace bytes */
+  int64_t in_flight_bytes_peak;  /* largest device bytes charged to the server */
   int64_t memory_waits;          /* batches halved or delayed for memory */
   double busy_ms;                /* summed wall time of the batches */
 } sofa_server_stats;

@@ -80,6 +80,19 @@ void DevBuf::release() {
   stream = nullptr;
 }
 
+void DevBuf::take(DevBuf& o) {
+  if (&o == this) return;
+  release();
+  p = o.p;
+  bytes = o.bytes;
+  from = o.from;
+  stream = o.stream;
+  o.p = nullptr;
+  o.bytes = 0;
+  o.from = Allocator{};
+  o.stream = nullptr;
+}
+
 sofa_status DevBuf::reserve(size_t b, hipStream_t st) {
   if (b <= bytes) return SOFA_OK;
   return alloc(b, st);
@@ -460,8 +473,8 @@ static_assert(sizeof(kPassesMany) / sizeof(int) <= kMaxPasses, "event slots");
 
 struct sofa_workspace {
   int64_t max_bytes = 0;
-  DevBuf buf;
-  DevBuf exh;
+  DevBuf buf;  // the regions of one batch (layout_for)
+  DevBuf aux;  // its fall-back buffers (aux_layout_for), reserved with it
   std::mutex mu;
   sofa_knn_stats stats{};
   hipEvent_t ev[7 + 3 * kMaxPasses] = {};
@@ -608,24 +621,89 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   return L;
 }
 
+// Fall-back buffers of a batch of B queries, reserved with the batch so
+// that no fall-back allocates: the exhaustive pass's lists, and the copies
+// (queries, ids, distances, radii) of the re-searches.  A re-search takes a
+// subset of its caller's queries and nests at most twice (a dropped-candidate
+// retry with a radius whose query then misses the radius), so two slices
+// sized for the top-level batch cover every level.
+constexpr int kResearchDepth = 2;
+struct AuxLayout {
+  size_t exh, research[kResearchDepth], total;
+};
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t research_slice_bytes(const sofa_index* ix, int64_t B, int k) {
+  return align256((size_t)B * ix->n * 4) + align256((size_t)B * k * 8) + align256((size_t)B * k * 4) +
+         align256((size_t)B * 4);
+}
+AuxLayout aux_layout_for(const sofa_index* ix, int64_t B, int k) {
+  AuxLayout A;
+  A.exh = 0;
+  size_t o = align256((size_t)kExhCap * (4 + 8 + 8) + 256);
+  for (int d = 0; d < kResearchDepth; d++) {
+    A.research[d] = o;
+    o += research_slice_bytes(ix, B, k);
+  }
+  A.total = o;
+  return A;
+}
+
 }  // namespace
+
+namespace sofa {
+int64_t knn_workspace_bytes(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
+  return (int64_t)(layout_for(ix, B, k, p).total + aux_layout_for(ix, B, k).total);
+}
+int64_t workspace_held_bytes(sofa_workspace* ws) {
+  return ws ? (int64_t)(ws->buf.bytes + ws->aux.bytes) : 0;
+}
+bool workspace_trim(sofa_workspace* ws) {
+  if (!ws) return true;
+  std::unique_lock<std::mutex> lk(ws->mu, std::try_to_lock);
+  if (!lk.owns_lock()) return false;  // a call is using it
+  ws->buf.release();
+  ws->aux.release();
+  return true;
+}
+}  // namespace sofa
 
 extern "C" sofa_status sofa_workspace_bytes_for(const sofa_index* ix, int64_t B, int32_t k, int32_t prune,
                                                 int64_t* bytes) {
   if (!ix || !bytes || B < 0 || k < 1) return set_error(SOFA_EINVAL, "bad arguments");
   sofa_knn_params p{};
   p.prune = prune;
-  *bytes = (int64_t)layout_for(ix, B, k, &p).total;
+  *bytes = knn_workspace_bytes(ix, B, k, &p);
   return SOFA_OK;
 }
 
+// Where one sofa_knn call keeps its data: the batch's regions (base, at
+// least layout_for bytes of the top-level batch), its fall-back buffers (aux,
+// aux_layout_for), host memory for the read-back after the search, and the
+// stage timers (nullable).
+struct KnnMem {
+  char* base = nullptr;
+  size_t base_bytes = 0;
+  char* aux = nullptr;
+  uint8_t* hback = nullptr;
+  size_t hback_bytes = 0;
+  hipEvent_t* ev = nullptr;
+};
+
+// bytes the host reads back after a batch of B queries: the bounds, radii,
+// statuses and counters, adjacent in the layout
+static size_t readback_bytes(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p) {
+  const Layout lay = layout_for(ix, B, k, p);
+  return lay.off[W_BAD] + 4 - lay.off[W_U];
+}
+
+// B0: the top-level batch, which sizes the fall-back slices of every depth
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
-                            sofa_workspace* ws, sofa_knn_stats& stats, int depth = 0);
+                            const KnnMem& mem, sofa_knn_stats& stats, int64_t B0, int depth = 0);
 
-extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
-                                const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
-                                void* stream) {
+// argument checks of sofa_knn
+static sofa_status check_knn_args(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
+                                  const sofa_knn_params* params, int64_t* d_ids, float* d_dists) {
   if (!ix) return set_error(SOFA_EINVAL, "null index");
   if (B < 0 || B > 65535) return set_error(SOFA_EINVAL, "B=%lld outside [0, 65535]", (long long)B);
   if (k < 1 || k > kMaxK || k > ix->N)
@@ -650,6 +728,14 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
     if (params->prune == 1 && !ix->has_bf16) return set_error(SOFA_EINVAL, "the index was built without the BF16 copy");
     if (params->prune == 2 && !ix->has_fp8) return set_error(SOFA_EINVAL, "the index was built without the FP8 copy");
   }
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
+                                const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
+                                void* stream) {
+  SOFA_TRY(check_knn_args(ix, d_queries, B, k, params, d_ids, d_dists));
+  if (B == 0) return SOFA_OK;
   sofa_workspace* ws = params ? params->ws : nullptr;
   if (!ws) {
     sofa_index* mix = const_cast<sofa_index*>(ix);
@@ -658,12 +744,27 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
   }
   std::unique_lock<std::mutex> lk(ws->mu, std::try_to_lock);
   if (!lk.owns_lock()) return set_error(SOFA_EBUSY, "workspace in use by another call");
+  const size_t lay_bytes = layout_for(ix, B, k, params).total;
+  const size_t aux_bytes = aux_layout_for(ix, B, k).total;
+  if (ws->max_bytes > 0 && (int64_t)(lay_bytes + aux_bytes) > ws->max_bytes)
+    return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay_bytes + aux_bytes,
+                     (long long)ws->max_bytes);
+  SOFA_TRY(ws->buf.reserve(lay_bytes, S(stream)));
+  SOFA_TRY(ws->aux.reserve(aux_bytes, S(stream)));
+  KnnMem mem;
+  mem.base = ws->buf.as<char>();
+  mem.base_bytes = ws->buf.bytes;
+  mem.aux = ws->aux.as<char>();
+  mem.hback_bytes = readback_bytes(ix, B, k, params);
+  mem.hback = ws->host_back(mem.hback_bytes);
+  if (!mem.hback) return set_error(SOFA_ENOMEM, "pinned host buffer of %zu bytes", mem.hback_bytes);
+  mem.ev = ws->events();
   hipEvent_t e0, e1;
   SOFA_HIP(hipEventCreate(&e0));
   SOFA_HIP(hipEventCreate(&e1));
   SOFA_HIP(hipEventRecord(e0, S(stream)));
   sofa_knn_stats stats{};
-  sofa_status s = knn_impl(ix, d_queries, B, k, params, d_ids, d_dists, S(stream), ws, stats);
+  sofa_status s = knn_impl(ix, d_queries, B, k, params, d_ids, d_dists, S(stream), mem, stats, B);
   (void)hipEventRecord(e1, S(stream));
   (void)hipEventSynchronize(e1);
   float ms = 0;
@@ -678,13 +779,15 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
 
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
-                            sofa_workspace* ws, sofa_knn_stats& stats, int depth) {
+                            const KnnMem& mem, sofa_knn_stats& stats, int64_t B0, int depth) {
   const Layout lay = layout_for(ix, B, k, p);
-  if (ws->max_bytes > 0 && (int64_t)lay.total > ws->max_bytes)
-    return set_error(SOFA_ENOMEM, "batch needs %zu workspace bytes, limit %lld", lay.total,
-                     (long long)ws->max_bytes);
-  SOFA_TRY(ws->buf.reserve(lay.total, st));
-  char* base = ws->buf.as<char>();
+  const AuxLayout aux = aux_layout_for(ix, B0, k);
+  // a re-search takes a subset of its caller's queries, which never needs
+  // more than the top-level batch reserved
+  if (lay.total > mem.base_bytes || depth > kResearchDepth)
+    return set_error(SOFA_EINTERNAL, "search at depth %d needs %zu workspace bytes, %zu reserved", depth,
+                     lay.total, mem.base_bytes);
+  char* base = mem.base;
   auto at = [&](int i) { return (void*)(base + lay.off[i]); };
   if (p && p->znormalise) {
     // the search, its fall-backs and their copies all read the normalised queries
@@ -734,7 +837,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   unsigned* bad = (unsigned*)at(W_BAD);
   SOFA_TRY(launch_fill_u32(bad, 0u, 1, st));
   SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 16, st));
-  hipEvent_t* ev = ws->events();
+  hipEvent_t* ev = mem.ev;
   if (ev) (void)hipEventRecord(ev[0], st);
   // approximate search: no radius, prune or fallback applies
   const int approx = p ? p->approx_leaves : 0;
@@ -822,8 +925,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   }
   // the bounds, statuses and counters in one copy to pinned memory
   const size_t back0 = lay.off[W_U], back1 = lay.off[W_BAD] + 4;
-  uint8_t* hb = ws->host_back(back1 - back0);
-  if (!hb) return set_error(SOFA_ENOMEM, "pinned host buffer of %zu bytes", back1 - back0);
+  uint8_t* hb = mem.hback;
+  if (back1 - back0 > mem.hback_bytes)
+    return set_error(SOFA_EINTERNAL, "read-back of %zu bytes, %zu reserved", back1 - back0, mem.hback_bytes);
   SOFA_HIP(hipMemcpyAsync(hb, base + back0, back1 - back0, hipMemcpyDeviceToHost, st));
   SOFA_HIP(hipStreamSynchronize(st));
   const int32_t* hst = reinterpret_cast<const int32_t*>(hb + (lay.off[W_STAT] - back0));
@@ -882,8 +986,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     } else if (st_q == 1 || (st_q >= 2 && has_radius)) {
       redo.push_back(q);
     } else if (st_q >= 2) {
-      if (ws->exh.bytes == 0) SOFA_TRY(ws->exh.alloc((size_t)kExhCap * (4 + 8 + 8) + 256, st));
-      char* eb = ws->exh.as<char>();
+      char* eb = mem.aux + aux.exh;
       uint32_t* pos = (uint32_t*)eb;
       double* d64 = (double*)(eb + (size_t)kExhCap * 4);
       int64_t* id = (int64_t*)(eb + (size_t)kExhCap * 12);
@@ -906,30 +1009,33 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   auto research = [&](const std::vector<int64_t>& list, const float* radii, int prune,
                       int sampling) -> sofa_status {
     const int64_t R = (int64_t)list.size();
-    DevBuf qb, ib, db, rb;
-    SOFA_TRY(qb.alloc((size_t)R * ix->n * 4, st));
-    SOFA_TRY(ib.alloc((size_t)R * k * 8, st));
-    SOFA_TRY(db.alloc((size_t)R * k * 4, st));
+    if (depth >= kResearchDepth || R > B0)
+      return set_error(SOFA_EINTERNAL, "re-search of %lld queries at depth %d", (long long)R, depth + 1);
+    // this depth's slice of the fall-back buffers, sized for B0 >= R queries
+    char* rs = mem.aux + aux.research[depth];
+    float* qcopy = (float*)rs;
+    rs += align256((size_t)B0 * ix->n * 4);
+    int64_t* rids = (int64_t*)rs;
+    rs += align256((size_t)B0 * k * 8);
+    float* rd = (float*)rs;
+    rs += align256((size_t)B0 * k * 4);
+    float* rr = (float*)rs;
     for (int64_t i = 0; i < R; i++)
-      SOFA_HIP(hipMemcpyAsync(qb.as<float>() + i * ix->n, d_q + list[i] * ix->n, (size_t)ix->n * 4,
+      SOFA_HIP(hipMemcpyAsync(qcopy + i * ix->n, d_q + list[i] * ix->n, (size_t)ix->n * 4,
                               hipMemcpyDeviceToDevice, st));
     sofa_knn_params p2{};
     if (p) p2.candidate_capacity = p->candidate_capacity;
     p2.prune = prune;
     p2.sampling = sampling;
     if (radii) {
-      SOFA_TRY(rb.alloc((size_t)R * 4, st));
-      SOFA_HIP(hipMemcpyAsync(rb.p, radii, (size_t)R * 4, hipMemcpyHostToDevice, st));
-      p2.d_radius = rb.as<float>();
+      SOFA_HIP(hipMemcpyAsync(rr, radii, (size_t)R * 4, hipMemcpyHostToDevice, st));
+      p2.d_radius = rr;
     }
     sofa_knn_stats s2{};
-    SOFA_TRY(knn_impl(ix, qb.as<float>(), R, k, &p2, ib.as<int64_t>(), db.as<float>(), st, ws, s2,
-                      depth + 1));
+    SOFA_TRY(knn_impl(ix, qcopy, R, k, &p2, rids, rd, st, mem, s2, B0, depth + 1));
     for (int64_t i = 0; i < R; i++) {
-      SOFA_HIP(hipMemcpyAsync(d_ids + list[i] * k, ib.as<int64_t>() + i * k, (size_t)k * 8,
-                              hipMemcpyDeviceToDevice, st));
-      SOFA_HIP(hipMemcpyAsync(d_d + list[i] * k, db.as<float>() + i * k, (size_t)k * 4,
-                              hipMemcpyDeviceToDevice, st));
+      SOFA_HIP(hipMemcpyAsync(d_ids + list[i] * k, rids + i * k, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
+      SOFA_HIP(hipMemcpyAsync(d_d + list[i] * k, rd + i * k, (size_t)k * 4, hipMemcpyDeviceToDevice, st));
     }
     SOFA_HIP(hipStreamSynchronize(st));
     stats.leaves_visited += s2.leaves_visited;

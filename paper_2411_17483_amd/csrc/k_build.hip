@@ -433,11 +433,7 @@ sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_i
   memcpy(&mn2, &bits, 8);
   ix->max_norm = sqrt(mn2);
   // keep the sorted keys for inspection
-  ix->keys.release();
-  ix->keys.p = k0.p;
-  ix->keys.bytes = k0.bytes;
-  k0.p = nullptr;
-  k0.bytes = 0;
+  ix->keys.take(k0);
   return SOFA_OK;
 }
 

@@ -8,8 +8,13 @@
 // Whenever a slot is free it takes, among the collections with fewer than
 // `per_collection` batches in flight, the queue whose oldest request is the
 // oldest overall, up to max_batch requests of it, and admits the batch only
-// if its workspace bytes fit beside the batches already in flight (halving
-// the batch, then waiting for memory to free up).  Requests that arrive
+// if the device memory of the server stays within its budget (halving the
+// batch, then waiting for memory to free up).  That memory is the slots'
+// staging buffers plus, per slot, what its workspace holds: a workspace keeps
+// the capacity of its largest batch (its fall-back buffers included), so a
+// running slot is charged the larger of that and its batch's bytes, and an
+// idle one what it holds.  When a batch does not fit, the idle slots give
+// their workspaces back first.  Requests that arrive
 // while batches run join the next batch of their collection: batching is
 // continuous, not a queue in front of one batch at a time.  A batch of a
 // large collection costs about one pass over its rows whatever its size, so
@@ -73,6 +78,10 @@ struct sofa_server {
     int64_t* hids = nullptr;
     float* hd = nullptr;
     std::thread th;
+    // guarded by the server's mutex
+    bool running = false;
+    int64_t held = 0;  // workspace bytes kept after the last batch
+    int64_t need = 0;  // bytes of the batch running
   };
 
   int device = 0;
@@ -88,13 +97,29 @@ struct sofa_server {
   std::map<int, int> busy;                  // batches in flight per collection
   std::unordered_map<int64_t, Req*> reqs;
   int64_t next_ticket = 1;
-  int64_t in_flight_bytes = 0;
+  int64_t fixed_bytes = 0;  // staging buffers of the slots
   bool stop = false;
   bool started = false;
   sofa_server_stats stats{};
 
   void worker(int si);
   void start();
+  // device bytes charged to slot t (mutex held)
+  int64_t charge(int t) const {
+    const Slot& x = slots[t];
+    return x.running ? std::max(x.held, x.need) : x.held;
+  }
+  int64_t charged_except(int si) const {
+    int64_t c = fixed_bytes;
+    for (int t = 0; t < (int)slots.size(); t++)
+      if (t != si) c += charge(t);
+    return c;
+  }
+  bool any_running() const {
+    for (const Slot& x : slots)
+      if (x.running) return true;
+    return false;
+  }
 };
 
 void sofa_server::start() {
@@ -135,11 +160,31 @@ void sofa_server::worker(int si) {
       return km;
     };
     int k = kmax(b);
+    // the parameters the batch runs with (the network's scratch is part of
+    // its bytes)
+    auto params_for = [&](int kk) {
+      sofa_knn_params q{};
+      q.prune = c.prune;
+      auto m = c.models.find(kk);
+      if (m != c.models.end()) q.radius_model = m->second;
+      return q;
+    };
     int64_t need = 0;
     bool admitted = false;
     for (;;) {
-      if (sofa_workspace_bytes_for(c.ix, b, k, c.prune, &need) != SOFA_OK) need = budget + 1;
-      if (in_flight_bytes + need <= budget) {
+      const sofa_knn_params pq = params_for(k);
+      need = knn_workspace_bytes(c.ix, b, k, &pq);
+      int64_t others = charged_except(si);
+      if (others + std::max(sl.held, need) > budget) {
+        // the idle slots give back what they keep from earlier batches
+        for (int t = 0; t < (int)slots.size(); t++)
+          if (t != si && !slots[t].running && slots[t].held > 0 && workspace_trim(slots[t].ws))
+            slots[t].held = 0;
+        others = charged_except(si);
+        // this slot's own larger buffer from an earlier batch
+        if (sl.held > need && others + sl.held > budget && workspace_trim(sl.ws)) sl.held = 0;
+      }
+      if (others + std::max(sl.held, need) <= budget) {
         admitted = true;
         break;
       }
@@ -152,7 +197,7 @@ void sofa_server::worker(int si) {
       break;
     }
     if (!admitted) {
-      if (in_flight_bytes == 0) {
+      if (!any_running()) {
         // one query alone exceeds the budget: fail it instead of waiting forever
         Req* r = best->second.front();
         best->second.pop_front();
@@ -173,11 +218,12 @@ void sofa_server::worker(int si) {
     std::vector<Req*> batch(best->second.begin(), best->second.begin() + b);
     best->second.erase(best->second.begin(), best->second.begin() + b);
     if (best->second.empty()) pending.erase(best);
-    in_flight_bytes += need;
+    sl.running = true;
+    sl.need = need;
     busy[ci]++;
     stats.batches++;
     stats.max_batch = std::max<int64_t>(stats.max_batch, b);
-    stats.in_flight_bytes_peak = std::max(stats.in_flight_bytes_peak, in_flight_bytes);
+    stats.in_flight_bytes_peak = std::max(stats.in_flight_bytes_peak, charged_except(si) + charge(si));
     const double t0 = now_ms();
     for (Req* r : batch) {
       r->t_start = t0;
@@ -191,11 +237,8 @@ void sofa_server::worker(int si) {
     sofa_status st = SOFA_OK;
     if (hipMemcpyAsync(sl.dq.p, sl.hq, (size_t)b * n * 4, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
       st = set_error(SOFA_EDEVICE, "query upload failed");
-    sofa_knn_params p{};
-    p.prune = c.prune;
+    sofa_knn_params p = params_for(k);
     p.ws = sl.ws;
-    auto m = c.models.find(k);
-    if (m != c.models.end()) p.radius_model = m->second;
     if (st == SOFA_OK)
       st = sofa_knn(c.ix, sl.dq.as<float>(), b, k, &p, sl.dids.as<int64_t>(), sl.dd.as<float>(), sl.stream);
     if (st == SOFA_OK &&
@@ -219,7 +262,8 @@ void sofa_server::worker(int si) {
       r->t_done = t1;
       r->done = true;
     }
-    in_flight_bytes -= need;
+    sl.running = false;
+    sl.held = workspace_held_bytes(sl.ws);
     busy[ci]--;
     stats.completed += b;
     stats.busy_ms += t1 - t0;
@@ -252,6 +296,7 @@ extern "C" sofa_status sofa_server_create(const sofa_server_params* params, sofa
     if (st == SOFA_OK) st = sl.dq.alloc((size_t)max_batch * kServeMaxN * 4);
     if (st == SOFA_OK) st = sl.dids.alloc((size_t)max_batch * kMaxK * 8);
     if (st == SOFA_OK) st = sl.dd.alloc((size_t)max_batch * kMaxK * 4);
+    s->fixed_bytes += (int64_t)(sl.dq.bytes + sl.dids.bytes + sl.dd.bytes);
     if (st == SOFA_OK && (hipHostMalloc((void**)&sl.hq, (size_t)max_batch * kServeMaxN * 4) != hipSuccess ||
                           hipHostMalloc((void**)&sl.hids, (size_t)max_batch * kMaxK * 8) != hipSuccess ||
                           hipHostMalloc((void**)&sl.hd, (size_t)max_batch * kMaxK * 4) != hipSuccess))

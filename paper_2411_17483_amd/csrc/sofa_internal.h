@@ -68,13 +68,31 @@ struct DevBuf {
   size_t bytes = 0;
   Allocator from;                 // where p came from
   hipStream_t stream = nullptr;   // the stream it was allocated for (may be null)
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;  // one owner per allocation
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { take(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    take(o);
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release();
+  // takes o's memory (and where it came from); o is left empty
+  void take(DevBuf& o);
   // exact size, drops old contents; `st` is passed to the caller's allocator
   sofa_status alloc(size_t b, hipStream_t st = nullptr);
   sofa_status reserve(size_t b, hipStream_t st = nullptr);  // grows only
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
+
+// Device bytes a sofa_knn batch takes in its workspace: the batch's regions
+// and its reserved fall-back buffers (params as given to sofa_knn).
+int64_t knn_workspace_bytes(const sofa_index* ix, int64_t B, int k, const sofa_knn_params* p);
+// bytes a workspace holds now (it keeps the capacity of its largest batch)
+int64_t workspace_held_bytes(sofa_workspace* ws);
+// frees what the workspace holds; false (nothing freed) while a call uses it
+bool workspace_trim(sofa_workspace* ws);
 
 }  // namespace sofa
 

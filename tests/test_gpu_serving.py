@@ -106,6 +106,58 @@ def test_serving_memory_admission(gpu_lib):
     srv.close()
 
 
+def test_serving_device_memory_within_budget(gpu_lib):
+    """The server's real device memory (hipMemGetInfo, sampled while a
+    mixed-k stream of requests runs) stays within its budget: the staging
+    buffers and every slot's workspace, which keeps the capacity of its
+    largest batch and its reserved fall-back buffers, are charged, and idle
+    slots give their memory back when a batch needs it."""
+    import threading
+    import torch
+    colls = _collections(gpu_lib)[:1]
+    ix = colls[0]["ix"]
+    many = ix.workspace_bytes(32, 100, prune=1)
+    # room for one and a half of the largest batches: four slots that each
+    # kept their largest workspace would need 4x that
+    budget = int(1.5 * many)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    low = [free0]
+    done = threading.Event()
+
+    def sample():
+        while not done.is_set():
+            low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+
+    srv = gpu_lib.Server(slots=4, max_batch=32, memory_budget=budget)
+    cid = srv.add_collection(ix, 1)
+    Q = colls[0]["Q"]
+    rng = np.random.default_rng(91)
+    ks = [int(rng.choice([1, 10, 100])) for _ in range(96)]
+    th = threading.Thread(target=sample)
+    th.start()
+    try:
+        tickets = [srv.submit(cid, Q[j % Q.shape[0]], k) for j, k in enumerate(ks)]
+        res = [srv.wait(t, k) for t, k in zip(tickets, ks)]
+        low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+    finally:
+        done.set()
+        th.join()
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(ks)
+    assert st["in_flight_bytes_peak"] <= budget
+    # allocation granularity: at most 2 MiB per buffer (5 per slot)
+    slack = 4 * 5 * (2 << 20)
+    assert free0 - low[0] <= budget + slack, (free0 - low[0], budget)
+    for k in (1, 10, 100):
+        sel = [j for j, kk in enumerate(ks) if kk == k]
+        ref_ids, _ = oracle.knn(colls[0]["X"], Q[[j % Q.shape[0] for j in sel]], k)
+        for row, j in enumerate(sel):
+            assert np.array_equal(res[j][0], ref_ids[row]), (k, j)
+
+
 def test_serving_argument_errors(gpu_lib):
     colls = _collections(gpu_lib)[:1]
     srv = gpu_lib.Server(slots=1, max_batch=4)
