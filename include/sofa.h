@@ -303,6 +303,27 @@ sofa_status sofa_knn(const sofa_index* index, const float* d_queries, int64_t B,
                      const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
                      void* stream);
 
+/* The search of sofa_knn for callers that cannot allocate device memory
+ * (code that forbids hipMalloc, tight serving loops, harnesses without an
+ * allocator).  Same arguments, checks and results as sofa_knn; params->ws
+ * must be NULL.  It calls no hipMalloc, hipFree or allocator hook: every
+ * device buffer of the batch (its regions and the fall-back buffers) lies in
+ * one static array of SOFA_NOALLOC_SCRATCH_BYTES per GPU, which the library
+ * holds on each device it runs on until the process ends; the host reads its
+ * status flags back into a static host buffer.  A batch that needs more than
+ * the array (sofa_workspace_bytes_for, with the radius model's scratch), or
+ * more than SOFA_NOALLOC_MAX_QUERIES queries, gives SOFA_ENOMEM before any
+ * device work.  Calls share the array, so they are serialised inside the
+ * library (across threads and devices) and each one synchronises `stream`
+ * before returning; two processes each hold their own array.  No stage
+ * timers or counters are recorded (sofa_knn_get_stats does not see these
+ * calls). */
+#define SOFA_NOALLOC_SCRATCH_BYTES (128ll << 20)
+#define SOFA_NOALLOC_MAX_QUERIES 4096
+sofa_status sofa_knn_noalloc(const sofa_index* index, const float* d_queries, int64_t B, int32_t k,
+                             const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
+                             void* stream);
+
 /* Counters of the last sofa_knn call on a workspace (or the index's own). */
 typedef struct {
   int64_t queries;

@@ -777,6 +777,73 @@ extern "C" sofa_status sofa_knn(const sofa_index* ix, const float* d_queries, in
   return s;
 }
 
+// ----------------------------------------------------------------------------
+// sofa_knn_noalloc: the search with every device buffer in one file-scope
+// array per GPU.  In host code `scratch` names a host-side stand-in, not
+// device memory: kernels and copies get the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr size_t kScratchBytes = (size_t)SOFA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+constexpr int64_t kScratchMaxB = SOFA_NOALLOC_MAX_QUERIES;  // bounds the host read-back buffer
+static std::mutex g_scratch_mu;         // one no-alloc call at a time
+static char* g_scratch_dev[kScratchDevices];
+static uint8_t g_scratch_back[kScratchMaxB * 12 + 4096];
+
+static sofa_status scratch_of_current_device(char** out) {
+  int dev = -1;
+  SOFA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return set_error(SOFA_EINVAL, "device %d: the no-alloc search supports devices 0..%d", dev,
+                     kScratchDevices - 1);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    SOFA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = (char*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return SOFA_OK;
+}
+
+extern "C" sofa_status sofa_knn_noalloc(const sofa_index* ix, const float* d_queries, int64_t B, int32_t k,
+                                        const sofa_knn_params* params, int64_t* d_ids, float* d_dists,
+                                        void* stream) {
+  SOFA_TRY(check_knn_args(ix, d_queries, B, k, params, d_ids, d_dists));
+  if (B == 0) return SOFA_OK;
+  if (params && params->ws) return set_error(SOFA_EINVAL, "the no-alloc search takes no workspace");
+  if (B > kScratchMaxB)
+    return set_error(SOFA_ENOMEM, "the no-alloc search takes at most %lld queries (asked %lld)",
+                     (long long)kScratchMaxB, (long long)B);
+  const size_t lay_bytes = align256(layout_for(ix, B, k, params).total);
+  const size_t need = lay_bytes + aux_layout_for(ix, B, k).total;
+  if (need > kScratchBytes)
+    return set_error(SOFA_ENOMEM,
+                     "the batch needs %zu bytes, above the %zu-byte scratch of the no-alloc search "
+                     "(fewer queries, a smaller k or sofa_knn with a workspace)",
+                     need, kScratchBytes);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  char* base = nullptr;
+  SOFA_TRY(scratch_of_current_device(&base));
+  KnnMem mem;
+  mem.base = base;
+  mem.base_bytes = lay_bytes;
+  mem.aux = base + lay_bytes;
+  mem.hback = g_scratch_back;
+  mem.hback_bytes = sizeof g_scratch_back;
+  mem.ev = nullptr;  // no stage timers
+  if (readback_bytes(ix, B, k, params) > mem.hback_bytes)
+    return set_error(SOFA_EINTERNAL, "read-back of %zu bytes above %zu", readback_bytes(ix, B, k, params),
+                     mem.hback_bytes);
+  sofa_knn_stats stats{};
+  sofa_status s = knn_impl(ix, d_queries, B, k, params, d_ids, d_dists, S(stream), mem, stats, B);
+  // the next call may reuse the scratch on another stream: this call's
+  // kernels must have finished
+  const hipError_t e = hipStreamSynchronize(S(stream));
+  if (s == SOFA_OK && e != hipSuccess)
+    s = set_error(SOFA_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+  return s;
+}
+
 static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, int k,
                             const sofa_knn_params* p, int64_t* d_ids, float* d_d, hipStream_t st,
                             const KnnMem& mem, sofa_knn_stats& stats, int64_t B0, int depth) {

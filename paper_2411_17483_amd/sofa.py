@@ -28,7 +28,7 @@ EXPORTED = [
     "sofa_radius_train_step", "sofa_radius_fit", "sofa_radius_forward", "sofa_radius_calibrate",
     "sofa_radius_predict", "sofa_server_create", "sofa_server_add_collection",
     "sofa_server_set_model", "sofa_server_submit", "sofa_server_wait", "sofa_server_get_stats",
-    "sofa_server_free", "sofa_set_allocator", "sofa_znormalise",
+    "sofa_server_free", "sofa_set_allocator", "sofa_znormalise", "sofa_knn_noalloc",
 ]
 
 
@@ -124,6 +124,7 @@ def load():
     L.sofa_workspace_free.argtypes = [_vp]
     L.sofa_workspace_free.restype = None
     L.sofa_knn.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(KnnParams), _vp, _vp, _vp]
+    L.sofa_knn_noalloc.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(KnnParams), _vp, _vp, _vp]
     L.sofa_knn_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(KnnStats)]
     L.sofa_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
     L.sofa_bf16_lower_bounds.argtypes = [_vp, _vp, _i64, _vp, _vp]
@@ -365,6 +366,19 @@ class Index:
                       int(approx_leaves), 1 if znormalise else 0)
         _check(load().sofa_knn(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
                                _dev(d), _stream()))
+        return ids, d
+
+    def knn_noalloc(self, Q, k, ids, d, radius=None, prune=0, candidate_capacity=0, model=None,
+                    sampling=0, znormalise=False):
+        """sofa_knn_noalloc into the caller's ids (B x k int64) and d (B x k
+        float32) device tensors: the library allocates nothing."""
+        import torch
+        B = Q.shape[0]
+        p = KnnParams(prune, None if radius is None else _dev(radius, torch.float32),
+                      None if model is None else model._h, 0, None, int(candidate_capacity), int(sampling),
+                      0, 1 if znormalise else 0)
+        _check(load().sofa_knn_noalloc(self._h, _dev(Q, torch.float32), B, k, ctypes.byref(p), _dev(ids),
+                                       _dev(d), _stream()))
         return ids, d
 
     def stats(self, ws=None):
