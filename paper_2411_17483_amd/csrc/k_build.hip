@@ -220,9 +220,11 @@ __global__ void k_keys(const uint8_t* __restrict__ words, int64_t N, int l, int 
 constexpr int kRsItems = 16;
 constexpr int kRsTile = 256 * kRsItems;
 
+// per tile, the count of each digit (hist[digit][tile]); dsum[digit]
+// accumulates the digit's total over the tiles (cleared beforehand)
 __global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t N,
                                                  int shift, uint32_t* __restrict__ hist,
-                                                 int64_t ntiles) {
+                                                 int64_t ntiles, uint32_t* __restrict__ dsum) {
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -232,29 +234,64 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* __restrict__ ke
     if (i < N) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+  const uint32_t c = cnt[threadIdx.x];
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = c;
+  if (c) atomicAdd(dsum + threadIdx.x, c);
 }
 
-// exclusive scan of h[0..M) in one block (M = 256 * ntiles < 2^31)
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ h, int64_t M) {
-  __shared__ uint32_t part[1024];
-  int64_t per = (M + 1023) / 1024;
-  int64_t b = threadIdx.x * per, e = b + per < M ? b + per : M;
-  uint32_t s = 0;
-  for (int64_t i = b; i < e; i++) s += h[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+// exclusive scan of hist in digit-major order, one workgroup per digit:
+// the digit's start is the sum of the totals of the smaller digits, then
+// its row of ntiles counts is scanned in pieces of 1024 x kScanPer
+constexpr int kScanPer = 4;
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ hist, int64_t ntiles,
+                                                  const uint32_t* __restrict__ dsum) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t start;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int d = blockIdx.x;
+  if (w == 0) {
+    // sum of dsum[0..d), at most four values per lane
+    uint32_t v = 0;
+    for (int i = lane; i < d; i += 64) v += dsum[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) start = v;
   }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (int64_t i = b; i < e; i++) {
-    uint32_t v = h[i];
-    h[i] = run;
-    run += v;
+  __syncthreads();
+  uint32_t carry = start;
+  uint32_t* row = hist + (int64_t)d * ntiles;
+  for (int64_t p0 = 0; p0 < ntiles; p0 += 1024 * kScanPer) {
+    uint32_t v[kScanPer], s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; e++) {
+      const int64_t i = p0 + (int64_t)t * kScanPer + e;
+      v[e] = i < ntiles ? row[i] : 0u;
+      s += v[e];
+    }
+    uint32_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t x = wsum[i];
+      wpre += i < w ? x : 0u;
+      tot += x;
+    }
+    uint32_t ex = carry + wpre + incl - s;
+#pragma unroll
+    for (int e = 0; e < kScanPer; e++) {
+      const int64_t i = p0 + (int64_t)t * kScanPer + e;
+      if (i < ntiles) row[i] = ex;
+      ex += v[e];
+    }
+    carry += tot;
+    __syncthreads();  // wsum is rewritten by the next piece
   }
 }
 
@@ -393,21 +430,24 @@ sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_i
                           const double* norm2_in, hipStream_t st) {
   const int64_t N = ix->N;
   const int n = ix->n, n_pad = ix->n_pad;
-  DevBuf k0, k1, v0, v1, hist, mx;
+  DevBuf k0, k1, v0, v1, hist, dsum, mx;
   SOFA_TRY(k0.alloc(8 * N));
   SOFA_TRY(k1.alloc(8 * N));
   SOFA_TRY(v0.alloc(4 * N));
   SOFA_TRY(v1.alloc(4 * N));
   const int64_t ntiles = (N + kRsTile - 1) / kRsTile;
   SOFA_TRY(hist.alloc(4 * 256 * ntiles));
+  SOFA_TRY(dsum.alloc(4 * 256 * 8));  // digit totals of each of the 8 passes
   SOFA_TRY(mx.alloc(8));
+  SOFA_TRY(launch_fill_u32(dsum.as<uint32_t>(), 0u, 256 * 8, st));
   k_keys<<<nblk(N, 256), 256, 0, st>>>(words_in, N, ix->bins.l, ix->bins.alpha, ix->key_scheme,
                                        k0.as<uint64_t>(), v0.as<uint32_t>());
   uint64_t *ka = k0.as<uint64_t>(), *kb = k1.as<uint64_t>();
   uint32_t *va = v0.as<uint32_t>(), *vb = v1.as<uint32_t>();
   for (int shift = 0; shift < 64; shift += 8) {
-    k_rs_hist<<<(unsigned)ntiles, 256, 0, st>>>(ka, N, shift, hist.as<uint32_t>(), ntiles);
-    k_rs_scan<<<1, 1024, 0, st>>>(hist.as<uint32_t>(), 256 * ntiles);
+    uint32_t* ds = dsum.as<uint32_t>() + 256 * (shift / 8);
+    k_rs_hist<<<(unsigned)ntiles, 256, 0, st>>>(ka, N, shift, hist.as<uint32_t>(), ntiles, ds);
+    k_rs_scan<<<256, 1024, 0, st>>>(hist.as<uint32_t>(), ntiles, ds);
     k_rs_scatter<<<(unsigned)ntiles, 256, 0, st>>>(ka, va, kb, vb, N, shift, hist.as<uint32_t>(), ntiles);
     uint64_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;

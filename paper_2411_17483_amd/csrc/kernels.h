@@ -44,6 +44,9 @@ __host__ __device__ inline uint64_t sfa_key(const uint32_t (&s8)[16], int scheme
   return key;
 }
 
+// p[0..n) = v on stream st (k_search.hip)
+sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
 // Index layout (k_build.hip): sort by the interleaved key, permute, envelopes.
 sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_in,
                           const double* norm2_in, hipStream_t st);

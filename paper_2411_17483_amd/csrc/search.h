@@ -56,7 +56,6 @@ constexpr int kApproxMax = 64;
 sofa_status launch_approx(const SearchArgs& a, int M, int32_t* leaves, hipStream_t st, hipEvent_t* ev);
 sofa_status launch_finalize(const SearchArgs& a, int64_t* out_ids, float* out_d, int32_t* status,
                             hipStream_t st, hipEvent_t* ev);
-sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 sofa_status launch_all_lb(const SearchArgs& a, float* d_lb, hipStream_t st);
 sofa_status launch_exhaustive(const SearchArgs& a, int q, uint32_t* pos, uint32_t* cnt,
                               uint32_t cap, double* d, int64_t* id, int64_t* out_ids, float* out_d,
