@@ -5,7 +5,9 @@ without variance selection, against iSAX, for alphabet sizes 4..256, l = 16)
 and of its sampling study (Section V-C: the fraction of the collection the
 bins are learned from).
 
-For each collection kind (rw, hf, mix; N x n, z-normalised, own seed) and
+For each collection kind (rw, hf, band, mix; N x n, z-normalised, own seed;
+band: eight sinusoids of 4 to 16 cycles per series, which the 16-value
+Fourier word holds and 16-sample segment means average away) and
 each variant and alphabet size it reports:
   - TLB: the mean over (query, row) pairs of the word lower bound over the
     Euclidean distance (16 noisy-copy queries x 20,000 random rows; the bound
@@ -52,7 +54,7 @@ def main():
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--alphas", default="4,8,16,32,64,128,256")
-    ap.add_argument("--kinds", default="rw,hf,mix")
+    ap.add_argument("--kinds", default="rw,hf,band,mix")
     ap.add_argument("--rates", default="0.001,0.005,0.01,0.05,0.1,0.2")
     ap.add_argument("--leaves", default="64,128,256,512,1024,2048,4096")
     ap.add_argument("--build-N", type=int, default=10_000_000)

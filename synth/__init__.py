@@ -16,8 +16,8 @@ _SRC = os.path.join(_HERE, "synth.c")
 _LIB = os.path.join(_HERE, "libsynth.so")
 _lib = None
 
-RW, HF, MIX = 0, 1, 2
-KINDS = {"rw": RW, "hf": HF, "mix": MIX}
+RW, HF, MIX, BAND = 0, 1, 2, 3
+KINDS = {"rw": RW, "hf": HF, "mix": MIX, "band": BAND}
 
 
 def build():

@@ -17,6 +17,9 @@
  *   high frequency (HF): x_t = sum_{i=1..8} sin(2 pi f_i t / n + phi_i) + e_t,
  *       f_i ~ U(0, n/2) cycles per series, phi_i ~ U(0, 2 pi), e ~ N(0, 0.5^2)
  *   mix: row i is RW when i is even, HF when i is odd.
+ *   band-limited high frequency (BAND): as HF with f_i ~ U(4, 16) cycles per
+ *       series, energy that a 16-value Fourier word holds but that segment
+ *       means of 16 samples (n = 256) largely average away.
  * Queries: source row j ~ U{0..N-1}; q = znorm(x_j + N(0, sigma^2)).
  */
 #include <math.h>
@@ -125,14 +128,16 @@ static void syn_rw_row(uint64_t seed, uint64_t row, int n, double* buf, float* o
   syn_znorm_store(buf, n, out);
 }
 
-static void syn_hf_row(uint64_t seed, uint64_t row, int n, double* buf, float* out) {
+/* f_i ~ U(f_lo, f_hi) cycles per series */
+static void syn_sines_row(uint64_t seed, uint64_t row, int n, double f_lo, double f_hi, double* buf,
+                          float* out) {
   syn_stream sp = syn_make_stream(seed, 2u, row); /* frequencies and phases */
   syn_stream sn = syn_make_stream(seed, 3u, row); /* additive noise */
   syn_normals(&sn, n, buf);
   for (int t = 0; t < n; t++) buf[t] *= 0.5;
   for (int i = 0; i < 8; i++) {
     syn_u4 r = syn_block(&sp, (uint32_t)i);
-    double f = syn_u01(r.v[0], r.v[1]) * (0.5 * n);
+    double f = f_lo + syn_u01(r.v[0], r.v[1]) * (f_hi - f_lo);
     double ph = syn_u01(r.v[2], r.v[3]) * 2.0 * SYN_PI;
     double w = 2.0 * SYN_PI * f / n;
     /* sin(w t + ph) by the angle-addition recurrence, re-anchored with a
@@ -154,7 +159,16 @@ static void syn_hf_row(uint64_t seed, uint64_t row, int n, double* buf, float* o
   syn_znorm_store(buf, n, out);
 }
 
-/* kind: 0 = random walk, 1 = high frequency, 2 = mix (even rows RW, odd HF).
+static void syn_hf_row(uint64_t seed, uint64_t row, int n, double* buf, float* out) {
+  syn_sines_row(seed, row, n, 0.0, 0.5 * n, buf, out);
+}
+
+static void syn_band_row(uint64_t seed, uint64_t row, int n, double* buf, float* out) {
+  syn_sines_row(seed, row, n, 4.0, 16.0, buf, out);
+}
+
+/* kind: 0 = random walk, 1 = high frequency, 2 = mix (even rows RW, odd HF),
+ * 3 = band-limited high frequency.
  * Writes rows [row0, row0+rows) of the collection into out (rows x n). */
 void syn_generate(float* out, long long row0, long long rows, int n, int kind,
                   unsigned long long seed, int nthreads) {
@@ -170,7 +184,9 @@ void syn_generate(float* out, long long row0, long long rows, int n, int kind,
     for (long long r = 0; r < rows; r++) {
       uint64_t row = (uint64_t)(row0 + r);
       int hf = (kind == 1) || (kind == 2 && (row & 1));
-      if (hf)
+      if (kind == 3)
+        syn_band_row(seed, row, n, buf, out + (size_t)r * n);
+      else if (hf)
         syn_hf_row(seed, row, n, buf, out + (size_t)r * n);
       else
         syn_rw_row(seed, row, n, buf, out + (size_t)r * n);

@@ -103,17 +103,18 @@ def test_isax_knn_matches_oracle(gpu_lib, k):
 def test_sfa_prunes_more_than_isax(gpu_lib):
     """The paper's comparison on synthetic data: with the same word length
     and alphabet, the same leaves and the same scan, the series each summary
-    leaves to the exact distance.  On random walks SFA leaves fewer.  On the
+    leaves to the exact distance.  On random walks SFA leaves fewer, and on
+    band-limited series (4 to 16 cycles) far fewer.  On the
     high-frequency recipe (8 sinusoids with frequencies up to n/2) neither
     summary prunes at k = 10: the energy lies above both the 16 segment means
     and the k <= 16 DFT pool, and the distances concentrate."""
     N, n, B, k = 40000, 256, 48, 10
     res = {}
-    for kind in ("rw", "hf", "mix"):
+    for kind in ("rw", "hf", "band", "mix"):
         X = synth.collection(N, n, kind, seed=51)
         Q, _ = synth.queries(X, B, sigma=0.1, seed=52)
-        for summary in (0, 1):
-            bins = gpu_lib.Bins.learn(_t(X), 4000, summary=summary)
+        for summary, kw in ((0, {}), (1, {}), (2, dict(selection=1))):
+            bins = gpu_lib.Bins.learn(_t(X), 4000, summary=min(summary, 1), **kw)
             ix = gpu_lib.Index(bins, _t(X), leaf_size=256)
             ix.knn(_t(Q), k)
             st = ix.stats()
@@ -121,3 +122,8 @@ def test_sfa_prunes_more_than_isax(gpu_lib):
     print(res)
     assert res[("rw", 0)][0] < res[("rw", 1)][0], res
     assert res[("hf", 0)][0] == res[("hf", 1)][0] == N * B, res
+    # band-limited series (4 to 16 cycles): the Fourier word holds their
+    # energy, 16-sample segment means average most of it away, and the
+    # variance selection keeps the band instead of the first pool values
+    assert res[("band", 0)][0] < res[("band", 1)][0], res
+    assert res[("band", 0)][0] < res[("band", 2)][0], res
