@@ -8,7 +8,11 @@ carry one noisy-copy query (sigma 0.1) of a uniformly chosen collection with
 k uniform in {1, 10, 100}; arrivals are Poisson at a fixed offered rate.  For
 each rate the run reports the achieved queries/s and the p50/p99 latency
 from submission to result (measured by the server's own clock), plus the
-batch sizes the loop formed.  A subset of requests is also answered one at
+batch sizes the loop formed and the HBM roofline fraction: the bytes the
+batches' searches had to read (the server's hbm_bytes: each prune-copy chunk
+with a non-empty query list once per pass, plus every exactly refined row)
+over the level's wall time, against the 8 TB/s peak, and the same bytes over
+the summed batch times (the rate of one batch while it runs).  A subset of requests is also answered one at
 a time and checked to be identical to its answers in the mix.
 
 Prints one JSON line.  `--scale` shrinks every collection (e.g. 0.05 for a
@@ -26,6 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+
+PEAK_HBM = 8.0e12  # B/s, MI355X published HBM3E bandwidth
 
 
 def log(*a):
@@ -74,6 +81,7 @@ def run_level(srv, cids, pools, qps, duration, seed, ks=(1, 10, 100)):
             results[i] = srv.wait(tickets[i], int(kk[i]))
 
     th = threading.Thread(target=waiter)
+    st0 = srv.stats()
     th.start()
     t_start = time.perf_counter()
     t_next = t_start
@@ -87,6 +95,9 @@ def run_level(srv, cids, pools, qps, duration, seed, ks=(1, 10, 100)):
         ready.release()
     th.join()
     wall = time.perf_counter() - t_start
+    st1 = srv.stats()
+    dbytes = st1["hbm_bytes"] - st0["hbm_bytes"]
+    dbusy = (st1["busy_ms"] - st0["busy_ms"]) * 1e-3
     lat = np.array([r[2][0] for r in results])
     queue = np.array([r[2][1] for r in results])
     batch = np.array([r[2][2] for r in results])
@@ -100,6 +111,9 @@ def run_level(srv, cids, pools, qps, duration, seed, ks=(1, 10, 100)):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "queue_p50_ms": float(np.percentile(queue, 50)),
             "mean_batch": float(np.mean(batch)), "max_batch": int(np.max(batch)),
+            "hbm_bytes": dbytes, "hbm_gb_per_s": dbytes / wall / 1e9,
+            "hbm_frac": dbytes / wall / PEAK_HBM,
+            "hbm_frac_while_busy": dbytes / dbusy / PEAK_HBM if dbusy > 0 else None,
             "per_k": per_k, "per_collection": per_c}
 
 
@@ -155,7 +169,8 @@ def main():
         res = run_level(srv, cids, pools, qps, args.duration, seed=int(qps))
         levels.append(res)
         log(f"offered {qps:.0f} q/s: achieved {res['achieved_qps']:.0f} q/s, p50 {res['p50_ms']:.2f} ms, "
-            f"p99 {res['p99_ms']:.2f} ms, mean batch {res['mean_batch']:.1f}")
+            f"p99 {res['p99_ms']:.2f} ms, mean batch {res['mean_batch']:.1f}, HBM {res['hbm_gb_per_s']:.0f} GB/s "
+            f"({res['hbm_frac']:.3f} of peak; {res['hbm_frac_while_busy'] or 0:.3f} per busy slot-second)")
     st = srv.stats()
     srv.close()
     out = {"metric": "serving p50/p99 latency and queries/s, 3 HBM-resident collections, "

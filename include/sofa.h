@@ -276,7 +276,7 @@ typedef struct {
    * by an exhaustive pass, so results stay exact. */
   int32_t candidate_capacity;
   /* BF16/FP8 prune only: 0 (default) and 1 run the 256-row chunks in passes
-   * of decreasing stride (1024, 32, 1 for k <= 3; 1024, 128, 16, 2, 1 from
+   * of decreasing stride (1024, 32, 1 for k <= 3; 2048, 256, 32, 4, 1 from
    * k = 4 on), each selecting candidates with the bound the earlier passes
    * established, with the (query, leaf) lists rebuilt from that bound before
    * the last passes; 2 runs one pass over all chunks (best when the radius
@@ -361,6 +361,10 @@ typedef struct {
   int64_t series_bf16_needed;
   /* launches of the batched-distance tile kernel (one per sampled pass) */
   int64_t prune_passes;
+  /* rows of the BF16/FP8 copy the tile kernel streamed from memory: each
+   * 256-row chunk with a non-empty query list, once per pass (times 2 n_pad
+   * bytes for BF16, n_pad for FP8, these are the bytes it must read) */
+  int64_t prune_rows_streamed;
 } sofa_knn_stats;
 
 /* Copies the counters of the last call on ws (or, with ws NULL, on the
@@ -518,8 +522,16 @@ typedef struct {
   int64_t in_flight_bytes_peak;  /* largest device bytes charged to the server */
   int64_t memory_waits;          /* batches halved or delayed for memory */
   double busy_ms;                /* summed wall time of the batches */
+  /* algorithmic HBM bytes of the batches' searches on the prune tiers: the
+   * prune-copy rows each search streamed (prune_rows_streamed of
+   * sofa_knn_stats times the row's bytes) plus 4 n_pad bytes for every row
+   * it refined exactly (series_refined) */
+  double hbm_bytes;
 } sofa_server_stats;
 
+/* Creates a server with the given parameters (NULL: defaults) and starts no
+ * thread until the first request.  SOFA_EINVAL for slots above 16 or
+ * max_batch above 65535; SOFA_ENOMEM if the staging buffers cannot be had. */
 sofa_status sofa_server_create(const sofa_server_params* params, sofa_server** out);
 /* Registers an index; prune as in sofa_knn_params (the index must hold the
  * copy).  n <= 1024.  *out_id is the collection id used by submit. */

@@ -466,7 +466,7 @@ extern "C" sofa_status sofa_index_export(const sofa_index* ix, uint8_t* d_words,
 // two more passes from k = 4 on (10M x 256: k = 10 refines 0.9M instead of
 // 1.6M rows), not at k = 1, where each pass costs more than it saves.
 constexpr int kPassesFew[] = {1024, 32, 1};
-constexpr int kPassesMany[] = {1024, 128, 16, 2, 1};
+constexpr int kPassesMany[] = {2048, 256, 32, 4, 1};
 constexpr int kManyFromK = 4;
 constexpr int kMaxPasses = 8;
 static_assert(sizeof(kPassesMany) / sizeof(int) <= kMaxPasses, "event slots");
@@ -1028,6 +1028,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   stats.series_refined += (int64_t)hstats[2];
   stats.series_bf16_checked += (int64_t)hstats[3];
   stats.series_bf16_needed += (int64_t)hstats[5];
+  stats.prune_rows_streamed += (int64_t)hstats[6];
   stats.prune_passes += bf_passes;
   stats.max_candidates = std::max<int64_t>(stats.max_candidates, (int64_t)hstats[4]);
   for (int64_t q = 0; q < B; q++) {
@@ -1110,6 +1111,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     stats.series_refined += s2.series_refined;
     stats.series_bf16_checked += s2.series_bf16_checked;
     stats.series_bf16_needed += s2.series_bf16_needed;
+    stats.prune_rows_streamed += s2.prune_rows_streamed;
     stats.prune_passes += s2.prune_passes;
     stats.overflow_fallbacks += s2.overflow_fallbacks;
     stats.overflow_evicted += s2.overflow_evicted;

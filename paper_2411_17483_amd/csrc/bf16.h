@@ -34,6 +34,7 @@ struct Bf16Args {
   int64_t chunk_first, chunk_stride, n_items;  // 256-row chunks of this pass
   int skip;                 // > 0: the pass enumerates the chunks that are not multiples of skip
   int64_t chunk_mult;       // chunk = chunk_mult * (enumerated index)
+  int slices;               // work items per chunk, each taking a share of its query groups
   float* dump;              // inspection only: B x N lower bounds of every pair (no pruning)
 };
 

@@ -87,33 +87,6 @@ __device__ __forceinline__ uint4 fp8_pack16(const float* __restrict__ p, float i
 }
 
 // ----------------------------------------------------------------------------
-// build: swizzled BF16 copy.  Thread i writes the 8 values of fragment slot
-// i = ((rb*KS + ks)*64 + lane): rows rb*32 + lane%32, columns ks*16 + 8*(lane/32) + e.
-__global__ void k_bf16_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
-                            uint4* __restrict__ xb) {
-  const int KS = n_pad / 16;
-  const int64_t total = nrb * KS * 64;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-  const int lane = (int)(i % 64);
-  const int64_t t = i / 64;
-  const int ks = (int)(t % KS);
-  const int64_t rb = t / KS;
-  const int64_t row = rb * 32 + lane % 32;
-  const int k0 = ks * 16 + 8 * (lane / 32);
-  uint32_t w[4] = {0, 0, 0, 0};
-  if (row < N) {
-    float4 a = *reinterpret_cast<const float4*>(X + row * n_pad + k0);
-    float4 b = *reinterpret_cast<const float4*>(X + row * n_pad + k0 + 4);
-    w[0] = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
-    w[1] = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
-    w[2] = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
-    w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
-  }
-  xb[i] = make_uint4(w[0], w[1], w[2], w[3]);
-  }
-}
-
 // per row: |x|^2 rounded down, r_x = |x - xh| up, |xh| up (one wave per row)
 __device__ __forceinline__ void norms_of(const float* __restrict__ row, int n_pad, int lane,
                                          float4& out) {
@@ -165,13 +138,45 @@ __device__ __forceinline__ void norms_of_fp8(const float* __restrict__ row, int 
                     __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
 }
 
-__global__ __launch_bounds__(256) void k_bf16_meta(const float* __restrict__ X, int64_t N, int n_pad,
-                                                   float4* __restrict__ meta) {
+// build: the swizzled BF16 copy and its per-row terms in one read of X.
+// Fragment slot ((rb*KS + ks)*64 + lane) holds the 8 values of row
+// rb*32 + lane%32, columns ks*16 + 8*(lane/32) + e.  One wave per 32-row
+// block writes the block's fragments and sums each row's terms over its
+// half of the columns in FP64; the two halves meet by one exchange.
+__global__ __launch_bounds__(256) void k_bf16_copy_meta(const float* __restrict__ X, int64_t N, int n_pad,
+                                                        int64_t nrb, uint4* __restrict__ xb,
+                                                        float4* __restrict__ meta) {
+  const int KS = n_pad / 16;
   const int lane = threadIdx.x & 63;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < N; row += (int64_t)gridDim.x * 4) {
-    float4 m;
-    norms_of(X + row * n_pad, n_pad, lane, m);
-    if (lane == 0) meta[row] = m;
+  for (int64_t rb = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); rb < nrb; rb += (int64_t)gridDim.x * 4) {
+    const int64_t row = rb * 32 + lane % 32;
+    const bool live = row < N;
+    double s2 = 0.0, r2 = 0.0, h2 = 0.0;
+    for (int ks = 0; ks < KS; ks++) {
+      const int k0 = ks * 16 + 8 * (lane / 32);
+      uint32_t w[4] = {0, 0, 0, 0};
+      if (live) {
+        const float4 a = *reinterpret_cast<const float4*>(X + row * n_pad + k0);
+        const float4 b = *reinterpret_cast<const float4*>(X + row * n_pad + k0 + 4);
+        const float xs[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+          const uint32_t h = bf16_bits(xs[e]);
+          w[e / 2] |= h << (16 * (e & 1));
+          const double x = xs[e], hv = bf16_val(h);
+          s2 += x * x;
+          r2 += (x - hv) * (x - hv);
+          h2 += hv * hv;
+        }
+      }
+      xb[(rb * KS + ks) * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    s2 += __shfl_xor(s2, 32);
+    r2 += __shfl_xor(r2, 32);
+    h2 += __shfl_xor(h2, 32);
+    if (lane < 32 && live)
+      meta[row] = make_float4(__double2float_rd(s2 * (1.0 - 1e-12)), __double2float_ru(sqrt(r2) * (1.0 + 1e-12)),
+                              __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
   }
 }
 
@@ -643,15 +648,18 @@ constexpr int group_units() { return 2 * KS * 64 * TileTraits<PREC>::kHalves; }
 // LDS DMA of a group's B fragments into dst, gathered from the query rows:
 // piece p (64 lanes x 16 B, a quarter of the pieces per wave) is column
 // block cb, K step ks (and half hh for FP8); lane l reads the 16 contiguous
-// bytes of its column's row that the instruction's operand layout puts there
+// bytes of its column's row that the instruction's operand layout puts there.
+// The gathers are buffer loads (qr: the query rows of every slot) rather
+// than global ones: while a global load to LDS is in flight the compiler
+// makes every LDS read wait for all earlier ones (it may be an LDS access of
+// either kind), which would serialise the B reads of the MFMA loop.
 template <int PREC, int KS>
-__device__ __forceinline__ void stage_group(const Bf16Args& b, const GroupSlots& gs, int wave, int lane,
-                                            u4v* dst) {
+__device__ __forceinline__ void stage_group(const GroupSlots& gs, int wave, int lane,
+                                            __amdgpu_buffer_rsrc_t qr, u4v* dst) {
   constexpr int H = TileTraits<PREC>::kHalves;
   constexpr int kPieces = 2 * KS * H;
-  constexpr int64_t kRowUnits = PREC == 1 ? 2 * KS : 4 * KS;  // u4v per query row
+  constexpr int kRowUnits = PREC == 1 ? 2 * KS : 4 * KS;  // u4v per query row
   static_assert(kPieces % 4 == 0, "whole pieces per wave");
-  const u4v* rows = reinterpret_cast<const u4v*>(b.qb);
 #pragma unroll
   for (int i = 0; i < kPieces / 4; i++) {
     const int piece = wave + 4 * i;
@@ -659,9 +667,8 @@ __device__ __forceinline__ void stage_group(const Bf16Args& b, const GroupSlots&
     const int ks = rem / H, hh = rem % H;
     const int slot = cb ? gs.s1 : gs.s0;
     const int u = PREC == 1 ? 2 * ks + (lane >> 5) : 4 * ks + 2 * (lane >> 5) + hh;
-    __builtin_amdgcn_global_load_lds((const void*)(rows + (int64_t)slot * kRowUnits + u),
-                                     (__attribute__((address_space(3))) void*)(dst + piece * 64),
-                                     16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(qr, (__attribute__((address_space(3))) void*)(dst + piece * 64), 16,
+                                             (slot * kRowUnits + u) * 16, 0, 0, 0);
   }
 }
 
@@ -741,11 +748,12 @@ __device__ __forceinline__ void col_epilogue(const SearchArgs& a, const Bf16Args
   }
 }
 
-// chunk of work item it; skip > 0 enumerates the chunks that are not
-// multiples of skip
+// chunk of work item it (slices consecutive items share a chunk); skip > 0
+// enumerates the chunks that are not multiples of skip
 __device__ __forceinline__ int64_t item_chunk(const Bf16Args& b, uint32_t it) {
-  return b.chunk_mult * (b.skip > 0 ? ((int64_t)it / (b.skip - 1)) * b.skip + (int64_t)(it % (b.skip - 1)) + 1
-                                    : (int64_t)it * b.chunk_stride + b.chunk_first);
+  const int64_t c = (int64_t)(it / (uint32_t)b.slices);
+  return b.chunk_mult * (b.skip > 0 ? (c / (b.skip - 1)) * b.skip + c % (b.skip - 1) + 1
+                                    : c * b.chunk_stride + b.chunk_first);
 }
 
 // A operand of one wave: row blocks rb and rb + 1 (32 rows each), all K
@@ -838,7 +846,8 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
                                            const float* xn2s, const GroupSlots& gcur, const GroupSlots& gnext,
                                            bool has_next2, GroupSlots& gnext2, int64_t off, uint32_t cnt,
                                            int g2, ColTerms& cols, const u4v* cur, u4v* nxt,
-                                           __amdgpu_buffer_rsrc_t ra, unsigned long long& st_pairs) {
+                                           __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t qr,
+                                           unsigned long long& st_pairs) {
   constexpr int H = TileTraits<PREC>::kHalves;
   const int wave = cs.wave, lane = cs.lane;
   const int q0 = cols.v0 ? __float_as_int(cols.c0.w) : -1;
@@ -850,7 +859,7 @@ __device__ __forceinline__ void group_step(const SearchArgs& a, const Bf16Args& 
   const float f0 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s0;
   const float f1 = PREC == 1 ? 2.0f : 2.0f * cs.sc * cols.s1;
   if (!LAST) {
-    stage_group<PREC, KS>(b, gnext, wave, lane, nxt);
+    stage_group<PREC, KS>(gnext, wave, lane, qr, nxt);
     load_cols<PREC>(b, gnext, cols);
     if (has_next2) gnext2 = group_slots(b, off, cnt, g2, lane);
   }
@@ -890,7 +899,10 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
   cs.gam = (float)(KS * TileTraits<PREC>::kStep + TileTraits<PREC>::kStep) * 0x1p-23f;
   const int wave = cs.wave, lane = cs.lane;
   const u4v* xv = reinterpret_cast<const u4v*>(b.xb);
-  unsigned long long st_pairs = 0, st_needed = 0;
+  // the query rows of every slot (G groups of 64), as a buffer for the gathers
+  constexpr int kQRowBytes = (PREC == 1 ? 2 * KS : 4 * KS) * 16;
+  const __amdgpu_buffer_rsrc_t qr = raw_rsrc(b.qb, b.G * kGroup * kQRowBytes);
+  unsigned long long st_pairs = 0, st_needed = 0, st_rows = 0;
   // work items are fetched one ahead, so that a chunk's last group can load
   // the next chunk's A operand; thread 0 writes item_sh between the barriers
   // that separate it from every thread's reads
@@ -915,15 +927,24 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     // the queries whose (query, leaf) pair survives, in groups of 64
     const uint32_t cnt = b.lcnt[leaf];
     const int64_t off = b.loff[leaf];
-    const int ng = (int)((cnt + kGroup - 1) / kGroup);
-    if (ng == 0) continue;  // uniform across the workgroup
-    st_needed += (unsigned long long)cnt * (unsigned long long)(a.N - cs.c0 < 256 ? a.N - cs.c0 : 256);
-    GroupSlots gcur = group_slots(b, off, cnt, 0, lane);
+    const int ng_all = (int)((cnt + kGroup - 1) / kGroup);
+    // this item's share [g0, g1) of the chunk's groups
+    const int slice = (int)(it % (uint32_t)b.slices);
+    const int g0 = (int)((int64_t)slice * ng_all / b.slices);
+    const int g1 = (int)((int64_t)(slice + 1) * ng_all / b.slices);
+    if (g1 == g0) continue;  // uniform across the workgroup
+    {
+      const uint32_t e0 = (uint32_t)g0 * kGroup, e1 = (uint32_t)g1 * kGroup < cnt ? (uint32_t)g1 * kGroup : cnt;
+      const unsigned long long rows = (unsigned long long)(a.N - cs.c0 < 256 ? a.N - cs.c0 : 256);
+      st_needed += (unsigned long long)(e1 - e0) * rows;
+      if (g0 == 0) st_rows += rows;  // the chunk's rows are streamed once per pass
+    }
+    GroupSlots gcur = group_slots(b, off, cnt, g0, lane);
     ColTerms cols;
-    stage_group<PREC, KS>(b, gcur, wave, lane, Bs0);
+    stage_group<PREC, KS>(gcur, wave, lane, qr, Bs0);
     load_cols<PREC>(b, gcur, cols);
     GroupSlots gnext = gcur;
-    if (ng > 1) gnext = group_slots(b, off, cnt, 1, lane);
+    if (g1 - g0 > 1) gnext = group_slots(b, off, cnt, g0 + 1, lane);
     // A operand: this wave's 64 rows, all K steps, in registers (already
     // loading when the previous chunk's last group reloaded them)
     if (a_chunk != chunk) load_a<PREC, KS>(xv, (cs.c0 + 64 * wave) / 32, lane, av);
@@ -954,24 +975,26 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
       }
       cs.xmin[r] = m;
     }
-    // groups alternate between the two buffers
-    for (int g = 0; g + 1 < ng; g++) {
+    // groups alternate between the two buffers (the item's first in Bs0)
+    for (int g = g0; g + 1 < g1; g++) {
       GroupSlots gnext2 = gnext;
-      group_step<PREC, KS, DUMP, false>(a, b, cs, av, xn2s, gcur, gnext, g + 2 < ng, gnext2, off, cnt, g + 2,
-                                        cols, (g & 1) ? Bs1 : Bs0, (g & 1) ? Bs0 : Bs1, ra, st_pairs);
+      const bool odd = (g - g0) & 1;
+      group_step<PREC, KS, DUMP, false>(a, b, cs, av, xn2s, gcur, gnext, g + 2 < g1, gnext2, off, cnt, g + 2,
+                                        cols, odd ? Bs1 : Bs0, odd ? Bs0 : Bs1, ra, qr, st_pairs);
       gcur = gnext;
       gnext = gnext2;
     }
     {
-      const int g = ng - 1;
+      const bool odd = (g1 - 1 - g0) & 1;
       GroupSlots unused = gnext;
       group_step<PREC, KS, DUMP, true>(a, b, cs, av, xn2s, gcur, gnext, false, unused, off, cnt, 0, cols,
-                                       (g & 1) ? Bs1 : Bs0, (g & 1) ? Bs0 : Bs1, ra, st_pairs);
+                                       odd ? Bs1 : Bs0, odd ? Bs0 : Bs1, ra, qr, st_pairs);
     }
     a_chunk = has_following ? next_chunk : (int64_t)-1;
   }
   if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
   if (threadIdx.x == 0 && st_needed && a.stats) atomicAdd(a.stats + 5, st_needed);
+  if (threadIdx.x == 0 && st_rows && a.stats) atomicAdd(a.stats + 6, st_rows);
 }
 
 // waves per SIMD of the tile kernel: the two waves of a SIMD hide each
@@ -1097,9 +1120,7 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
 sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                               uint4* xb, float4* meta, float4* leafmeta, hipStream_t st) {
   const int64_t nrb = ((N + 255) / 256) * 8;  // 32-row blocks, padded to whole 256-row chunks
-  const int KS = n_pad / 16;
-  k_bf16_copy<<<grid_blocks(nrb * KS * 64, 256), 256, 0, st>>>(X, N, n_pad, nrb, xb);
-  k_bf16_meta<<<grid_blocks(N, 4), 256, 0, st>>>(X, N, n_pad, meta);
+  k_bf16_copy_meta<<<grid_blocks(nrb, 4), 256, 0, st>>>(X, N, n_pad, nrb, xb, meta);
   k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
@@ -1120,10 +1141,12 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
 
 // slot-order masks, then per leaf the slots of the queries that need it:
 // count, offsets, fill
-static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+// slot_masks: the slot-order masks are already in b.smask
+static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st, bool slot_masks = false) {
   const int Spad = b.G * kGroup;
   const int64_t n_sub = a.n_blocks * kSubPerBlock;
-  k_smask<<<grid_blocks(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
+  if (!slot_masks)
+    k_smask<<<grid_blocks(a.n_blocks * Spad, 256), 256, 0, st>>>(a.masks, a.n_blocks, a.B, Spad, b.perm, b.smask);
   k_leaf_lists<0><<<(unsigned)n_sub, 256, 0, st>>>(b.smask, a.n_leaves, Spad, b.lcnt, b.bsum, nullptr, nullptr,
                                                    nullptr);
   k_scan_counts<<<1, 1024, 0, st>>>(b.bsum, n_sub, b.boff);
@@ -1132,10 +1155,10 @@ static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st)
 }
 
 sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
-  SearchArgs m = a;
-  m.stats = nullptr;  // the first masks counted the visited leaves
-  SOFA_TRY(launch_leaf_mask(m, st));
-  launch_lists(a, b, st);
+  // the masks from the tightened U, straight into slot order (the first
+  // masks counted the visited leaves; the query-order masks are not read again)
+  SOFA_TRY(launch_slot_masks(a, b.G * kGroup, b.perm, b.smask, st));
+  launch_lists(a, b, st, true);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -1187,6 +1210,7 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
   b.chunk_mult = 1;
   b.chunk_first = 0;
   b.chunk_stride = 1;
+  b.slices = 1;
   b.n_items = (a.N + 255) / 256;
   SOFA_TRY(launch_slotc(a, b, false, st));
   unsigned grid = 256 * kTileWaves;
@@ -1200,8 +1224,13 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
   b.chunk_mult = mult;
   b.chunk_first = first;
   b.chunk_stride = stride;
-  b.n_items = n_items;
   b.skip = skip;
+  // a pass of few chunks (the coarse sampled passes) splits each chunk's
+  // query groups over several work items, so that it fills the grid
+  unsigned grid = 256 * kTileWaves;
+  b.slices = 1;
+  while (b.slices < 16 && n_items * b.slices < 2 * (int64_t)grid) b.slices *= 2;
+  b.n_items = n_items * b.slices;
   if (n_items <= 0) {
     // keep the pass's timers valid (zero length)
     if (ev)
@@ -1210,8 +1239,7 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
   }
   // the bounds U of this pass (earlier passes tighten them), cleared counts
   SOFA_TRY(launch_slotc(a, b, true, st));
-  unsigned grid = 256 * kTileWaves;
-  if ((int64_t)grid > n_items) grid = (unsigned)(n_items > 0 ? n_items : 1);
+  if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
   if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_tiles<false>(a, b, grid, st));
   if (ev) (void)hipEventRecord(ev[1], st);

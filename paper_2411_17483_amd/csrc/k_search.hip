@@ -148,6 +148,29 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   if (lane == 0 && best != kEmpty) atomicMin(reinterpret_cast<unsigned long long*>(a.best) + q, best);
 }
 
+// the survivor mask of query q in 64-leaf block blk under the current U
+__device__ __forceinline__ uint64_t block_mask(const SearchArgs& a, int64_t blk, int q) {
+  const uint32_t t = f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
+  const int64_t nl = a.n_leaves - blk * kLeavesPerItem;  // leaves of this block
+  const uint64_t valid = nl >= kLeavesPerItem ? ~0ull : ((1ull << nl) - 1ull);
+  const uint4* src = reinterpret_cast<const uint4*>(a.lbh + (blk * a.B + q) * kLeavesPerItem);
+  uint4 v[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) v[i] = src[i];
+  uint64_t m = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int bit = 8 * i + 2 * e;
+      m |= (uint64_t)((w[e] & 0xFFFFu) <= t) << bit;
+      m |= (uint64_t)((w[e] >> 16) <= t) << (bit + 1);
+    }
+  }
+  return m & valid;
+}
+
 // survivor masks per 64-leaf block from the stored bounds: a leaf survives
 // when its bound is within U (with the slack of the FP32 bound sum).  The
 // codes of non-negative values order like the values, so the test is an
@@ -162,25 +185,7 @@ __global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long visited = 0;
   if (q < a.B) {
-    const uint32_t t = f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
-    const int64_t nl = a.n_leaves - blk * kLeavesPerItem;  // leaves of this block
-    const uint64_t valid = nl >= kLeavesPerItem ? ~0ull : ((1ull << nl) - 1ull);
-    const uint4* src = reinterpret_cast<const uint4*>(a.lbh + (blk * a.B + q) * kLeavesPerItem);
-    uint4 v[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) v[i] = src[i];
-    uint64_t m = 0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int bit = 8 * i + 2 * e;
-        m |= (uint64_t)((w[e] & 0xFFFFu) <= t) << bit;
-        m |= (uint64_t)((w[e] >> 16) <= t) << (bit + 1);
-      }
-    }
-    m &= valid;
+    const uint64_t m = block_mask(a, blk, q);
     a.masks[blk * a.B + q] = m;
     visited = (unsigned long long)__popcll(m);
   }
@@ -617,6 +622,25 @@ static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) 
   mark(ev, 3, st);
   (void)launch_leaf_mask(a, st);
   mark(ev, 4, st);
+}
+
+// the same masks in sorted-slot order (smask[blk][s] for the query in slot
+// s, zero past B), straight from the stored bounds: the lists' rebuild from
+// a tightened U needs no query-order copy
+__global__ __launch_bounds__(256) void k_slot_masks(SearchArgs a, int Spad, const int32_t* __restrict__ perm,
+                                                    uint64_t* __restrict__ smask) {
+  const int64_t blk = blockIdx.x;
+  const int s = blockIdx.y * 256 + threadIdx.x;
+  if (s >= Spad) return;
+  smask[blk * Spad + s] = s < a.B ? block_mask(a, blk, perm[s]) : 0ull;
+}
+
+sofa_status launch_slot_masks(const SearchArgs& a, int Spad, const int32_t* perm, uint64_t* smask,
+                              hipStream_t st) {
+  const dim3 gm((unsigned)a.n_blocks, nblk(Spad, 256));
+  k_slot_masks<<<gm, 256, 0, st>>>(a, Spad, perm, smask);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
 }
 
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st) {

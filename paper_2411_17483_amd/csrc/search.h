@@ -33,7 +33,7 @@ struct SearchArgs {
   const uint32_t* cevmin;  // nullable: B smallest lower bound of a dropped BF16 candidate
   unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
                               // [3] tile pairs computed [4] most candidates of a query
-                              // [5] tile pairs needed
+                              // [5] tile pairs needed [6] prune-copy rows streamed
   // factors derived from the FP32 error bounds
   float lb_f, band_f, upd_f, abandon_f;
   double eta_x;
@@ -49,6 +49,10 @@ sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, i
 sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev);
 // survivor masks from the stored envelope bounds and the current U
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st);
+// the same masks written in sorted-slot order: smask[blk][s] for query
+// perm[s], zero for s >= B (Spad slots)
+sofa_status launch_slot_masks(const SearchArgs& a, int Spad, const int32_t* perm, uint64_t* smask,
+                              hipStream_t st);
 // approximate search: the front, then the M (<= kApproxMax) leaves of
 // smallest envelope bound per query (B x kApproxMax leaf ids in `leaves`)
 // scanned exactly; launch_finalize ranks what they hold

@@ -26,7 +26,9 @@ __device__ __forceinline__ float lb_leaf(const float* T, const uint4& sq, const 
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     uint32_t q = byte_of(sq, j), a = byte_of(lo, j), b = byte_of(hi, j);
-    uint32_t c = q < a ? a : (q > b ? b : q);
+    // clamp(q, a, b) for a <= b, as a min and a max (byte operands select
+    // straight from the envelope words)
+    uint32_t c = max(min(q, b), a);
     s += T[j * kAlphaMax + c];
   }
   return s;

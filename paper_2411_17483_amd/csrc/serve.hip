@@ -248,6 +248,12 @@ void sofa_server::worker(int si) {
       st = set_error(SOFA_EDEVICE, "result download failed");
     const double t1 = now_ms();
     const std::string err = st == SOFA_OK ? std::string() : std::string(sofa_last_error());
+    // the bytes the batch's search had to read (prune tiers)
+    double bytes = 0.0;
+    sofa_knn_stats ks{};
+    if (st == SOFA_OK && c.prune != 0 && sofa_knn_get_stats(sl.ws, nullptr, &ks) == SOFA_OK)
+      bytes = (double)ks.prune_rows_streamed * (double)c.ix->n_pad * (c.prune == 1 ? 2.0 : 1.0) +
+              (double)ks.series_refined * 4.0 * (double)c.ix->n_pad;
 
     lk.lock();
     for (int i = 0; i < b; i++) {
@@ -267,6 +273,7 @@ void sofa_server::worker(int si) {
     busy[ci]--;
     stats.completed += b;
     stats.busy_ms += t1 - t0;
+    stats.hbm_bytes += bytes;
     cv_done.notify_all();
     cv_mem.notify_all();
     cv_work.notify_all();  // the collection may take another batch now

@@ -76,7 +76,7 @@ class KnnStats(ctypes.Structure):
                 ("ms_bf16_refine", ctypes.c_double), ("overflow_evicted", _i64),
                 ("overflow_bf16_drop", _i64), ("overflow_band", _i64), ("max_candidates", _i64),
                 ("overflow_retries", _i64), ("series_bf16_needed", _i64),
-                ("prune_passes", _i64)]
+                ("prune_passes", _i64), ("prune_rows_streamed", _i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,7 +89,8 @@ class ServerParams(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("batches", _i64), ("max_batch", _i64),
-                ("in_flight_bytes_peak", _i64), ("memory_waits", _i64), ("busy_ms", ctypes.c_double)]
+                ("in_flight_bytes_peak", _i64), ("memory_waits", _i64), ("busy_ms", ctypes.c_double),
+                ("hbm_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
