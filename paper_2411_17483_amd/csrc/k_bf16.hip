@@ -205,55 +205,70 @@ __global__ __launch_bounds__(256) void k_bf16_leafmeta(const float4* __restrict_
 }
 
 // ----------------------------------------------------------------------------
-// build: FP8 copy.  Scale per 256-row chunk (one workgroup per chunk).
-__global__ __launch_bounds__(256) void k_fp8_chunk_scale(const float* __restrict__ X, int64_t N,
-                                                         int n_pad, float* __restrict__ cscale) {
+// build: FP8 copy.  A power-of-two scale per 256-row chunk, then the e4m3
+// copy and each row's terms, one workgroup per chunk: the chunk's maximum
+// |x| first (its 256 rows then sit in the caches), then wave w writes row
+// blocks 2w and 2w + 1 of the chunk.  Fragment half h of slot
+// ((rb*KS + ks)*2 + h)*64 + lane holds row rb*32 + lane%32, columns
+// 64 ks + 32 (lane/32) + 16 h + (0..15); the lane sums its row's terms over
+// its half of the columns in FP64, and the two halves meet by one exchange.
+__global__ __launch_bounds__(256) void k_fp8_chunk_build(const float* __restrict__ X, int64_t N, int n_pad,
+                                                         float* __restrict__ cscale, uint4* __restrict__ xf,
+                                                         float4* __restrict__ meta) {
   __shared__ float red[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t c0 = (int64_t)blockIdx.x * 256;
-  float m = 0.0f;
-  for (int r = wave; r < 256 && c0 + r < N; r += 4)
-    for (int c = lane * 4; c < n_pad; c += 256) {
-      const float4 v = *reinterpret_cast<const float4*>(X + (c0 + r) * n_pad + c);
-      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-    }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if (lane == 0) red[wave] = m;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    cscale[blockIdx.x] = fp8_scale_for(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
-}
-
-// Thread i writes the 16-byte half h of fragment slot ((rb*KS + ks)*2 + h)*64 + lane:
-// row rb*32 + lane%32, columns 64 ks + 32 (lane/32) + 16 h + (0..15).
-__global__ void k_fp8_copy(const float* __restrict__ X, int64_t N, int n_pad, int64_t nrb,
-                           const float* __restrict__ cscale, uint4* __restrict__ xf) {
   const int KS = n_pad / 64;
-  const int64_t total = nrb * KS * 128;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-  const int lane = (int)(i % 64);
-  const int h = (int)((i / 64) % 2);
-  const int64_t t = i / 128;
-  const int ks = (int)(t % KS);
-  const int64_t rb = t / KS;
-  const int64_t row = rb * 32 + lane % 32;
-  const int k0 = ks * 64 + 32 * (lane / 32) + 16 * h;
-  uint4 w = make_uint4(0u, 0u, 0u, 0u);
-  if (row < N) w = fp8_pack16(X + row * n_pad + k0, 1.0f / cscale[row / 256]);
-  xf[i] = w;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_fp8_meta(const float* __restrict__ X, int64_t N, int n_pad,
-                                                  const float* __restrict__ cscale,
-                                                  float4* __restrict__ meta) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < N; row += (int64_t)gridDim.x * 4) {
-    float4 m;
-    norms_of_fp8(X + row * n_pad, n_pad, lane, cscale[row / 256], m);
-    if (lane == 0) meta[row] = m;
+  const int64_t n_chunks = (N + 255) / 256;
+  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    const int64_t c0 = chunk * 256;
+    float m = 0.0f;
+    for (int r = wave; r < 256 && c0 + r < N; r += 4)
+      for (int c = lane * 4; c < n_pad; c += 256) {
+        const float4 v = *reinterpret_cast<const float4*>(X + (c0 + r) * n_pad + c);
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    const float sc = fp8_scale_for(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+    __syncthreads();  // red is rewritten by the next chunk
+    if (threadIdx.x == 0) cscale[chunk] = sc;
+    const float inv = 1.0f / sc;  // exact: sc is a power of two
+    for (int b2 = 0; b2 < 2; b2++) {
+      const int64_t rb = chunk * 8 + 2 * wave + b2;
+      const int64_t row = rb * 32 + lane % 32;
+      const bool live = row < N;
+      double s2 = 0.0, r2 = 0.0, h2 = 0.0;
+      for (int ks = 0; ks < KS; ks++)
+        for (int hh = 0; hh < 2; hh++) {
+          const int k0 = ks * 64 + 32 * (lane / 32) + 16 * hh;
+          uint32_t w[4] = {0, 0, 0, 0};
+          if (live) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              const float4 v = *reinterpret_cast<const float4*>(X + row * n_pad + k0 + 4 * j);
+              const float xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+              for (int e = 0; e < 4; e++) {
+                const uint32_t code = e4m3_code(xs[e] * inv);
+                w[j] |= code << (8 * e);
+                const double x = xs[e], hv = (double)sc * (double)e4m3_val(code);
+                s2 += x * x;
+                r2 += (x - hv) * (x - hv);
+                h2 += hv * hv;
+              }
+            }
+          }
+          xf[((rb * KS + ks) * 2 + hh) * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      s2 += __shfl_xor(s2, 32);
+      r2 += __shfl_xor(r2, 32);
+      h2 += __shfl_xor(h2, 32);
+      if (lane < 32 && live)
+        meta[row] = make_float4(__double2float_rd(s2 * (1.0 - 1e-12)), __double2float_ru(sqrt(r2) * (1.0 + 1e-12)),
+                                __double2float_ru(sqrt(h2) * (1.0 + 1e-12)), 0.0f);
+    }
   }
 }
 
@@ -1129,11 +1144,7 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
 sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                              uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st) {
   const int64_t n_chunks = (N + 255) / 256;
-  const int64_t nrb = n_chunks * 8;  // 32-row blocks, padded to whole 256-row chunks
-  const int KS = n_pad / 64;
-  k_fp8_chunk_scale<<<(unsigned)n_chunks, 256, 0, st>>>(X, N, n_pad, cscale);
-  k_fp8_copy<<<grid_blocks(nrb * KS * 128, 256), 256, 0, st>>>(X, N, n_pad, nrb, cscale, xf);
-  k_fp8_meta<<<grid_blocks(N, 4), 256, 0, st>>>(X, N, n_pad, cscale, meta);
+  k_fp8_chunk_build<<<grid_blocks(n_chunks, 1), 256, 0, st>>>(X, N, n_pad, cscale, xf, meta);
   k_bf16_leafmeta<<<nblk(n_leaves, 4), 256, 0, st>>>(meta, N, L, n_leaves, leafmeta);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
