@@ -65,10 +65,13 @@ sofa_status launch_znorm(const float* in, int64_t m, int n, float* out, hipStrea
 }
 
 // ----------------------------------------------------------------------------
-// projection
-constexpr int kPrjCh = 128;            // staged columns per chunk
-constexpr int kPrjRow = kPrjCh + 4;    // padded LDS row (floats), keeps 16-byte alignment
-
+// projection.  A wave takes 16 rows at a time and loads them straight into
+// the MFMA operand layout, no LDS staging: for 16-column block m, lane
+// (li, g) = (lane % 16, lane / 16) holds columns 16m + 4g .. 16m + 4g + 3 of
+// row li (the four lanes of a row read 64 contiguous bytes), and the four
+// v_mfma_f32_16x16x4f32 steps of the block take one component each, with
+// the basis rows read in the same column order.  Each wave works on its own
+// rows, so no workgroup barrier orders the waves.
 template <int NG, bool QUANT>
 __global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, int64_t m, int n,
                                                  int64_t ldx, const float* __restrict__ BT,
@@ -77,7 +80,6 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, in
                                                  uint8_t* __restrict__ words,
                                                  double* __restrict__ norm2,
                                                  unsigned* __restrict__ bad) {
-  __shared__ __attribute__((aligned(16))) float S[4][16 * kPrjRow];
   __shared__ float bq[QUANT ? kTable : 1];
   __shared__ __attribute__((aligned(16))) uint8_t Wb[4][16 * 16];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -86,45 +88,41 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, in
     for (int i = threadIdx.x; i < kTable; i += 256) bq[i] = beta32[i];
   __syncthreads();
   unsigned badf = 0;
-  const int64_t ntile = (m + 63) / 64;
-  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int64_t row0 = tile * 64 + wave * 16;
+  const int nblk16 = (n + 15) / 16;  // column blocks holding data
+  const int64_t ntile = (m + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row0 = tile * 16;
+    const int64_t row = row0 + li;
+    const float* xr = X + (row < m ? row : m - 1) * ldx;
     f4v acc[NG];
 #pragma unroll
     for (int gi = 0; gi < NG; gi++) acc[gi] = (f4v){0.f, 0.f, 0.f, 0.f};
     double nrm = 0.0;
-    for (int c0 = 0; c0 < n; c0 += kPrjCh) {
-      // stage 16 rows x kPrjCh columns (coalesced float4 loads)
+    // column blocks in batches of four: 4 x 16 B per lane in flight
+    for (int mb = 0; mb < nblk16; mb += 4) {
+      float4 a[4];
 #pragma unroll
-      for (int r = 0; r < (16 * kPrjCh / 4) / 64; r++) {
-        int f = lane + 64 * r;
-        int rr = f / (kPrjCh / 4), c4 = f % (kPrjCh / 4);
-        int col = c0 + 4 * c4;
-        int64_t row = row0 + rr;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (row < m && col < n) v = *reinterpret_cast<const float4*>(X + row * ldx + col);
-        *reinterpret_cast<float4*>(&S[wave][rr * kPrjRow + 4 * c4]) = v;
+      for (int u = 0; u < 4; u++) {
+        const int col = 16 * (mb + u) + 4 * g;
+        a[u] = (row < m && mb + u < nblk16 && col < n) ? *reinterpret_cast<const float4*>(xr + col)
+                                                        : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      __syncthreads();
-      // lane group g owns columns [c0 + g*kPrjCh/4, c0 + (g+1)*kPrjCh/4) of the chunk
 #pragma unroll
-      for (int s4 = 0; s4 < kPrjCh / 16; s4++) {
-        int cc = g * (kPrjCh / 4) + 4 * s4;
-        float4 a = *reinterpret_cast<const float4*>(&S[wave][li * kPrjRow + cc]);
-        nrm += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
-        if (!(isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w))) badf = 1;
+      for (int u = 0; u < 4; u++) {
+        if (mb + u >= nblk16) break;
+        const int col = 16 * (mb + u) + 4 * g;
+        nrm += (double)a[u].x * a[u].x + (double)a[u].y * a[u].y + (double)a[u].z * a[u].z +
+               (double)a[u].w * a[u].w;
+        if (!(isfinite(a[u].x) && isfinite(a[u].y) && isfinite(a[u].z) && isfinite(a[u].w))) badf = 1;
 #pragma unroll
         for (int gi = 0; gi < NG; gi++) {
-          float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (c0 + cc < n_pad)
-            b = *reinterpret_cast<const float4*>(BT + (int64_t)(gi * 16 + li) * n_pad + c0 + cc);
-          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[gi], 0, 0, 0);
-          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[gi], 0, 0, 0);
-          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[gi], 0, 0, 0);
-          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[gi], 0, 0, 0);
+          const float4 b = *reinterpret_cast<const float4*>(BT + (int64_t)(gi * 16 + li) * n_pad + col);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].x, b.x, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].y, b.y, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].z, b.z, acc[gi], 0, 0, 0);
+          acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].w, b.w, acc[gi], 0, 0, 0);
         }
       }
-      __syncthreads();
     }
     // D[row 4g+r][col li] of each 16-column group
     if (out) {
@@ -132,33 +130,38 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, in
       for (int gi = 0; gi < NG; gi++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          int64_t row = row0 + 4 * g + r;
-          if (row < m) out[row * ld_out + gi * 16 + li] = acc[gi][r];
+          const int64_t ro = row0 + 4 * g + r;
+          if (ro < m) out[ro * ld_out + gi * 16 + li] = acc[gi][r];
         }
     }
     if (norm2) {
       nrm += __shfl_xor(nrm, 16);
       nrm += __shfl_xor(nrm, 32);
-      if (g == 0 && row0 + li < m) norm2[row0 + li] = nrm;
+      if (g == 0 && row < m) norm2[row] = nrm;
     }
     if (QUANT) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         float c = acc[0][r];
-        int s = 0;
+        int sy = 0;
         if (li < l) {
           const float* bj = bq + li * kAlphaMax;
 #pragma unroll
           for (int step = 128; step > 0; step >>= 1)
-            if (bj[s + step - 1] <= c) s += step;
+            if (bj[sy + step - 1] <= c) sy += step;
         }
-        Wb[wave][(4 * g + r) * 16 + li] = (uint8_t)s;
+        Wb[wave][(4 * g + r) * 16 + li] = (uint8_t)sy;
       }
-      __syncthreads();
+      // the wave's own staging bytes: order its LDS writes before its reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (lane < 16 && row0 + lane < m)
         *reinterpret_cast<uint4*>(words + (row0 + lane) * kWordBytes) =
             *reinterpret_cast<const uint4*>(&Wb[wave][lane * 16]);
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   if (bad && badf) atomicOr(bad, 1u);
@@ -168,8 +171,10 @@ template <int NG, bool QUANT>
 static void launch_project_t(const float* X, int64_t m, int n, int64_t ldx, const float* bt,
                              int n_pad, float* out, int ld_out, const float* beta32, int l,
                              uint8_t* words, double* norm2, unsigned* bad, hipStream_t st) {
+  // four 16-row tiles per workgroup round; enough workgroups to keep every
+  // CU's waves loading
   int64_t tiles = (m + 63) / 64;
-  unsigned grid = (unsigned)(tiles < 256 * 6 ? tiles : 256 * 6);
+  unsigned grid = (unsigned)(tiles < 256 * 8 ? tiles : 256 * 8);
   if (grid == 0) grid = 1;
   k_project<NG, QUANT><<<grid, 256, 0, st>>>(X, m, n, ldx, bt, n_pad, out, ld_out, beta32, l,
                                              words, norm2, bad);
@@ -346,7 +351,9 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
   }
 }
 
-// permuted copy: leaf-order position p holds row src = perm[p]
+// permuted copy: leaf-order position p holds row src = perm[p].  A wave
+// moves kPermRows rows per step, all their loads issued before any store.
+constexpr int kPermRows = 4;
 __global__ __launch_bounds__(256) void k_permute(const float* __restrict__ X, int n,
                                                  const uint32_t* __restrict__ perm, int64_t N,
                                                  int n_pad, float* __restrict__ Xo,
@@ -356,16 +363,25 @@ __global__ __launch_bounds__(256) void k_permute(const float* __restrict__ X, in
                                                  double* __restrict__ nout,
                                                  int32_t* __restrict__ ids) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < N; p += (int64_t)gridDim.x * 4) {
-    const int64_t src = perm[p];
-    for (int c = lane * 4; c < n_pad; c += 256) {
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < n) v = *reinterpret_cast<const float4*>(X + src * n + c);
-      *reinterpret_cast<float4*>(Xo + p * n_pad + c) = v;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * kPermRows; p0 < N; p0 += nw * kPermRows) {
+    for (int c0 = 0; c0 < n_pad; c0 += 256) {
+      const int c = c0 + lane * 4;
+      if (c >= n_pad) break;  // rows shorter than 256 values: lanes past the row idle
+      float4 v[kPermRows];
+#pragma unroll
+      for (int r = 0; r < kPermRows; r++) {
+        const int64_t p = p0 + r;
+        v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p < N && c < n) v[r] = *reinterpret_cast<const float4*>(X + (int64_t)perm[p] * n + c);
+      }
+#pragma unroll
+      for (int r = 0; r < kPermRows; r++)
+        if (p0 + r < N) *reinterpret_cast<float4*>(Xo + (p0 + r) * n_pad + c) = v[r];
     }
-    if (lane == 0) {
-      *reinterpret_cast<uint4*>(wout + p * kWordBytes) =
-          *reinterpret_cast<const uint4*>(win + src * kWordBytes);
+    if (lane < kPermRows && p0 + lane < N) {
+      const int64_t p = p0 + lane, src = perm[p];
+      *reinterpret_cast<uint4*>(wout + p * kWordBytes) = *reinterpret_cast<const uint4*>(win + src * kWordBytes);
       nout[p] = nin[src];
       ids[p] = (int32_t)src;
     }
@@ -458,7 +474,7 @@ sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_i
   SOFA_TRY(ix->ids.alloc(4 * N));
   SOFA_TRY(ix->norm2.alloc(8 * N));
   SOFA_TRY(ix->env.alloc(32 * ix->n_leaves));
-  k_permute<<<grid_blocks(N, 4), 256, 0, st>>>(X, n, va, N, n_pad, ix->X.as<float>(), words_in,
+  k_permute<<<grid_blocks(N, 4 * kPermRows), 256, 0, st>>>(X, n, va, N, n_pad, ix->X.as<float>(), words_in,
                                         ix->words.as<uint8_t>(), norm2_in, ix->norm2.as<double>(),
                                         ix->ids.as<int32_t>());
   k_envelope<<<nblk(ix->n_leaves, 4), 256, 0, st>>>(ix->words.as<uint8_t>(), N, ix->L, ix->n_leaves,
