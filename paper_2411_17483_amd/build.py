@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsofa.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "k_learn.hip", "k_build.hip", "k_search.hip", "k_bf16.hip", "k_mlp.hip",
+SOURCES = ["api.hip", "k_learn.hip", "k_build.hip", "k_search.hip", "k_bf16.hip", "k_tiles.hip", "k_mlp.hip",
            "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

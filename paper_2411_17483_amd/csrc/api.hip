@@ -542,7 +542,7 @@ enum {
   W_QP, W_POOL, W_QN, W_TAB, W_SQ, W_BEST, W_MASK, W_LBH, W_CTR, W_RES, W_RCNT, W_FLAG, W_HIST, W_HBASE,
   // read back by the host after the call: adjacent, one copy
   W_U, W_U0, W_STAT, W_STATS, W_BAD,
-  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_BSUM, W_BOFF, W_LSLOT, W_SMASK, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
+  W_CAND, W_CCNT, W_CEV, W_QCNT, W_PERM, W_LCNT, W_LOFF, W_LSLOT, W_SLOTC, W_QB, W_QMETA, W_QSCALE, W_BCTR,
   W_MLP, W_APPROX, W_QZ, W_END
 };
 
@@ -598,16 +598,13 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_PERM] = bf ? (size_t)B * 4 : 0;
   sz[W_LCNT] = bf ? (size_t)ix->n_leaves * 4 : 0;
   sz[W_LOFF] = bf ? (size_t)ix->n_leaves * 8 : 0;
-  sz[W_BSUM] = bf ? (size_t)ix->n_blocks * 4 * 4 : 0;  // per 16-leaf sub-block
-  sz[W_BOFF] = bf ? (size_t)ix->n_blocks * 4 * 8 : 0;
   sz[W_LSLOT] = bf ? (size_t)ix->n_leaves * B * 2 : 0;  // worst case: every query needs every leaf
-  sz[W_SMASK] = bf ? (size_t)ix->n_blocks * G * kGroup * 8 : 0;
   sz[W_SLOTC] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_QB] = bf ? (size_t)G * kGroup * ix->n_pad * 2 : 0;
   sz[W_QMETA] = bf ? (size_t)G * kGroup * 16 : 0;
   sz[W_QSCALE] = bf ? (size_t)G * kGroup * 4 : 0;
   sz[W_BCTR] = bf ? 64 : 0;
-  sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? mlp_act_floats(p->radius_model->dims, B) * 4 : 0;
+  sz[W_MLP] = (p && p->radius_model && !p->d_radius) ? model_radius_scratch_floats(p->radius_model->dims, B) * 4 : 0;
   sz[W_APPROX] = (p && p->approx_leaves > 0) ? (size_t)B * kApproxMax * 4 : 0;
   sz[W_QZ] = (p && p->znormalise) ? (size_t)B * ix->n * 4 : 0;
   Layout L;
@@ -949,10 +946,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.qcount = (uint32_t*)at(W_QCNT);
     b.lcnt = (uint32_t*)at(W_LCNT);
     b.loff = (int64_t*)at(W_LOFF);
-    b.bsum = (uint32_t*)at(W_BSUM);
-    b.boff = (int64_t*)at(W_BOFF);
     b.lslot = (uint16_t*)at(W_LSLOT);
-    b.smask = (uint64_t*)at(W_SMASK);
     b.slotc = (float4*)at(W_SLOTC);
     b.G = (int)((B + kGroup - 1) / kGroup);
     b.cand = (uint32_t*)at(W_CAND);
@@ -1214,7 +1208,7 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   if (B > 65535) return set_error(SOFA_EINVAL, "B too large");
   hipStream_t st = S(stream);
   const int64_t G = (B + kGroup - 1) / kGroup;
-  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, lcnt, loff, bsum, boff, lslot, sm, sc, perm, qb, qmeta, qscale,
+  DevBuf qp, pool, qn, tab, sq, u0, bad, masks, lcnt, loff, lslot, sc, perm, qb, qmeta, qscale,
       ctr, U, stats;
   SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4, st));
   SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4, st));
@@ -1227,10 +1221,7 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   SOFA_TRY(masks.alloc((size_t)ix->n_blocks * B * 8, st));
   SOFA_TRY(lcnt.alloc((size_t)ix->n_leaves * 4, st));
   SOFA_TRY(loff.alloc((size_t)ix->n_leaves * 8, st));
-  SOFA_TRY(bsum.alloc((size_t)ix->n_blocks * 4 * 4, st));  // per 16-leaf sub-block
-  SOFA_TRY(boff.alloc((size_t)ix->n_blocks * 4 * 8, st));
   SOFA_TRY(lslot.alloc((size_t)ix->n_leaves * B * 2, st));
-  SOFA_TRY(sm.alloc((size_t)ix->n_blocks * G * kGroup * 8, st));
   SOFA_TRY(sc.alloc((size_t)G * kGroup * 16, st));
   SOFA_TRY(perm.alloc((size_t)B * 4, st));
   SOFA_TRY(qb.alloc((size_t)G * kGroup * ix->n_pad * 2, st));
@@ -1281,10 +1272,7 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   b.qcount = u0.as<uint32_t>();  // scratch for the density sort
   b.lcnt = lcnt.as<uint32_t>();
   b.loff = loff.as<int64_t>();
-  b.bsum = bsum.as<uint32_t>();
-  b.boff = boff.as<int64_t>();
   b.lslot = lslot.as<uint16_t>();
-  b.smask = sm.as<uint64_t>();
   b.slotc = sc.as<float4>();
   b.G = (int)G;
   b.counter = ctr.as<uint32_t>();

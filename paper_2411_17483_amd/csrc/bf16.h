@@ -6,6 +6,10 @@
 namespace sofa {
 
 constexpr int kGroup = 64;  // queries per MFMA query group
+// waves per SIMD of the tile kernel: the two waves of a SIMD hide each
+// other's epilogues and LDS waits (one wave running both column blocks of a
+// group together, with 512 registers, measured slower on 10M x 256)
+constexpr int kTileWaves = 2;
 
 struct Bf16Args {
   int prec;                 // 1: BF16 copy, 2: FP8 (e4m3) copy
@@ -18,12 +22,9 @@ struct Bf16Args {
   float4* qmeta;            // per slot: |q|^2 (down), r_q (up), |qh| (up), |q| (up)
   int32_t* perm;            // sorted slot -> query
   uint32_t* qcount;         // surviving leaves per query
-  uint64_t* smask;          // n_blocks x (64 G) survivor masks in sorted-slot order
   uint32_t* lcnt;           // n_leaves: queries whose (query, leaf) pair survives
   int64_t* loff;            // n_leaves: start of each leaf's list in lslot
-  uint32_t* bsum;           // 4 n_blocks: list entries of each 16-leaf sub-block
-  int64_t* boff;            // 4 n_blocks: start of each sub-block's lists in lslot
-  uint16_t* lslot;          // per leaf, the sorted slots of those queries, ascending
+  uint16_t* lslot;          // per leaf (B entries from leaf * B), the sorted slots of those queries
   float4* slotc;            // per slot and pass: bound terms (a, b, c) and the query id
   int G;                    // query groups
   uint32_t* cand;           // B x cap candidate rows
@@ -49,6 +50,9 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
 // order: later passes see only the pairs that still survive
 sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
+// the tile kernel over b's work items on a persistent grid (dump: write
+// every pair's lower bound to b.dump instead of pruning)
+sofa_status launch_bf16_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, bool dump, hipStream_t st);
 // ev (nullable): events recorded before the tile kernel, between it and the
 // candidate refinement, and after
 sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,

@@ -395,6 +395,101 @@ __global__ void k_radius(const float* __restrict__ y, int64_t B, float margin, f
   if (u0) u0[i] = __double2float_ru(R * R * (1.0 + 1e-12));
 }
 
+// The forward pass and radius of a batch in one launch, for inference (the
+// radii of a search, sofa_radius_predict): the operations of k_standardize,
+// k_fwd (each output's FMA chain over k from a zero accumulator, then the
+// bias and the GELU), k_out (its per-lane sums and shuffle tree) and
+// k_radius, in the same order, so the radii equal those of the separate
+// kernels bit for bit.  Workgroup: kInferQ queries, activations in LDS;
+// thread j computes neuron j (and j + 256, ...) of each layer for them.
+constexpr int kInferQ = 4;
+
+__host__ __device__ inline size_t infer_lds_bytes(const MlpDims& d) {
+  return (size_t)kInferQ * (d.D + d.H1 + d.H2) * 4;
+}
+
+__global__ __launch_bounds__(256) void k_infer(const float* __restrict__ feat, int64_t ld, int64_t B, MlpDims d,
+                                               const float* __restrict__ wr, const float* __restrict__ mu,
+                                               const float* __restrict__ sd, float margin,
+                                               float* __restrict__ r, float* __restrict__ u0) {
+  extern __shared__ float act[];
+  float* xs = act;                   // kInferQ x D
+  float* h1 = xs + kInferQ * d.D;    // kInferQ x H1
+  float* h2 = h1 + kInferQ * d.H1;   // kInferQ x H2
+  const int64_t q0 = (int64_t)blockIdx.x * kInferQ;
+  const int nq = (int)(B - q0 < kInferQ ? B - q0 : kInferQ);
+  const int t = threadIdx.x;
+  for (int i = t; i < nq * d.D; i += 256) {
+    const int q = i / d.D, k = i % d.D;
+    xs[i] = (feat[(q0 + q) * ld + k] - mu[k]) / sd[k];
+  }
+  __syncthreads();
+  const float* W1 = wr + d.oW1;
+  for (int j = t; j < d.H1; j += 256) {
+    float acc[kInferQ];
+#pragma unroll
+    for (int q = 0; q < kInferQ; q++) acc[q] = 0.0f;
+    for (int k = 0; k < d.D; k++) {
+      const float w = W1[(int64_t)j * d.D + k];
+#pragma unroll
+      for (int q = 0; q < kInferQ; q++) acc[q] = fmaf(xs[q * d.D + k], w, acc[q]);
+    }
+    const float bj = wr[d.ob1 + j];
+#pragma unroll
+    for (int q = 0; q < kInferQ; q++)
+      if (q < nq) h1[q * d.H1 + j] = gelu(acc[q] + bj);
+  }
+  __syncthreads();
+  const float* W2 = wr + d.oW2;
+  for (int j = t; j < d.H2; j += 256) {
+    float acc[kInferQ];
+#pragma unroll
+    for (int q = 0; q < kInferQ; q++) acc[q] = 0.0f;
+    for (int k = 0; k < d.H1; k++) {
+      const float w = W2[(int64_t)j * d.H1 + k];
+#pragma unroll
+      for (int q = 0; q < kInferQ; q++) acc[q] = fmaf(h1[q * d.H1 + k], w, acc[q]);
+    }
+    const float bj = wr[d.ob2 + j];
+#pragma unroll
+    for (int q = 0; q < kInferQ; q++)
+      if (q < nq) h2[q * d.H2 + j] = gelu(acc[q] + bj);
+  }
+  __syncthreads();
+  const int lane = t & 63, q = t >> 6;  // one wave per query (kInferQ = 4 waves)
+  if (q < nq) {
+    const float* w3 = wr + d.oW3;
+    float s = 0.0f;
+    for (int i = lane; i < d.H2; i += 64) s = fmaf(w3[i], h2[q * d.H2 + i], s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) {
+      const float y = s + wr[d.ob3];
+      const double R = exp((double)y + (double)margin);
+      if (r) r[q0 + q] = (float)R;
+      if (u0) u0[q0 + q] = __double2float_ru(R * R * (1.0 + 1e-12));
+    }
+  }
+}
+static_assert(kInferQ * 64 <= 256, "one wave per query of a workgroup");
+
+// the fused launch holds a workgroup's activations in at most 64 KB of LDS
+// (the default dimensions take 8.5 KB)
+bool infer_fits(const MlpDims& d) { return infer_lds_bytes(d) <= 65536; }
+size_t model_radius_scratch_floats(const MlpDims& d, int64_t B) {
+  return infer_fits(d) ? 0 : mlp_act_floats(d, B);
+}
+
+sofa_status launch_infer(const sofa_radius* m, const float* feat, int64_t ld, int64_t B, float* r, float* u0,
+                         hipStream_t st) {
+  if (B <= 0) return SOFA_OK;
+  const MlpDims& d = m->dims;
+  k_infer<<<nblk(B, kInferQ), 256, infer_lds_bytes(d), st>>>(feat, ld, B, d, m->wr.as<float>(), m->mu.as<float>(),
+                                                             m->sd.as<float>(), m->margin, r, u0);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
 // ----------------------------------------------------------------------------
 // host side
 static sofa_status ensure_act(sofa_radius* m, int64_t B) {
@@ -660,6 +755,11 @@ extern "C" sofa_status sofa_radius_predict(const sofa_radius* m, const float* d_
   if (!m || !d_feat || !d_radius || B < 0) return set_error(SOFA_EINVAL, "bad arguments");
   if (B == 0) return SOFA_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (infer_fits(m->dims)) {
+    SOFA_TRY(launch_infer(m, d_feat, m->dims.D, B, d_radius, nullptr, st));
+    SOFA_HIP(hipStreamSynchronize(st));
+    return SOFA_OK;
+  }
   DevBuf act;
   SOFA_TRY(act.alloc(mlp_act_floats(m->dims, B) * 4));
   MlpAct a = act_views(act.as<float>(), m->dims, B);
@@ -673,6 +773,7 @@ namespace sofa {
 // radii of a query batch inside sofa_knn: forward on the pool values, U0
 sofa_status launch_model_radius(const sofa_radius* m, const float* pool, int64_t ld, int64_t B,
                                 float* scratch, float* U0, hipStream_t st) {
+  if (infer_fits(m->dims)) return launch_infer(m, pool, ld, B, nullptr, U0, st);
   MlpAct a = act_views(scratch, m->dims, B);
   mlp_forward(m, pool, ld, B, a, st);
   k_radius<<<nblk(B, 256), 256, 0, st>>>(a.y, B, m->margin, nullptr, U0);

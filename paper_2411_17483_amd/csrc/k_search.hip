@@ -94,18 +94,6 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
 // the survivor masks once the seed has set U.
 constexpr int kSegLeaves = 16384;  // leaves per workgroup: one 16 KB table load serves them all
 
-// FP16 code of a non-negative bound, rounded down; +inf stays +inf, finite
-// values above the largest code clamp to it
-__device__ __forceinline__ uint16_t f16_down(float x) {
-  const uint32_t f = __float_as_uint(x);
-  if (f & 0x80000000u) return 0;                // cannot occur; 0 keeps the leaf
-  if (f >= 0x7F800000u) return 0x7C00u;         // +inf
-  const int e = (int)(f >> 23) - 127 + 15;
-  if (e >= 31) return 0x7BFFu;
-  if (e <= 0) return (uint16_t)(x * 0x1p24f);   // subnormal: floor(x / 2^-24), exact scaling
-  return (uint16_t)((e << 10) | ((f >> 13) & 0x3FFu));
-}
-
 __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __shared__ float T[kTable];
   const int q = blockIdx.y;
@@ -115,29 +103,32 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
   __syncthreads();
   const uint4 sq = a.sq[q];
   const int lane = threadIdx.x & 63;
+  const int64_t last = a.n_leaves - 1;
   uint64_t best = kEmpty;
-  // two leaves per thread and iteration (independent lookup chains)
-  for (int it = 0; it < kSegLeaves / 256; it += 2) {
-    float lb2[2];
-    bool valid2[2];
+  // kU leaves per thread and iteration: their envelope loads are issued
+  // together (a leaf past the end reads the last one; its bound is dropped)
+  constexpr int kU = 4;
+  for (int it = 0; it < kSegLeaves / 256; it += kU) {
+    if (seg0 + (int64_t)it * 256 >= a.n_leaves) break;  // uniform over the workgroup
+    uint4 lo[kU], hi[kU];
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < kU; u++) {
       const int64_t leaf = seg0 + (it + u) * 256 + threadIdx.x;
-      valid2[u] = leaf < a.n_leaves;
-      lb2[u] = INFINITY;
-      if (valid2[u]) {
-        const uint4* e = reinterpret_cast<const uint4*>(a.env + leaf * 32);
-        lb2[u] = lb_leaf(T, sq, e[0], e[1]);
-      }
+      const uint4* e = reinterpret_cast<const uint4*>(a.env + (leaf < last ? leaf : last) * 32);
+      lo[u] = e[0];
+      hi[u] = e[1];
     }
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < kU; u++) {
       const int64_t leaf = seg0 + (it + u) * 256 + threadIdx.x;
-      const uint64_t key = ((uint64_t)__float_as_uint(lb2[u]) << 32) | (uint64_t)(uint32_t)leaf;
-      if (valid2[u]) {
-        best = key < best ? key : best;
-        a.lbh[((leaf / kLeavesPerItem) * a.B + q) * kLeavesPerItem + leaf % kLeavesPerItem] = f16_down(lb2[u]);
-      }
+      const bool valid = leaf < a.n_leaves;
+      const float lb = lb_leaf(T, sq, lo[u], hi[u]);
+      // computed for every leaf (a select, not a branch), so that the loads
+      // stay ahead of the arithmetic
+      const uint64_t key = valid ? ((uint64_t)__float_as_uint(lb) << 32) | (uint64_t)(uint32_t)leaf : kEmpty;
+      best = key < best ? key : best;
+      if (valid)
+        a.lbh[((leaf / kLeavesPerItem) * a.B + q) * kLeavesPerItem + leaf % kLeavesPerItem] = f16_down(lb);
     }
   }
 #pragma unroll
@@ -150,7 +141,7 @@ __global__ __launch_bounds__(256) void k_leaf_lb(SearchArgs a) {
 
 // the survivor mask of query q in 64-leaf block blk under the current U
 __device__ __forceinline__ uint64_t block_mask(const SearchArgs& a, int64_t blk, int q) {
-  const uint32_t t = f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
+  const uint32_t t = u_code(a, q);
   const int64_t nl = a.n_leaves - blk * kLeavesPerItem;  // leaves of this block
   const uint64_t valid = nl >= kLeavesPerItem ? ~0ull : ((1ull << nl) - 1ull);
   const uint4* src = reinterpret_cast<const uint4*>(a.lbh + (blk * a.B + q) * kLeavesPerItem);
@@ -201,16 +192,21 @@ __global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
   }
 }
 
-// 3. seed: one wave per query scans the best leaf's rows.
+// 3. seed: one workgroup per query scans the best leaf's rows, wave w taking
+// the 16-row steps w, w + 4, ... with its own candidate list; the four lists'
+// k smallest keys then give the k-th smallest key of the leaf (every key
+// below it is among some wave's k smallest), so U is the same as one wave
+// scanning the whole leaf would set.
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
+  __shared__ uint64_t keys[4][64 * R];
+  __shared__ uint64_t kth_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
-  const int q = blockIdx.x * 4 + wave;
-  if (q >= a.B) return;
-  float U0 = a.U0[q];
-  uint64_t bestk = a.best[q];
+  const int q = blockIdx.x;
+  const float U0 = a.U0[q];
+  const uint64_t bestk = a.best[q];
   if (bestk == kEmpty || a.seed_leaf == 0) {
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       a.U[q] = __float_as_uint(U0);
       a.hbase[q] = U0;
     }
@@ -224,7 +220,7 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
   wl.reset();
   float Umin = U0;
   // 16 rows per step: row p0 + 4r + g in 16-lane group g, slot r
-  for (int64_t p0 = start; p0 < end; p0 += 4 * kRefRows) {
+  for (int64_t p0 = start + 4 * kRefRows * wave; p0 < end; p0 += 16 * kRefRows) {
     uint32_t pm[kRefRows];
     bool am[kRefRows];
 #pragma unroll
@@ -252,9 +248,30 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
       Umin = uw < Umin ? uw : Umin;
     }
   }
-  if (lane == 0) {
-    a.U[q] = __float_as_uint(Umin);
-    a.hbase[q] = Umin;
+  // the waves' k smallest keys (kEmpty past a short list)
+#pragma unroll
+  for (int r = 0; r < R; r++) keys[wave][64 * r + lane] = (64 * r + lane < a.k) ? wl.e[r] : kEmpty;
+  if (threadIdx.x == 0) kth_sh = kEmpty;
+  __syncthreads();
+  // the key with exactly k - 1 smaller keys among the 4k (keys are distinct:
+  // they hold the row position)
+  const int nk = 4 * a.k;
+  for (int i = threadIdx.x; i < nk; i += 256) {
+    const uint64_t ki = keys[i / a.k][i % a.k];
+    if (ki == kEmpty) continue;
+    int below = 0;
+    for (int j = 0; j < nk; j++) below += keys[j / a.k][j % a.k] < ki ? 1 : 0;
+    if (below == a.k - 1) kth_sh = ki;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float U = U0;
+    if (kth_sh != kEmpty) {
+      const float uw = key_d(kth_sh) * a.upd_f;
+      U = uw < U ? uw : U;
+    }
+    a.U[q] = __float_as_uint(U);
+    a.hbase[q] = U;
   }
 }
 
@@ -618,29 +635,10 @@ static void launch_front_t(const SearchArgs& a, hipStream_t st, hipEvent_t* ev) 
   mark(ev, 1, st);
   k_leaf_lb<<<gl, 256, 0, st>>>(a);
   mark(ev, 2, st);
-  k_seed<NIT, R><<<nblk(a.B, 4), 256, 0, st>>>(a);
+  k_seed<NIT, R><<<(unsigned)a.B, 256, 0, st>>>(a);
   mark(ev, 3, st);
   (void)launch_leaf_mask(a, st);
   mark(ev, 4, st);
-}
-
-// the same masks in sorted-slot order (smask[blk][s] for the query in slot
-// s, zero past B), straight from the stored bounds: the lists' rebuild from
-// a tightened U needs no query-order copy
-__global__ __launch_bounds__(256) void k_slot_masks(SearchArgs a, int Spad, const int32_t* __restrict__ perm,
-                                                    uint64_t* __restrict__ smask) {
-  const int64_t blk = blockIdx.x;
-  const int s = blockIdx.y * 256 + threadIdx.x;
-  if (s >= Spad) return;
-  smask[blk * Spad + s] = s < a.B ? block_mask(a, blk, perm[s]) : 0ull;
-}
-
-sofa_status launch_slot_masks(const SearchArgs& a, int Spad, const int32_t* perm, uint64_t* smask,
-                              hipStream_t st) {
-  const dim3 gm((unsigned)a.n_blocks, nblk(Spad, 256));
-  k_slot_masks<<<gm, 256, 0, st>>>(a, Spad, perm, smask);
-  SOFA_HIP(hipGetLastError());
-  return SOFA_OK;
 }
 
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st) {

@@ -30,8 +30,12 @@ struct MlpAct {
 
 size_t mlp_act_floats(const MlpDims& d, int64_t B);
 MlpAct act_views(float* base, const MlpDims& d, int64_t B);
+// radii of a search's queries into U0; scratch: model_radius_scratch_floats
+// floats (none when the fused inference kernel holds the activations in LDS)
 sofa_status launch_model_radius(const sofa_radius* m, const float* pool, int64_t ld, int64_t B,
                                 float* scratch, float* U0, hipStream_t st);
+bool infer_fits(const MlpDims& d);
+size_t model_radius_scratch_floats(const MlpDims& d, int64_t B);
 
 }  // namespace sofa
 

@@ -49,10 +49,6 @@ sofa_status launch_search(const SearchArgs& a, int64_t* out_ids, float* out_d, i
 sofa_status launch_front(const SearchArgs& a, hipStream_t st, hipEvent_t* ev);
 // survivor masks from the stored envelope bounds and the current U
 sofa_status launch_leaf_mask(const SearchArgs& a, hipStream_t st);
-// the same masks written in sorted-slot order: smask[blk][s] for query
-// perm[s], zero for s >= B (Spad slots)
-sofa_status launch_slot_masks(const SearchArgs& a, int Spad, const int32_t* perm, uint64_t* smask,
-                              hipStream_t st);
 // approximate search: the front, then the M (<= kApproxMax) leaves of
 // smallest envelope bound per query (B x kApproxMax leaf ids in `leaves`)
 // scanned exactly; launch_finalize ranks what they hold

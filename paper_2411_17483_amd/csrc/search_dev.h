@@ -34,6 +34,25 @@ __device__ __forceinline__ float lb_leaf(const float* T, const uint4& sq, const 
   return s;
 }
 
+// FP16 code of a non-negative bound, rounded down; +inf stays +inf, finite
+// values above the largest code clamp to it
+__device__ __forceinline__ uint16_t f16_down(float x) {
+  const uint32_t f = __float_as_uint(x);
+  if (f & 0x80000000u) return 0;                // cannot occur; 0 keeps the leaf
+  if (f >= 0x7F800000u) return 0x7C00u;         // +inf
+  const int e = (int)(f >> 23) - 127 + 15;
+  if (e >= 31) return 0x7BFFu;
+  if (e <= 0) return (uint16_t)(x * 0x1p24f);   // subnormal: floor(x / 2^-24), exact scaling
+  return (uint16_t)((e << 10) | ((f >> 13) & 0x3FFu));
+}
+
+// the FP16 code a stored envelope bound must not exceed for its leaf to
+// survive U: U widened by the slack of the FP32 bound sum, rounded down (the
+// codes of non-negative values order like the values)
+__device__ __forceinline__ uint32_t u_code(const SearchArgs& a, int q) {
+  return f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
+}
+
 __device__ __forceinline__ float key_d(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
 constexpr uint64_t kEmpty = ~0ull;
 
@@ -192,13 +211,35 @@ __device__ __forceinline__ void load_q(const float* qrow, int li, float4 (&q)[NI
 
 // FP64 squared distance in time order with no contraction: the same
 // arithmetic as the ranking key of record.
+// q and x 16-byte aligned, n a multiple of 4.  The sum runs over t in order
+// (no contraction); the loads are issued kExactU float4 pairs at a time, so
+// that one thread's 2n loads do not wait one by one.
+constexpr int kExactU = 8;
 __device__ inline double exact_d2(const float* __restrict__ q, const float* __restrict__ x, int n) {
 #pragma clang fp contract(off)
+  const float4* qv = reinterpret_cast<const float4*>(q);
+  const float4* xv = reinterpret_cast<const float4*>(x);
   double s = 0.0;
-  for (int t = 0; t < n; t++) {
-    double d = (double)q[t] - (double)x[t];
-    double sq = d * d;
-    s = s + sq;
+  for (int t0 = 0; t0 < n; t0 += 4 * kExactU) {
+    float4 a[kExactU], b[kExactU];
+#pragma unroll
+    for (int u = 0; u < kExactU; u++) {
+      const bool in = t0 + 4 * u < n;
+      a[u] = in ? qv[t0 / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      b[u] = in ? xv[t0 / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kExactU; u++) {
+      if (t0 + 4 * u >= n) break;
+      const float qs[4] = {a[u].x, a[u].y, a[u].z, a[u].w};
+      const float xs[4] = {b[u].x, b[u].y, b[u].z, b[u].w};
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const double d = (double)qs[e] - (double)xs[e];
+        const double sq = d * d;
+        s = s + sq;
+      }
+    }
   }
   return s;
 }

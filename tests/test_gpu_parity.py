@@ -791,6 +791,25 @@ def test_mlp_forward_matches_oracle(gpu_lib):
     assert np.all(np.abs(y2 - ref2) <= bound2), np.max(np.abs(y2 - ref2) / bound2)
 
 
+def test_radius_predict_is_forward_plus_margin(gpu_lib):
+    """The radii of sofa_radius_predict come from one fused kernel (the one
+    a search uses for its radii) that repeats the forward kernels'
+    operations in their order: they are exp(y + margin) of sofa_radius_forward's
+    y bit for bit, with standardisation, on 301 rows (not a multiple of the
+    kernel's 4 rows per workgroup) and on a single row."""
+    flat = _mlp_params(1)
+    m = gpu_lib.RadiusModel(k=10)
+    mu = np.linspace(-1, 1, 32).astype(np.float32)
+    sd = np.linspace(0.5, 2, 32).astype(np.float32)
+    m.set(params=flat, mu=mu, sd=sd, margin=0.1875)
+    for B in (301, 1):
+        x, _ = _mlp_data(6 + B, B)
+        y = m.forward(_t(x)).cpu().numpy()
+        r = m.predict(_t(x)).cpu().numpy()
+        ref = np.exp(y.astype(np.float64) + 0.1875).astype(np.float32)
+        assert np.array_equal(r, ref), np.max(np.abs(r / ref - 1))
+
+
 def test_mlp_gradients_match_oracle(gpu_lib):
     """Every gradient element and the loss against the FP64 oracle, within
     the element-wise FP32 error bound of tests/mlp_bound.py."""
@@ -915,9 +934,8 @@ def test_tile_pair_counters(gpu_lib):
 
 @pytest.mark.parametrize("k", [1, 10])
 def test_prune_batch_above_1024_queries(gpu_lib, k):
-    """A batch of 1,500 queries (1,536 slots: the per-leaf lists are built
-    from mask rows staged in two pieces) on both prune tiers, with and
-    without list rebuilds (k = 10 rebuilds before its last two passes, k = 1
+    """A batch of 1,500 queries (1,536 slots, 24 query groups per leaf at
+    most) on both prune tiers, with and without list rebuilds (k = 10 rebuilds before its last two passes, k = 1
     without a radius before its last), against the oracle."""
     N, n, B = 12000 + 13, 64, 1500
     X = synth.collection(N, n, "mix", seed=341)
@@ -947,8 +965,9 @@ def test_prune_lengths_with_padding(gpu_lib, n):
 
 
 def test_largest_batch(gpu_lib):
-    """The largest batch a call takes, 65,535 queries (65,536 slots of 64:
-    64 staged pieces of mask rows), on the plain scan and both prune tiers
+    """The largest batch a call takes, 65,535 queries (65,536 slots: the
+    list builds stage each sub-block's survivor bits in 16 pieces of 4,096
+    slots, twice), on the plain scan and both prune tiers
     against the oracle; one more query is refused."""
     N, n, B = 2000 + 3, 64, 65535
     X = synth.collection(N, n, "mix", seed=351)
