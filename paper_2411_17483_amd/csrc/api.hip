@@ -587,7 +587,7 @@ Layout layout_for(const sofa_index* ix, int64_t B, int k, const sofa_knn_params*
   sz[W_RCNT] = (size_t)B * 4;
   sz[W_FLAG] = (size_t)B * 8;
   sz[W_STAT] = (size_t)B * 4;
-  sz[W_STATS] = 8 * 8;
+  sz[W_STATS] = (size_t)kStatShards * kStatSlots * 8;
   sz[W_BAD] = 4;
   sz[W_HIST] = (size_t)B * 256 * 4;
   sz[W_HBASE] = (size_t)B * 4;
@@ -785,7 +785,7 @@ constexpr int kScratchDevices = 64;
 constexpr int64_t kScratchMaxB = SOFA_NOALLOC_MAX_QUERIES;  // bounds the host read-back buffer
 static std::mutex g_scratch_mu;         // one no-alloc call at a time
 static char* g_scratch_dev[kScratchDevices];
-static uint8_t g_scratch_back[kScratchMaxB * 12 + 4096];
+static uint8_t g_scratch_back[kScratchMaxB * 12 + kStatShards * kStatSlots * 8 + 4096];
 
 static sofa_status scratch_of_current_device(char** out) {
   int dev = -1;
@@ -900,7 +900,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   int32_t* status = (int32_t*)at(W_STAT);
   unsigned* bad = (unsigned*)at(W_BAD);
   SOFA_TRY(launch_fill_u32(bad, 0u, 1, st));
-  SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 16, st));
+  SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 2 * kStatShards * kStatSlots, st));
   hipEvent_t* ev = mem.ev;
   if (ev) (void)hipEventRecord(ev[0], st);
   // approximate search: no radius, prune or fallback applies
@@ -995,8 +995,14 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   const float* hu0 = reinterpret_cast<const float*>(hb + (lay.off[W_U0] - back0));
   const uint32_t* hu = reinterpret_cast<const uint32_t*>(hb + (lay.off[W_U] - back0));
   const unsigned hbad = *reinterpret_cast<const unsigned*>(hb + (lay.off[W_BAD] - back0));
-  const unsigned long long* hstats =
-      reinterpret_cast<const unsigned long long*>(hb + (lay.off[W_STATS] - back0));
+  // the counters' shards: sums (slot 4: the maximum)
+  unsigned long long hstats[kStatSlots] = {};
+  {
+    const unsigned long long* sh = reinterpret_cast<const unsigned long long*>(hb + (lay.off[W_STATS] - back0));
+    for (int c = 0; c < kStatShards; c++)
+      for (int i = 0; i < kStatSlots; i++)
+        hstats[i] = i == 4 ? std::max(hstats[i], sh[c * kStatSlots + i]) : hstats[i] + sh[c * kStatSlots + i];
+  }
   if (hbad) return set_error(SOFA_EINVAL, "the queries contain non-finite values");
   if (ev && stats.queries == 0) {
     float t[6] = {0, 0, 0, 0, 0, 0};
@@ -1209,7 +1215,7 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   hipStream_t st = S(stream);
   const int64_t G = (B + kGroup - 1) / kGroup;
   DevBuf qp, pool, qn, tab, sq, u0, bad, masks, lcnt, loff, lslot, sc, perm, qb, qmeta, qscale,
-      ctr, U, stats;
+      ctr, U;
   SOFA_TRY(qp.alloc((size_t)B * ix->n_pad * 4, st));
   SOFA_TRY(pool.alloc((size_t)B * ix->bins.ncol_pool * 4, st));
   SOFA_TRY(qn.alloc((size_t)B * 8, st));
@@ -1228,11 +1234,9 @@ static sofa_status prune_lower_bounds(const sofa_index* ix, const float* d_queri
   SOFA_TRY(qmeta.alloc((size_t)G * kGroup * 16, st));
   SOFA_TRY(qscale.alloc((size_t)G * kGroup * 4, st));
   SOFA_TRY(ctr.alloc(64, st));
-  SOFA_TRY(stats.alloc(64, st));
   SOFA_TRY(launch_fill_u32(bad.as<uint32_t>(), 0u, 1, st));
-  SOFA_TRY(launch_fill_u32(stats.as<uint32_t>(), 0u, 16, st));
   SearchArgs a{};
-  a.stats = stats.as<unsigned long long>();
+  a.stats = nullptr;  // no statistics for the inspection call
   a.X = ix->X.as<float>();
   a.N = ix->N;
   a.n = ix->n;

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const uint32_t cnt_all = b.ccnt[q];
   const uint32_t cnt = cnt_all < (uint32_t)b.cap ? cnt_all : (uint32_t)b.cap;
-  if (z == 0 && threadIdx.x == 0 && a.stats) atomicMax(a.stats + 4, (unsigned long long)cnt_all);
+  if (z == 0 && threadIdx.x == 0) stat_max(a, 4, (unsigned long long)cnt_all);
   if ((uint32_t)(z * 4 + wave) * 64 >= cnt) return;
   float4 qr[NIT];
   load_q<NIT>(a.Qp + (int64_t)q * a.n_pad, li, qr);
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void k_refine_cand(SearchArgs a, Bf16Args b) {
     }
   }
   flush_wave_list<R>(a, q, wl, Umin, lane);
-  if (lane == 0 && st_refined && a.stats) atomicAdd(a.stats + 2, st_refined);
+  if (lane == 0) stat_add(a, 2, st_refined);
 }
 
 // ----------------------------------------------------------------------------

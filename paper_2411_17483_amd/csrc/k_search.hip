@@ -186,8 +186,7 @@ __global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
     if (lane == 0) vis[wave] = visited;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const unsigned long long v = vis[0] + vis[1] + vis[2] + vis[3];
-      if (v) atomicAdd(a.stats + 0, v);
+      stat_add(a, 0, vis[0] + vis[1] + vis[2] + vis[3]);
     }
   }
 }
@@ -388,8 +387,8 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
     __syncthreads();
   }
   if (lane == 0) {
-    if (st_words && a.stats) atomicAdd(a.stats + 1, st_words);
-    if (st_refined && a.stats) atomicAdd(a.stats + 2, st_refined);
+    stat_add(a, 1, st_words);
+    stat_add(a, 2, st_refined);
   }
 }
 
@@ -805,7 +804,7 @@ __global__ __launch_bounds__(256) void k_approx_scan(SearchArgs a, int M, const 
   }
   if (lane == 0 && Umin < U_in) atomicMin(a.U + q, __float_as_uint(Umin));
   flush_wave_list<R>(a, q, wl, Umin, lane);
-  if (lane == 0 && scanned && a.stats) atomicAdd(a.stats + 2, scanned);
+  if (lane == 0) stat_add(a, 2, scanned);
 }
 
 template <int NIT, int R>

@@ -458,9 +458,11 @@ void k_bf16_tiles(SearchArgs a, Bf16Args b) {
     }
     a_chunk = has_following ? next_chunk : (int64_t)-1;
   }
-  if (lane == 0 && st_pairs && a.stats) atomicAdd(a.stats + 3, st_pairs);
-  if (threadIdx.x == 0 && st_needed && a.stats) atomicAdd(a.stats + 5, st_needed);
-  if (threadIdx.x == 0 && st_rows && a.stats) atomicAdd(a.stats + 6, st_rows);
+  if (lane == 0) stat_add(a, 3, st_pairs);
+  if (threadIdx.x == 0) {
+    stat_add(a, 5, st_needed);
+    stat_add(a, 6, st_rows);
+  }
 }
 
 // launch over the supported (precision, K steps) pairs.  FP8 rows of 1024

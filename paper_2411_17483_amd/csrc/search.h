@@ -5,6 +5,12 @@
 
 namespace sofa {
 
+// Search statistics are kept in kStatShards copies of kStatSlots counters,
+// each copy on its own 128-byte line; a workgroup adds to the copy its
+// block index selects, and the host sums the copies (slot 4: the maximum).
+// Thousands of workgroups adding to one counter would queue on one address.
+constexpr int kStatSlots = 16, kStatShards = 64;
+
 struct SearchArgs {
   // index (leaf order)
   const float* X;        // N x n_pad
@@ -31,9 +37,10 @@ struct SearchArgs {
   uint32_t* hist;        // B x 256 counts of flushed candidate distances
   float* hbase;          // B histogram range [0, hbase) (the bound after the seed)
   const uint32_t* cevmin;  // nullable: B smallest lower bound of a dropped BF16 candidate
-  unsigned long long* stats;  // [0] leaves visited [1] words checked [2] rows refined
-                              // [3] tile pairs computed [4] most candidates of a query
-                              // [5] tile pairs needed [6] prune-copy rows streamed
+  unsigned long long* stats;  // kStatShards x kStatSlots (nullable): [0] leaves visited
+                              // [1] words checked [2] rows refined [3] tile pairs computed
+                              // [4] most candidates of a query [5] tile pairs needed
+                              // [6] prune-copy rows streamed
   // factors derived from the FP32 error bounds
   float lb_f, band_f, upd_f, abandon_f;
   double eta_x;

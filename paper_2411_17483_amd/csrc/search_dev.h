@@ -53,6 +53,19 @@ __device__ __forceinline__ uint32_t u_code(const SearchArgs& a, int q) {
   return f16_down(__uint_as_float(a.U[q]) * (1.0f + 0x1p-16f));
 }
 
+__device__ __forceinline__ unsigned long long* stat_ptr(const SearchArgs& a, int slot) {
+  const unsigned shard = (blockIdx.x + 13u * blockIdx.y) % (unsigned)kStatShards;
+  return a.stats + shard * kStatSlots + slot;
+}
+__device__ __forceinline__ void stat_add(const SearchArgs& a, int slot, unsigned long long v) {
+  if (a.stats && v) atomicAdd(stat_ptr(a, slot), v);
+}
+__device__ __forceinline__ void stat_max(const SearchArgs& a, int slot, unsigned long long v) {
+  if (!a.stats) return;
+  unsigned long long* p = stat_ptr(a, slot);
+  if (v > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, v);
+}
+
 __device__ __forceinline__ float key_d(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
 constexpr uint64_t kEmpty = ~0ull;
 
