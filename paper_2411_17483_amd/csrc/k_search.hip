@@ -196,9 +196,11 @@ __global__ __launch_bounds__(256) void k_leaf_mask(SearchArgs a) {
 // k smallest keys then give the k-th smallest key of the leaf (every key
 // below it is among some wave's k smallest), so U is the same as one wave
 // scanning the whole leaf would set.
+static_assert(kMaxK + 16 <= 64 * 2, "a wave list of two registers per lane holds every k's keys");
+
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
-  __shared__ uint64_t keys[4][64 * R];
+  __shared__ uint64_t keys[4 * 64 * R];  // wave w's rank r at w * k + r
   __shared__ uint64_t kth_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int q = blockIdx.x;
@@ -249,17 +251,18 @@ __global__ __launch_bounds__(256) void k_seed(SearchArgs a) {
   }
   // the waves' k smallest keys (kEmpty past a short list)
 #pragma unroll
-  for (int r = 0; r < R; r++) keys[wave][64 * r + lane] = (64 * r + lane < a.k) ? wl.e[r] : kEmpty;
+  for (int r = 0; r < R; r++)
+    if (64 * r + lane < a.k) keys[wave * a.k + 64 * r + lane] = wl.e[r];
   if (threadIdx.x == 0) kth_sh = kEmpty;
   __syncthreads();
   // the key with exactly k - 1 smaller keys among the 4k (keys are distinct:
   // they hold the row position)
   const int nk = 4 * a.k;
   for (int i = threadIdx.x; i < nk; i += 256) {
-    const uint64_t ki = keys[i / a.k][i % a.k];
+    const uint64_t ki = keys[i];
     if (ki == kEmpty) continue;
     int below = 0;
-    for (int j = 0; j < nk; j++) below += keys[j / a.k][j % a.k] < ki ? 1 : 0;
+    for (int j = 0; j < nk; j++) below += keys[j] < ki ? 1 : 0;
     if (below == a.k - 1) kth_sh = ki;
   }
   __syncthreads();
