@@ -285,6 +285,12 @@ constexpr int kSub = 8;                        // leaves per work item
 constexpr int kSubPerBlock = kLeavesPerItem / kSub;
 constexpr int kQueues = 8;
 
+// early-abandon check period of the plain path's distances, in 64-element
+// steps.  Checking every 64 or 128 elements puts each row's later loads
+// behind a 16-lane reduction and a compare, and measured slower on 10M x 256
+// (3.5k and 4.0k against 4.2k queries/s) although most refined rows are far.
+constexpr int kPlainCheck = 4;
+
 template <int NIT, int R>
 __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
   __shared__ float T[kTable];
@@ -355,10 +361,10 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
           }
           const int ca = c0[g], cb = c1[g];
           const float abandon = Umin * a.abandon_f;
-          float da = dist4<NIT>(a.X + (base + (ca >= 0 ? ca : 0)) * a.n_pad, ca >= 0, qr, li, abandon);
+          float da = dist4<NIT, kPlainCheck>(a.X + (base + (ca >= 0 ? ca : 0)) * a.n_pad, ca >= 0, qr, li, abandon);
           float db = INFINITY;
           if (c1[0] >= 0)
-            db = dist4<NIT>(a.X + (base + (cb >= 0 ? cb : 0)) * a.n_pad, cb >= 0, qr, li, abandon);
+            db = dist4<NIT, kPlainCheck>(a.X + (base + (cb >= 0 ? cb : 0)) * a.n_pad, cb >= 0, qr, li, abandon);
           float band = Umin * a.band_f;
           uint64_t ins = __ballot(li == 0 && ((ca >= 0 && da <= band) || (cb >= 0 && db <= band)));
           while (ins) {

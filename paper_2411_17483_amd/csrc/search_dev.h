@@ -115,10 +115,10 @@ struct WaveList {
 
 // FP32 squared distance of 4 rows at once: lane group g = lane/16 handles the
 // row at xrow (when active); lane li = lane%16 owns elements li*4 + 64*it.
-// Partial sums are checked every 256 elements against `abandon`; a group whose
-// partial exceeds it stops loading.  Returns the group's sum (all 16 lanes) or
-// +inf when abandoned/inactive.
-template <int NIT>
+// Partial sums are checked every 64 CHK elements against `abandon`; a group
+// whose partial exceeds it stops loading.  Returns the group's sum (all 16
+// lanes) or +inf when abandoned/inactive.
+template <int NIT, int CHK = 4>
 __device__ __forceinline__ float dist4(const float* __restrict__ xrow, bool active,
                                        const float4 (&q)[NIT], int li, float abandon) {
   float acc = 0.0f;
@@ -133,7 +133,7 @@ __device__ __forceinline__ float dist4(const float* __restrict__ xrow, bool acti
       acc = fmaf(d2, d2, acc);
       acc = fmaf(d3, d3, acc);
     }
-    if ((it & 3) == 3 && it + 1 < NIT) {
+    if (it % CHK == CHK - 1 && it + 1 < NIT) {
       float p = acc;
       p += __shfl_xor(p, 8);
       p += __shfl_xor(p, 4);
