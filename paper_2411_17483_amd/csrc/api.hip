@@ -902,12 +902,28 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
   a.eta_x = ix->eta_x;
   int32_t* status = (int32_t*)at(W_STAT);
   unsigned* bad = (unsigned*)at(W_BAD);
-  SOFA_TRY(launch_fill_u32(bad, 0u, 1, st));
-  SOFA_TRY(launch_fill_u32((uint32_t*)a.stats, 0u, 2 * kStatShards * kStatSlots, st));
+  const int approx = p ? p->approx_leaves : 0;
+  const bool bf = !approx && p && (p->prune == 1 || p->prune == 2);
+  {
+    // the flag, the statistics and (prune) the dropped-candidate bounds and
+    // per-query leaf counts cleared in one launch
+    FillRanges f{};
+    f.p[0] = bad;
+    f.n[0] = 1;
+    f.p[1] = (uint32_t*)a.stats;
+    f.n[1] = 2 * kStatShards * kStatSlots;
+    if (bf) {
+      f.p[2] = (uint32_t*)at(W_CEV);
+      f.n[2] = B;
+      f.v[2] = 0xFFFFFFFFu;
+      f.p[3] = (uint32_t*)at(W_QCNT);
+      f.n[3] = B;
+    }
+    SOFA_TRY(launch_fill_ranges(f, st));
+  }
   hipEvent_t* ev = mem.ev;
   if (ev) (void)hipEventRecord(ev[0], st);
   // approximate search: no radius, prune or fallback applies
-  const int approx = p ? p->approx_leaves : 0;
   SOFA_TRY(launch_prepare(a, d_q, (p && !approx) ? p->d_radius : nullptr, ix->bins, (float*)at(W_POOL),
                           (double*)at(W_QN), bad, st));
   const bool use_model = !approx && p && p->radius_model && !p->d_radius;
@@ -915,7 +931,6 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_model_radius(p->radius_model, (const float*)at(W_POOL), ix->bins.ncol_pool, B,
                                  (float*)at(W_MLP), a.U0, st));
   const bool has_radius = !approx && p && (p->d_radius || use_model);
-  const bool bf = !approx && p && (p->prune == 1 || p->prune == 2);
   int bf_passes = 0;
   if (approx > 0) {
     // no seed: its leaf (chosen on the FP32 bound) need not be among the
@@ -927,8 +942,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     SOFA_TRY(launch_search(a, d_ids, d_d, status, st, ev));
   } else {
     uint32_t* cev = (uint32_t*)at(W_CEV);
-    a.cevmin = cev;
-    SOFA_TRY(launch_fill_u32(cev, 0xFFFFFFFFu, B, st));
+    a.cevmin = cev;  // cleared with the flag above
     SOFA_TRY(launch_front(a, st, ev));
     Bf16Args b{};
     b.prec = p->prune;
@@ -957,7 +971,7 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     b.cevmin = cev;
     b.cap = bf16_cap(p, k, B);
     b.counter = (uint32_t*)at(W_BCTR);
-    SOFA_TRY(launch_bf16_queries(a, b, st));
+    SOFA_TRY(launch_bf16_queries(a, b, st, false));  // qcount cleared above
     const int64_t n_chunks = (ix->N + 255) / 256;
     const int sampling = p->sampling;
     if (sampling == 2) {
@@ -975,8 +989,8 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
       const int relist_from = many ? n_passes - 2 : (has_radius ? n_passes : n_passes - 1);
       int64_t prev = 0;
       for (int ps = 0; ps < n_passes; ps++) {
-        if (ps >= relist_from) SOFA_TRY(launch_bf16_relist(a, b, st));
         const int64_t sp = strides[ps];
+        if (ps >= relist_from) SOFA_TRY(launch_bf16_relist(a, b, sp, prev, st));
         const int64_t n_sp = (n_chunks + sp - 1) / sp;
         const int64_t n_prev = prev ? (n_chunks + prev - 1) / prev : 0;
         SOFA_TRY(launch_bf16_pass(a, b, sp, 0, prev ? 0 : 1, n_sp - n_prev, prev ? (int)(prev / sp) : 0, st,

@@ -45,10 +45,14 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
 // fragment), cscale per 256-row chunk, per-row meta and per-leaf maxima
 sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                              uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st);
-sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st);
+// clear_qcount false: b.qcount (B entries) is already zero
+sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st, bool clear_qcount = true);
 // rebuild the (query, leaf) lists from the current bounds U, keeping the slot
-// order: later passes see only the pairs that still survive
-sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st);
+// order: later passes see only the pairs that still survive.  Only the leaves
+// of the next pass (the multiples of sp that are not multiples of prev, when
+// prev > 0) get lists; the others are left empty.
+sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, int64_t sp, int64_t prev,
+                               hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
 // the tile kernel over b's work items on a persistent grid (dump: write
 // every pair's lower bound to b.dump instead of pruning)

@@ -384,10 +384,12 @@ __device__ __forceinline__ void stage_sub_bits(const SearchArgs& a, const int32_
   }
 }
 
+// sp > 0: only the leaves of the chunks that a pass over the multiples of sp
+// (not of prev, when prev > 0) takes get their lists; the others get none
 template <bool FROM_CODES>
 __global__ __launch_bounds__(256) void k_lists(SearchArgs a, int Spad, const int32_t* __restrict__ perm,
                                                uint32_t* __restrict__ lcnt, int64_t* __restrict__ loff,
-                                               uint16_t* __restrict__ lslot) {
+                                               uint16_t* __restrict__ lslot, int64_t sp, int64_t prev) {
   __shared__ uint16_t sm[kListPiece];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // Workgroups go to the 8 XCDs round robin, and the four sub-blocks of a
@@ -402,7 +404,15 @@ __global__ __launch_bounds__(256) void k_lists(SearchArgs a, int Spad, const int
   const int64_t leaf0 = (blk * kSubPerBlock + sub_in) * kSubLeaves + 4 * wave;  // this wave's first leaf
   // leaves of the sub-block that exist
   const int64_t nl = a.n_leaves - (blk * kSubPerBlock + sub_in) * kSubLeaves;
-  const uint32_t valid = nl >= kSubLeaves ? 0xFFFFu : ((1u << (nl > 0 ? nl : 0)) - 1u);
+  uint32_t valid = nl >= kSubLeaves ? 0xFFFFu : ((1u << (nl > 0 ? nl : 0)) - 1u);
+  if (sp > 0) {
+    // lane j < 16 tests leaf j of the sub-block: its L / 256 chunks
+    const int64_t per = a.L / 256, c0 = ((blk * kSubPerBlock + sub_in) * kSubLeaves + lane) * per;
+    bool need = false;
+    if (lane < kSubLeaves)
+      for (int64_t c = c0; c < c0 + per; c++) need = need || (c % sp == 0 && (prev <= 0 || c % prev != 0));
+    valid &= (uint32_t)__ballot(need) & 0xFFFFu;
+  }
   const uint64_t lt = (1ull << lane) - 1ull;
   uint32_t c[4] = {0u, 0u, 0u, 0u};
   for (int s0 = 0; s0 < Spad; s0 += kListPiece) {
@@ -643,21 +653,23 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
 
 // per leaf, the slots of the queries that need it
 template <bool FROM_CODES>
-static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st, int64_t sp, int64_t prev) {
   const int64_t n_sub = a.n_blocks * kSubPerBlock;
-  k_lists<FROM_CODES><<<(unsigned)n_sub, 256, 0, st>>>(a, b.G * kGroup, b.perm, b.lcnt, b.loff, b.lslot);
+  k_lists<FROM_CODES><<<(unsigned)n_sub, 256, 0, st>>>(a, b.G * kGroup, b.perm, b.lcnt, b.loff, b.lslot, sp,
+                                                       prev);
 }
 
-sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, hipStream_t st) {
+sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, int64_t sp, int64_t prev,
+                               hipStream_t st) {
   // straight from the stored bound codes under the tightened U, in slot order
-  launch_lists<true>(a, b, st);
+  launch_lists<true>(a, b, st, sp, prev);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
 
-sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st) {
+sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st, bool clear_qcount) {
   const int B = a.B;
-  SOFA_TRY(launch_fill_u32(b.qcount, 0u, B, st));
+  if (clear_qcount) SOFA_TRY(launch_fill_u32(b.qcount, 0u, B, st));
   {
     const int64_t sl = a.n_blocks < 64 ? a.n_blocks : 64;
     dim3 grid(nblk(B, 256), (unsigned)(sl > 0 ? sl : 1));
@@ -665,7 +677,7 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   }
   k_qsort<<<nblk(B, 4), 256, 0, st>>>(b.qcount, a.best, B, a.n_leaves, b.perm);
   const int Spad = b.G * kGroup;
-  launch_lists<false>(a, b, st);
+  launch_lists<false>(a, b, st, 0, 0);
   if (b.prec == 2) {
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
     k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,

@@ -402,14 +402,45 @@ __global__ __launch_bounds__(256) void k_refine(SearchArgs a) {
 }
 
 // 5. finalize: FP64 recomputation of the in-band candidates and ranking.
+// The rows are staged in LDS a batch at a time, every thread's loads in
+// flight together; then one thread per row sums its distance in dimension
+// order.  (A thread reading its row from memory itself waits for one round
+// trip per eight float4 loads.)
 constexpr int kSMax = 1024;
+constexpr int kFinStageFloats = 4096;  // staged row values per batch (16 KB)
+static_assert(kFinStageFloats >= kMaxN, "at least one row per batch");
+
+// exact_d2 over rows staged in LDS: the same operations in the same order,
+// one float4 at a time (few registers: four workgroups fit on a SIMD set)
+__device__ __forceinline__ double lds_d2(const float4* q, const float4* x, int n) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  for (int i = 0; i < n / 4; i++) {
+    const float4 a = q[i], b = x[i];
+    const double d0 = (double)a.x - (double)b.x;
+    const double s0 = d0 * d0;
+    s = s + s0;
+    const double d1 = (double)a.y - (double)b.y;
+    const double s1 = d1 * d1;
+    s = s + s1;
+    const double d2 = (double)a.z - (double)b.z;
+    const double s2 = d2 * d2;
+    s = s + s2;
+    const double d3 = (double)a.w - (double)b.w;
+    const double s3 = d3 * d3;
+    s = s + s3;
+  }
+  return s;
+}
 
 __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restrict__ out_ids,
                                                   float* __restrict__ out_d,
                                                   int32_t* __restrict__ status) {
   __shared__ uint32_t spos[kSMax];
   __shared__ double sd[kSMax];
-  __shared__ int64_t sid[kSMax];
+  __shared__ int32_t sid[kSMax];
+  __shared__ float4 sq4[kMaxN / 4];
+  __shared__ float4 sx4[kFinStageFloats / 4 + kFinStageFloats / 64];  // rows padded by one float4
   __shared__ uint32_t scount;
   __shared__ int sstat;
   const int q = blockIdx.x, t = threadIdx.x;
@@ -442,17 +473,36 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
     if (t == 0) status[q] = ovf ? ovf : 5;
     return;
   }
-  const float* qrow = a.Qp + (int64_t)q * a.n_pad;
-  for (uint32_t i = t; i < s; i += 256) {
-    uint32_t pos = spos[i];
-    sd[i] = exact_d2(qrow, a.X + (int64_t)pos * a.n_pad, a.n);
-    sid[i] = a.ids[pos];
+  // n_pad is a power of two >= 64, so a row is 2^lg float4
+  const int nq4 = a.n_pad / 4, lg = __builtin_ctz((unsigned)nq4);
+  const float4* q4 = reinterpret_cast<const float4*>(a.Qp + (int64_t)q * a.n_pad);
+  const float4* x4 = reinterpret_cast<const float4*>(a.X);
+  for (int i = t; i < nq4; i += 256) sq4[i] = q4[i];
+  const uint32_t per = (uint32_t)(kFinStageFloats / a.n_pad);  // rows per batch
+  for (uint32_t r0 = 0; r0 < s; r0 += per) {
+    const int tot = (int)((s - r0 < per ? s - r0 : per) << lg);  // <= kFinStageFloats / 4
+    float4 v[kFinStageFloats / 4 / 256];
+#pragma unroll
+    for (int u = 0; u < kFinStageFloats / 4 / 256; u++) {
+      const int i = u * 256 + t < tot ? u * 256 + t : 0;  // past the batch: a repeat of its first value
+      v[u] = x4[((int64_t)spos[r0 + (i >> lg)] << lg) + (i & (nq4 - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < kFinStageFloats / 4 / 256; u++) {
+      const int i = u * 256 + t;
+      if (i < tot) sx4[i + (i >> lg)] = v[u];  // row r at r (nq4 + 1): rows start in different banks
+    }
+    __syncthreads();
+    if ((int)t < tot >> lg) {
+      sd[r0 + t] = lds_d2(sq4, sx4 + t * (nq4 + 1), a.n);
+      sid[r0 + t] = a.ids[spos[r0 + t]];
+    }
+    __syncthreads();  // the batch's rows are read before the next overwrites them
   }
-  __syncthreads();
   const int k = a.k;
   for (uint32_t i = t; i < s; i += 256) {
     double di = sd[i];
-    int64_t ii = sid[i];
+    int64_t ii = sid[i];  // the index's ids are 32-bit
     uint32_t rank = 0;
     for (uint32_t j = 0; j < s; j++) rank += (sd[j] < di || (sd[j] == di && sid[j] < ii)) ? 1u : 0u;
     if (rank < (uint32_t)k) {
@@ -615,6 +665,21 @@ __global__ __launch_bounds__(256) void k_all_lb(const float* __restrict__ tables
 // host launchers
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(p, v, n);
+  SOFA_HIP(hipGetLastError());
+  return SOFA_OK;
+}
+
+__global__ void k_fill_ranges(FillRanges f) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+  for (int r = 0; r < 4; r++)
+    for (int64_t i = i0; i < f.n[r]; i += stride) f.p[r][i] = f.v[r];
+}
+
+sofa_status launch_fill_ranges(const FillRanges& f, hipStream_t st) {
+  int64_t m = 0;
+  for (int r = 0; r < 4; r++) m = f.n[r] > m ? f.n[r] : m;
+  if (m > 0) k_fill_ranges<<<nblk(m, 256) < 1024 ? nblk(m, 256) : 1024u, 256, 0, st>>>(f);
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }

@@ -46,6 +46,13 @@ __host__ __device__ inline uint64_t sfa_key(const uint32_t (&s8)[16], int scheme
 
 // p[0..n) = v on stream st (k_search.hip)
 sofa_status launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// up to four fills p[i][0..n[i]) = v[i] in one launch (unused entries: n = 0)
+struct FillRanges {
+  uint32_t* p[4];
+  int64_t n[4];
+  uint32_t v[4];
+};
+sofa_status launch_fill_ranges(const FillRanges& f, hipStream_t st);
 
 // Index layout (k_build.hip): sort by the interleaved key, permute, envelopes.
 sofa_status launch_layout(sofa_index* ix, const float* X, const uint8_t* words_in,
