@@ -51,16 +51,31 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
                                                 uint4* __restrict__ sq) {
   __shared__ float v[16];
   __shared__ uint8_t sym[16];
+  // the breakpoints, staged with every thread's loads in flight at once (the
+  // binary search and the table read them from LDS)
+  __shared__ float4 bs4[kTable / 4];
+  const float* bs = reinterpret_cast<const float*>(bs4);
   const int q = blockIdx.x, t = threadIdx.x;
   const double eta_q = eta_per_norm * sqrt(qnorm2[q]) + 1e-30;
+  {
+    const float4* b4 = reinterpret_cast<const float4*>(beta32);
+    const int nb4 = l * kAlphaMax / 4;
+    float4 w[kTable / 4 / 256];
+#pragma unroll
+    for (int u = 0; u < kTable / 4 / 256; u++) w[u] = b4[u * 256 + t < nb4 ? u * 256 + t : 0];
+    // entries past the l rows hold a repeat of the first (never read)
+#pragma unroll
+    for (int u = 0; u < kTable / 4 / 256; u++) bs4[u * 256 + t] = w[u];
+  }
+  const float vq = (t < l) ? pool[(int64_t)q * ld_pool + sel[t]] : 0.0f;
+  __syncthreads();
   if (t < 16) {
-    float vv = (t < l) ? pool[(int64_t)q * ld_pool + sel[t]] : 0.0f;
-    v[t] = vv;
+    v[t] = vq;
     int s = 0;
     if (t < l) {
-      const float* bj = beta32 + t * kAlphaMax;
+      const float* bj = bs + t * kAlphaMax;
       for (int step = 128; step > 0; step >>= 1)
-        if (bj[s + step - 1] <= vv) s += step;
+        if (bj[s + step - 1] <= vq) s += step;
     }
     sym[t] = (uint8_t)s;
   }
@@ -76,8 +91,8 @@ __global__ __launch_bounds__(256) void k_tables(const float* __restrict__ pool, 
     float out = 0.0f;
     if (j < l) {
       double vj = (double)v[j];
-      double lo = (s == 0) ? -INFINITY : (double)beta32[j * kAlphaMax + s - 1] - eta;
-      double hi = (double)beta32[j * kAlphaMax + s] + eta;  // +inf beyond alpha-1
+      double lo = (s == 0) ? -INFINITY : (double)bs[j * kAlphaMax + s - 1] - eta;
+      double hi = (double)bs[j * kAlphaMax + s] + eta;  // +inf beyond alpha-1
       double gap = 0.0;
       if (lo - vj > gap) gap = lo - vj;
       if (vj - hi > gap) gap = vj - hi;
@@ -487,10 +502,12 @@ __global__ __launch_bounds__(256) void k_finalize(SearchArgs a, int64_t* __restr
       const int i = u * 256 + t < tot ? u * 256 + t : 0;  // past the batch: a repeat of its first value
       v[u] = x4[((int64_t)spos[r0 + (i >> lg)] << lg) + (i & (nq4 - 1))];
     }
+    // row r at r (nq4 + 1), so that rows start in different banks; values
+    // past the batch land past its rows (never read)
 #pragma unroll
     for (int u = 0; u < kFinStageFloats / 4 / 256; u++) {
       const int i = u * 256 + t;
-      if (i < tot) sx4[i + (i >> lg)] = v[u];  // row r at r (nq4 + 1): rows start in different banks
+      sx4[i + (i >> lg)] = v[u];
     }
     __syncthreads();
     if ((int)t < tot >> lg) {
