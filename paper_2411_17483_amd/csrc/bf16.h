@@ -50,7 +50,9 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
 // rebuild the (query, leaf) lists from the current bounds U, keeping the slot
 // order: later passes see only the pairs that still survive.  Only the leaves
 // of the next pass (the multiples of sp that are not multiples of prev, when
-// prev > 0) get lists; the others are left empty.
+// prev > 0) get lists; the others are left empty.  The same launch writes
+// that pass's slot terms and clears its counts (launch_bf16_pass with
+// terms_ready).
 sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, int64_t sp, int64_t prev,
                                hipStream_t st);
 sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipStream_t st);
@@ -59,8 +61,9 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
 sofa_status launch_bf16_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, bool dump, hipStream_t st);
 // ev (nullable): events recorded before the tile kernel, between it and the
 // candidate refinement, and after
+// terms_ready: a relist launched just before wrote this pass's slot terms
 sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
-                             int64_t stride, int64_t n_items, int skip, hipStream_t st,
+                             int64_t stride, int64_t n_items, int skip, bool terms_ready, hipStream_t st,
                              hipEvent_t* ev);
 
 }  // namespace sofa

@@ -333,6 +333,39 @@ constexpr int kListPiece = 4096;
 // its bound and codes) are issued together rather than one chain per slot
 constexpr int kStageU = 4;
 
+// per slot, for the current pass: with t = |x|^2 - 2P, a row survives when
+//   t <= a + b * max|xh| + c * max r_x + 2^-20 * max|x|^2   (leaf maxima)
+// where a = U lb_f - |q|^2 (1 - 2^-20), b = 2 (g |qh| + r_q), c = 2 |q|; .w = query id.
+// With ccnt (B entries) and the work counter given, they are cleared for the
+// pass as well.
+struct SlotTerms {
+  const float4* qmeta;
+  const int32_t* perm;
+  int B, Spad;
+  const uint32_t* U;
+  float lb_f, gam;
+  float4* slotc;     // null: nothing to do
+  uint32_t* ccnt;    // nullable
+  uint32_t* counter; // nullable
+};
+
+__device__ __forceinline__ void slot_terms(const SlotTerms& t, int s) {
+  if (t.counter && s == 0) *t.counter = 0u;
+  if (t.ccnt && s < t.B) t.ccnt[s] = 0u;
+  if (s >= t.Spad) return;
+  float4 c = make_float4(-INFINITY, 0.0f, 0.0f, __int_as_float(-1));
+  if (s < t.B) {
+    const int q = t.perm[s];
+    const float4 qm = t.qmeta[s];
+    const float u = __uint_as_float(t.U[q]);
+    c = make_float4(u * t.lb_f - qm.x * (1.0f - 0x1p-20f), 2.0f * (t.gam * qm.z + qm.y), 2.0f * qm.w,
+                    __int_as_float(q));
+  }
+  t.slotc[s] = c;
+}
+
+__global__ void k_slotc(SlotTerms t) { slot_terms(t, blockIdx.x * blockDim.x + threadIdx.x); }
+
 template <bool FROM_CODES>
 __device__ __forceinline__ void stage_sub_bits(const SearchArgs& a, const int32_t* __restrict__ perm,
                                                int64_t blk, int sub_in, uint32_t valid, int s0, int m,
@@ -386,11 +419,18 @@ __device__ __forceinline__ void stage_sub_bits(const SearchArgs& a, const int32_
 
 // sp > 0: only the leaves of the chunks that a pass over the multiples of sp
 // (not of prev, when prev > 0) takes get their lists; the others get none
+// With terms.slotc given, the launch also writes the slot terms (and clears
+// the counts) of the pass that follows: U does not change in between.
 template <bool FROM_CODES>
 __global__ __launch_bounds__(256) void k_lists(SearchArgs a, int Spad, const int32_t* __restrict__ perm,
                                                uint32_t* __restrict__ lcnt, int64_t* __restrict__ loff,
-                                               uint16_t* __restrict__ lslot, int64_t sp, int64_t prev) {
+                                               uint16_t* __restrict__ lslot, int64_t sp, int64_t prev,
+                                               SlotTerms terms) {
   __shared__ uint16_t sm[kListPiece];
+  if (terms.slotc) {
+    const int ns = terms.Spad > terms.B ? terms.Spad : terms.B;
+    for (int s = blockIdx.x * 256 + (int)threadIdx.x; s < ns; s += gridDim.x * 256) slot_terms(terms, s);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // Workgroups go to the 8 XCDs round robin, and the four sub-blocks of a
   // block read the four quarters of the same 128-byte rows of codes: the
@@ -438,30 +478,6 @@ __global__ __launch_bounds__(256) void k_lists(SearchArgs a, int Spad, const int
         lcnt[leaf0 + j] = c[j];
         loff[leaf0 + j] = (leaf0 + j) * a.B;
       }
-}
-
-// per slot, for the current pass: with t = |x|^2 - 2P, a row survives when
-//   t <= a + b * max|xh| + c * max r_x + 2^-20 * max|x|^2   (leaf maxima)
-// where a = U lb_f - |q|^2 (1 - 2^-20), b = 2 (g |qh| + r_q), c = 2 |q|; .w = query id
-// With ccnt (B entries) and the work counter given, the same launch clears
-// them for the pass.
-__global__ void k_slotc(const float4* __restrict__ qmeta, const int32_t* __restrict__ perm, int B,
-                        int Spad, const uint32_t* __restrict__ U, float lb_f, float gam,
-                        float4* __restrict__ slotc, uint32_t* __restrict__ ccnt,
-                        uint32_t* __restrict__ counter) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (counter && s == 0) *counter = 0u;
-  if (ccnt && s < B) ccnt[s] = 0u;
-  if (s >= Spad) return;
-  float4 c = make_float4(-INFINITY, 0.0f, 0.0f, __int_as_float(-1));
-  if (s < B) {
-    const int q = perm[s];
-    const float4 qm = qmeta[s];
-    const float u = __uint_as_float(U[q]);
-    c = make_float4(u * lb_f - qm.x * (1.0f - 0x1p-20f), 2.0f * (gam * qm.z + qm.y), 2.0f * qm.w,
-                    __int_as_float(q));
-  }
-  slotc[s] = c;
 }
 
 // BF16 query rows per sorted slot (n_pad values, zero past B); a lane's
@@ -652,17 +668,42 @@ sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_
 }
 
 // per leaf, the slots of the queries that need it
+// accumulation bound g = (K + K step) 2^-23 of the FP32 MFMA sums
+static float prune_gamma(const SearchArgs& a, const Bf16Args& b) {
+  const int step = b.prec == 2 ? 64 : 16;
+  return (float)(a.n_pad + step) * 0x1p-23f;
+}
+
+// the slot terms of the current U; the candidate counts (when `clear_ccnt`)
+// and the work counter cleared with them
+static SlotTerms slot_terms_of(const SearchArgs& a, const Bf16Args& b, bool clear_ccnt) {
+  SlotTerms t;
+  t.qmeta = b.qmeta;
+  t.perm = b.perm;
+  t.B = a.B;
+  t.Spad = b.G * kGroup;  // >= B
+  t.U = a.U;
+  t.lb_f = a.lb_f;
+  t.gam = prune_gamma(a, b);
+  t.slotc = b.slotc;
+  t.ccnt = clear_ccnt ? b.ccnt : nullptr;
+  t.counter = b.counter;
+  return t;
+}
+
 template <bool FROM_CODES>
-static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st, int64_t sp, int64_t prev) {
+static void launch_lists(const SearchArgs& a, const Bf16Args& b, hipStream_t st, int64_t sp, int64_t prev,
+                         const SlotTerms& terms) {
   const int64_t n_sub = a.n_blocks * kSubPerBlock;
   k_lists<FROM_CODES><<<(unsigned)n_sub, 256, 0, st>>>(a, b.G * kGroup, b.perm, b.lcnt, b.loff, b.lslot, sp,
-                                                       prev);
+                                                       prev, terms);
 }
 
 sofa_status launch_bf16_relist(const SearchArgs& a, const Bf16Args& b, int64_t sp, int64_t prev,
                                hipStream_t st) {
-  // straight from the stored bound codes under the tightened U, in slot order
-  launch_lists<true>(a, b, st, sp, prev);
+  // straight from the stored bound codes under the tightened U, in slot
+  // order, with the next pass's slot terms
+  launch_lists<true>(a, b, st, sp, prev, slot_terms_of(a, b, true));
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -677,7 +718,8 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   }
   k_qsort<<<nblk(B, 4), 256, 0, st>>>(b.qcount, a.best, B, a.n_leaves, b.perm);
   const int Spad = b.G * kGroup;
-  launch_lists<false>(a, b, st, 0, 0);
+  SlotTerms none{};
+  launch_lists<false>(a, b, st, 0, 0, none);
   if (b.prec == 2) {
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
     k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
@@ -692,18 +734,10 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
   return SOFA_OK;
 }
 
-// accumulation bound g = (K + K step) 2^-23 of the FP32 MFMA sums
-static float prune_gamma(const SearchArgs& a, const Bf16Args& b) {
-  const int step = b.prec == 2 ? 64 : 16;
-  return (float)(a.n_pad + step) * 0x1p-23f;
-}
-
 // the bound terms of every slot from the current U; the candidate counts
 // (when `clear_ccnt`) and the work counter cleared in the same launch
 static sofa_status launch_slotc(const SearchArgs& a, const Bf16Args& b, bool clear_ccnt, hipStream_t st) {
-  const int Spad = b.G * kGroup;  // >= B
-  k_slotc<<<nblk(Spad, 256), 256, 0, st>>>(b.qmeta, b.perm, a.B, Spad, a.U, a.lb_f, prune_gamma(a, b),
-                                           b.slotc, clear_ccnt ? b.ccnt : nullptr, b.counter);
+  k_slotc<<<nblk(b.G * kGroup, 256), 256, 0, st>>>(slot_terms_of(a, b, clear_ccnt));
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
 }
@@ -723,7 +757,7 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
 }
 
 sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
-                             int64_t stride, int64_t n_items, int skip, hipStream_t st,
+                             int64_t stride, int64_t n_items, int skip, bool terms_ready, hipStream_t st,
                              hipEvent_t* ev) {
   b.chunk_mult = mult;
   b.chunk_first = first;
@@ -742,7 +776,8 @@ sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int6
     return SOFA_OK;
   }
   // the bounds U of this pass (earlier passes tighten them), cleared counts
-  SOFA_TRY(launch_slotc(a, b, true, st));
+  // (already written when the lists were rebuilt just before)
+  if (!terms_ready) SOFA_TRY(launch_slotc(a, b, true, st));
   if ((int64_t)grid > b.n_items) grid = (unsigned)b.n_items;
   if (ev) (void)hipEventRecord(ev[0], st);
   SOFA_TRY(launch_bf16_tiles(a, b, grid, false, st));
