@@ -367,6 +367,28 @@ def test_knn_band_overflow_ranked_from_refined_rows(gpu_lib):
                 assert st["overflow_evicted"] == 1 and st["overflow_fallbacks"] == 1, (k, st)
 
 
+@pytest.mark.parametrize("n,prec", [(64, 1), (1024, 2)])
+def test_finalize_ranks_bands_over_several_batches(gpu_lib, n, prec):
+    """The finalize stages the in-band rows in LDS a batch at a time: 64
+    rows at n = 64 and 4 at n = 1024. Query 0 has 180 exact copies, so its
+    final band holds 181 rows at distance zero. That spans 3 batches at
+    n = 64 and 46 at n = 1024. Ids (ties to the lower row id) and distances
+    are the oracle's on the plain path and on the prune tier of the index's
+    copy: BF16 at n = 64, FP8 at n = 1024."""
+    N = 4000 + 3
+    X = synth.collection(N, n, "rw", seed=61 + n)
+    dup = np.sort(np.random.default_rng(2).choice(np.arange(1, N), 180, replace=False))
+    X[dup] = X[0]
+    Q = np.stack([X[0], X[11]])
+    bins = _bins(gpu_lib, X, 2000)
+    ix = gpu_lib.Index(bins, _t(X), leaf_size=256, precision=prec)
+    for prune in (0, prec):
+        for k in (10, 100):
+            ids, d = ix.knn(_t(Q), k, prune=prune)
+            ref_ids, ref_d2 = oracle.knn(X, Q, k)
+            _check_knn(ids.cpu().numpy(), d.cpu().numpy(), ref_ids, ref_d2)
+
+
 def test_knn_tiny_candidate_capacity_stays_exact(gpu_lib):
     N, n, B = 20000, 256, 24
     X = synth.collection(N, n, "mix", seed=81)
