@@ -975,7 +975,8 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
     const int64_t n_chunks = (ix->N + 255) / 256;
     const int sampling = p->sampling;
     if (sampling == 2) {
-      SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, false, st, ev ? ev + 7 : nullptr));
+      // the query side wrote the first pass's slot terms
+      SOFA_TRY(launch_bf16_pass(a, b, 1, 0, 1, n_chunks, 0, true, st, ev ? ev + 7 : nullptr));
       bf_passes = 1;
     } else {
       const bool many = k >= kManyFromK;
@@ -993,8 +994,9 @@ static sofa_status knn_impl(const sofa_index* ix, const float* d_q, int64_t B, i
         if (ps >= relist_from) SOFA_TRY(launch_bf16_relist(a, b, sp, prev, st));
         const int64_t n_sp = (n_chunks + sp - 1) / sp;
         const int64_t n_prev = prev ? (n_chunks + prev - 1) / prev : 0;
+        // slot terms already written: by the query side (first pass) or a relist
         SOFA_TRY(launch_bf16_pass(a, b, sp, 0, prev ? 0 : 1, n_sp - n_prev, prev ? (int)(prev / sp) : 0,
-                                  ps >= relist_from, st,
+                                  ps == 0 || ps >= relist_from, st,
                                   ev ? ev + 7 + 3 * ps : nullptr));
         prev = sp;
       }

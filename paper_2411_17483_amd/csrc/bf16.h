@@ -45,7 +45,10 @@ sofa_status launch_bf16_build(const float* X, int64_t N, int n_pad, int L, int64
 // fragment), cscale per 256-row chunk, per-row meta and per-leaf maxima
 sofa_status launch_fp8_build(const float* X, int64_t N, int n_pad, int L, int64_t n_leaves,
                              uint4* xf, float* cscale, float4* meta, float4* leafmeta, hipStream_t st);
-// clear_qcount false: b.qcount (B entries) is already zero
+// the query side of the prune: density sort, first lists, query rows and
+// terms, and the slot terms of the first pass from the current U (with the
+// candidate counts and work counter cleared).  clear_qcount false: b.qcount
+// (B entries) is already zero.
 sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st, bool clear_qcount = true);
 // rebuild the (query, leaf) lists from the current bounds U, keeping the slot
 // order: later passes see only the pairs that still survive.  Only the leaves
@@ -61,7 +64,8 @@ sofa_status launch_bf16_dump(const SearchArgs& a, Bf16Args b, float* d_lb, hipSt
 sofa_status launch_bf16_tiles(const SearchArgs& a, const Bf16Args& b, unsigned grid, bool dump, hipStream_t st);
 // ev (nullable): events recorded before the tile kernel, between it and the
 // candidate refinement, and after
-// terms_ready: a relist launched just before wrote this pass's slot terms
+// terms_ready: the query side (first pass) or a relist launched just before
+// wrote this pass's slot terms
 sofa_status launch_bf16_pass(const SearchArgs& a, Bf16Args b, int64_t mult, int64_t first,
                              int64_t stride, int64_t n_items, int skip, bool terms_ready, hipStream_t st,
                              hipEvent_t* ev);

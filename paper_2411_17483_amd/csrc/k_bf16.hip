@@ -480,39 +480,38 @@ __global__ __launch_bounds__(256) void k_lists(SearchArgs a, int Spad, const int
       }
 }
 
-// BF16 query rows per sorted slot (n_pad values, zero past B); a lane's
-// fragment of the 32x32x16 B operand is 16 contiguous bytes of one row
-__global__ void k_qrows_bf16(const float* __restrict__ Qp, int B, int n_pad, int Spad,
-                             const int32_t* __restrict__ perm, uint4* __restrict__ qb) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int per = n_pad / 8;
-  if (i >= (int64_t)Spad * per) return;
-  const int s = (int)(i / per), k0 = (int)(i % per) * 8;
-  uint32_t w[4] = {0, 0, 0, 0};
-  if (s < B) {
-    const float* qr = Qp + (int64_t)perm[s] * n_pad;
-    float4 a = *reinterpret_cast<const float4*>(qr + k0);
-    float4 b = *reinterpret_cast<const float4*>(qr + k0 + 4);
-    w[0] = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
-    w[1] = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
-    w[2] = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
-    w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
-  }
-  qb[i] = make_uint4(w[0], w[1], w[2], w[3]);
-}
-
+// BF16 query side, a wave per sorted slot: the slot's BF16 row (n_pad values,
+// zero past B; a lane's fragment of the 32x32x16 B operand is 16 contiguous
+// bytes of it), its bound terms and, U being final once the seed has run,
+// its slot terms for the first pass
 __global__ __launch_bounds__(256) void k_qmeta_bf16(const float* __restrict__ Qp, int B, int n_pad,
                                                     const int32_t* __restrict__ perm, int Spad,
-                                                    float4* __restrict__ qmeta) {
+                                                    float4* __restrict__ qmeta, uint4* __restrict__ qb,
+                                                    SlotTerms terms) {
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= Spad) return;
+  const float* qr = s < B ? Qp + (int64_t)perm[s] * n_pad : nullptr;
+  const int per = n_pad / 8;
+  for (int c = lane; c < per; c += 64) {
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (qr) {
+      const float4 a = *reinterpret_cast<const float4*>(qr + 8 * c);
+      const float4 b = *reinterpret_cast<const float4*>(qr + 8 * c + 4);
+      w[0] = bf16_bits(a.x) | (bf16_bits(a.y) << 16);
+      w[1] = bf16_bits(a.z) | (bf16_bits(a.w) << 16);
+      w[2] = bf16_bits(b.x) | (bf16_bits(b.y) << 16);
+      w[3] = bf16_bits(b.z) | (bf16_bits(b.w) << 16);
+    }
+    qb[(int64_t)s * per + c] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
   float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (s < B) norms_of(Qp + (int64_t)perm[s] * n_pad, n_pad, lane, m);
+  if (qr) norms_of(qr, n_pad, lane, m);
   // m = (|q|^2 down, r_q up, |qh| up); the bound also needs |q| (up)
   if (lane == 0) {
     m.w = __double2float_ru(sqrt((double)m.x) * (1.0 + 1e-7) + 1e-30);
     qmeta[s] = m;
+    slot_terms(terms, s);  // reads the qmeta just written (same thread)
   }
 }
 
@@ -552,7 +551,7 @@ __global__ void k_qrows_fp8(const float* __restrict__ Qp, int B, int n_pad, int 
 __global__ __launch_bounds__(256) void k_qmeta_fp8(const float* __restrict__ Qp, int B, int n_pad,
                                                    const int32_t* __restrict__ perm, int Spad,
                                                    const float* __restrict__ qscale,
-                                                   float4* __restrict__ qmeta) {
+                                                   float4* __restrict__ qmeta, SlotTerms terms) {
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= Spad) return;
@@ -561,6 +560,7 @@ __global__ __launch_bounds__(256) void k_qmeta_fp8(const float* __restrict__ Qp,
   if (lane == 0) {
     m.w = __double2float_ru(sqrt((double)m.x) * (1.0 + 1e-7) + 1e-30);
     qmeta[s] = m;
+    slot_terms(terms, s);  // the first pass's slot terms (see k_qmeta_bf16)
   }
 }
 
@@ -724,11 +724,11 @@ sofa_status launch_bf16_queries(const SearchArgs& a, Bf16Args& b, hipStream_t st
     k_qscale_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale);
     k_qrows_fp8<<<nblk((int64_t)Spad * (a.n_pad / 16), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
                                                                           b.qscale, b.qb);
-    k_qmeta_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale, b.qmeta);
+    k_qmeta_fp8<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qscale, b.qmeta,
+                                               slot_terms_of(a, b, true));
   } else {
-    k_qrows_bf16<<<nblk((int64_t)Spad * (a.n_pad / 8), 256), 256, 0, st>>>(a.Qp, B, a.n_pad, Spad, b.perm,
-                                                                          b.qb);
-    k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta);
+    k_qmeta_bf16<<<nblk(Spad, 4), 256, 0, st>>>(a.Qp, B, a.n_pad, b.perm, Spad, b.qmeta, b.qb,
+                                                slot_terms_of(a, b, true));
   }
   SOFA_HIP(hipGetLastError());
   return SOFA_OK;
